@@ -1,0 +1,238 @@
+/*
+ * scarff.h - C ABI of the MI355X (gfx950) Cartesian form-factor engine.
+ *
+ * The engine evaluates the transition form factor of a molecule in a
+ * contracted Cartesian Gaussian basis,
+ *
+ *     f_s(q) = s_f * sum_{mu,nu} T^s_{mu nu} <phi_mu| e^{i q.r} |phi_nu>,
+ *
+ * for a batch of transitions s (paper Sec. 2.2, the form-factor definition
+ * with AO-basis transition density matrices; Sec. 4, eq. CartesianMethod
+ * for the separable closed form that is evaluated).  The spin factor s_f is
+ * 1 by default; the paper's sqrt(2) for singlet spin degeneracy (Sec. 2.2)
+ * is set with scff_set_options.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units: bohr for positions, bohr^-2 for exponents, atomic units for q.
+ *  - Shells: l = 0, 1, 2 (s, p, Cartesian d).  Component order inside a
+ *    shell is s; x, y, z; xx, xy, xz, yy, yz, zz.  AO index mu runs over
+ *    shells in the order given, components fastest.  T is given in that
+ *    order.
+ *  - Ownership: the caller owns every buffer.  Loads copy their inputs; no
+ *    caller pointer is retained after a call returns.
+ *  - Errors: every int-returning call returns SCFF_OK (0) or a negative
+ *    code; scff_last_error() then describes the failure.  A failed call
+ *    leaves the context as it was and writes no output.
+ *  - Threading: a context is not re-entrant; use one context per thread or
+ *    serialise calls.  The server (scff_server_*) is thread-safe.
+ *  - Device: one context drives one HIP device.  Device output pointers
+ *    must be device memory of that device (e.g. from torch.empty(...,
+ *    device='cuda')); the call is then asynchronous on the given stream.
+ */
+#ifndef SCARFF_H
+#define SCARFF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define SCFF_OK          0
+#define SCFF_EINVAL     -1   /* malformed argument (shape, range, NULL)         */
+#define SCFF_ENOMEM     -2   /* allocation failed or HBM budget exceeded       */
+#define SCFF_EDEVICE    -3   /* no usable HIP device / a HIP call failed        */
+#define SCFF_ESTATE     -4   /* call out of order (e.g. eval before loads)      */
+#define SCFF_EBUSY      -5   /* server queue full / ticket not finished         */
+#define SCFF_ECANCELLED -6   /* server request cancelled                        */
+
+/* ---- precision of the pair contraction (paper Sec. 5.3 step "final grid
+ *      contraction"; precision is this engine's choice) -------------------- */
+#define SCFF_FP32    0   /* FP32 generator + FP32 MFMA contraction              */
+#define SCFF_BF16X3  1   /* FP32 generator + split-BF16 (hi*hi+hi*lo+lo*hi) MFMA */
+
+typedef struct scff_ctx scff_ctx;
+
+/* q_a = linspace(qmin[a], qmax[a], n[a]) on each axis a (endpoints included);
+ * n[a] == 1 gives the single value qmin[a].  Output element order is
+ * [state][ix][iy][iz] with iz fastest. */
+typedef struct {
+    int n[3];
+    double qmin[3];
+    double qmax[3];
+} scff_grid;
+
+typedef struct {
+    int nbf;                          /* Cartesian basis functions            */
+    int n_shells;
+    int n_states;
+    long long shell_pairs_total;      /* unique shell pairs A <= B            */
+    long long pairs_total;            /* unique component pairs mu <= nu      */
+    long long pairs_kept;             /* K: component pairs after screening   */
+    long long prim_pairs_total;       /* sum over component pairs of prim pairs */
+    long long prim_comp_pairs_kept;   /* R: (component pair, prim pair) terms kept */
+    size_t device_bytes;              /* device memory held by the context    */
+} scff_info;
+
+/* Version string of the library, static storage. */
+const char* scff_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next call on this thread. */
+const char* scff_last_error(void);
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
+ * device memory the context may hold (0 = no cap); exceeding it fails with
+ * SCFF_ENOMEM.  Returns SCFF_EDEVICE if no HIP device is usable. */
+int scff_create(int device, size_t hbm_budget_bytes, scff_ctx** out);
+
+/* Release every resource of the context (NULL is ignored). */
+void scff_destroy(scff_ctx* ctx);
+
+/*
+ * Load geometry and basis (paper Sec. 5.1 "hierarchical data structure";
+ * App. A for the primitive form and its normalisation).
+ *   xyz_bohr     [n_atoms*3]     atom positions
+ *   shell_atom   [n_shells]      atom index of each shell
+ *   shell_l      [n_shells]      0, 1 or 2
+ *   shell_nprim  [n_shells]      primitives per shell (1..16)
+ *   exps, coefs  [sum nprim]     exponents alpha_k > 0 (bohr^-2) and
+ *                                contraction coefficients d_k, concatenated
+ *                                in shell order
+ *   normalise    1: every primitive is scaled to unit self-overlap and every
+ *                contracted Cartesian component to unit norm; 0: primitives
+ *                are unit-normalised, the d_k are used as given.
+ *   nbf_out      (may be NULL) number of Cartesian basis functions.
+ * Invalidates previously loaded transitions if nbf changes.
+ */
+int scff_load_molecule(scff_ctx* ctx, int n_atoms, const double* xyz_bohr, int n_shells,
+                       const int* shell_atom, const int* shell_l, const int* shell_nprim,
+                       const double* exps, const double* coefs, int normalise, int* nbf_out);
+
+/*
+ * Load the AO-basis transition density matrices (paper Sec. 2.2, T_pq).
+ *   T  [n_states][nbf][nbf] row-major, real.  1 <= n_states <= 32.
+ * Only (T + T^T)/2 contributes (Omega_{mu nu} = Omega_{nu mu}); the engine
+ * packs T_{mu nu} + T_{nu mu} per unique pair.
+ */
+int scff_load_transitions(scff_ctx* ctx, int n_states, const double* T);
+
+/*
+ * Options.  screen_eps >= 0: pair screening threshold (paper Sec. 5.3,
+ * thresholding of Cartesian pair terms).  A (component pair, primitive pair)
+ * term is dropped only if, for every transition, the dropped terms' summed
+ * q-independent magnitude bounds stay below screen_eps times the sum of all
+ * term bounds of that transition.  0 disables screening.
+ * spin_factor multiplies every result (default 1.0; sqrt(2) gives the
+ * paper's singlet normalisation).
+ */
+int scff_set_options(scff_ctx* ctx, double screen_eps, double spin_factor);
+
+/*
+ * Evaluate on a Cartesian q-grid (paper Sec. 5.3, full-grid materialisation
+ * of eq. CartesianMethod).
+ *   precision      SCFF_FP32 or SCFF_BF16X3
+ *   f              complex64 interleaved [n_states][nx][ny][nz][2], or NULL
+ *   f2             |f|^2 float [n_states][nx][ny][nz], or NULL
+ *   out_on_device  1: f/f2 are device pointers, the call is asynchronous on
+ *                  hip_stream (NULL = default stream); 0: host pointers, the
+ *                  call returns when they are filled.
+ *   hip_stream     a hipStream_t of the context's device, or NULL.
+ * Requires a loaded molecule and transitions (else SCFF_ESTATE).
+ * Grid sizes: 1 <= n[a] <= 4096.
+ */
+int scff_eval_grid(scff_ctx* ctx, const scff_grid* grid, int precision, float* f, float* f2,
+                   int out_on_device, void* hip_stream);
+
+/*
+ * Evaluate at arbitrary points q [n_q][3] (host array, a.u.).  Same outputs
+ * as scff_eval_grid with the grid axes replaced by the point index:
+ * f [n_states][n_q][2], f2 [n_states][n_q].  1 <= n_q <= 2^24.
+ */
+int scff_eval_points(scff_ctx* ctx, int n_q, const double* q, int precision, float* f,
+                     float* f2, int out_on_device, void* hip_stream);
+
+/* Sizes and screening statistics of the loaded problem. */
+int scff_query(scff_ctx* ctx, scff_info* info);
+
+/*
+ * One-dimensional V-tensors of the loaded molecule on a grid (paper Sec. 5.3,
+ * the option to compute only the 1D V-tensors, eq. CartesianVector).  For
+ * every kept (component pair, primitive pair) term t and axis a the engine
+ * holds V_t^a(q_a) on the grid axis; f_s(q) = sum_t Tp_s(t) V_t^x V_t^y V_t^z.
+ * Writes, as host arrays:
+ *   n_terms_out            R (number of kept terms)
+ *   vx, vy, vz             complex64 [R][n_a][2] (NULL to skip an axis)
+ *   tp                     float [n_states][R]: the packed, normalised
+ *                          transition weights (NULL to skip)
+ * Call first with all array pointers NULL to learn R.
+ */
+int scff_export_vtensors(scff_ctx* ctx, const scff_grid* grid, long long* n_terms_out, float* vx,
+                         float* vy, float* vz, float* tp);
+
+/* ---- serving: continuous batching of independent requests -------------- */
+typedef struct scff_server scff_server;
+
+typedef struct {
+    /* molecule (as scff_load_molecule) */
+    int n_atoms;
+    const double* xyz_bohr;
+    int n_shells;
+    const int* shell_atom;
+    const int* shell_l;
+    const int* shell_nprim;
+    const double* exps;
+    const double* coefs;
+    int normalise;
+    /* transitions (as scff_load_transitions) */
+    int n_states;
+    const double* T;
+    /* evaluation */
+    scff_grid grid;
+    int precision;
+    double screen_eps;
+    double spin_factor;
+    /* host outputs, owned by the caller, written when the request completes;
+     * must stay valid until scff_server_wait reports completion */
+    float* f;    /* [n_states][nx][ny][nz][2] or NULL */
+    float* f2;   /* [n_states][nx][ny][nz] or NULL     */
+} scff_request;
+
+typedef struct {
+    long long submitted, completed, failed, cancelled;
+    long long queued, inflight;
+    size_t admitted_bytes, budget_bytes, peak_admitted_bytes;
+} scff_server_stats;
+
+/* Create a server on `device`.  Requests are admitted while the device
+ * bytes of all in-flight requests fit `hbm_budget_bytes` (0 = 64 GiB) and at
+ * most `max_inflight` requests run at once (1..64).  Requests that do not
+ * fit wait in FIFO order.  A request larger than the whole budget fails
+ * with SCFF_ENOMEM. */
+int scff_server_create(int device, size_t hbm_budget_bytes, int max_inflight,
+                       scff_server** out);
+
+/* Copy the request's inputs and enqueue it; returns a ticket (> 0). */
+int scff_server_submit(scff_server* srv, const scff_request* req, unsigned long long* ticket);
+
+/* Wait up to timeout_ns (< 0: forever) for a ticket.  Returns SCFF_OK when
+ * the request finished (its status in *status: SCFF_OK or the error code),
+ * SCFF_EBUSY on timeout.  latency_ns (may be NULL) receives submit-to-done
+ * time.  A ticket can be waited for successfully once. */
+int scff_server_wait(scff_server* srv, unsigned long long ticket, long long timeout_ns,
+                     int* status, long long* latency_ns);
+
+/* Cancel a queued (not yet admitted) request. SCFF_EBUSY if already running. */
+int scff_server_cancel(scff_server* srv, unsigned long long ticket);
+
+int scff_server_stats_get(scff_server* srv, scff_server_stats* out);
+
+/* Drain nothing: pending requests are cancelled, running ones finish first. */
+void scff_server_destroy(scff_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCARFF_H */

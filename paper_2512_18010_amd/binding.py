@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libscarff.so (the C ABI in include/scarff.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  The raw entry points are exposed under their C names
+(``scff_create``, ``scff_eval_grid``, ...); ``Context`` wraps them for
+numpy / torch callers.  PyTorch is used only to allocate device memory and
+to name the current HIP stream.
+
+If the library is missing this module raises at import: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscarff.so")
+
+SCFF_OK, SCFF_EINVAL, SCFF_ENOMEM, SCFF_EDEVICE, SCFF_ESTATE, SCFF_EBUSY, SCFF_ECANCELLED = 0, -1, -2, -3, -4, -5, -6
+SCFF_FP32, SCFF_BF16X3 = 0, 1
+PRECISIONS = {"fp32": SCFF_FP32, "bf16x3": SCFF_BF16X3}
+ERROR_NAMES = {0: "SCFF_OK", -1: "SCFF_EINVAL", -2: "SCFF_ENOMEM", -3: "SCFF_EDEVICE",
+               -4: "SCFF_ESTATE", -5: "SCFF_EBUSY", -6: "SCFF_ECANCELLED"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2512_18010_amd.build` "
+                      "(the engine has no non-HIP fallback)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+P = ctypes.POINTER
+c_int, c_double, c_float, c_size_t, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_float, ctypes.c_size_t, ctypes.c_void_p
+c_longlong, c_ulonglong = ctypes.c_longlong, ctypes.c_ulonglong
+
+
+class scff_grid(ctypes.Structure):
+    _fields_ = [("n", c_int * 3), ("qmin", c_double * 3), ("qmax", c_double * 3)]
+
+
+class scff_info(ctypes.Structure):
+    _fields_ = [("nbf", c_int), ("n_shells", c_int), ("n_states", c_int),
+                ("shell_pairs_total", c_longlong), ("pairs_total", c_longlong),
+                ("pairs_kept", c_longlong), ("prim_pairs_total", c_longlong),
+                ("prim_comp_pairs_kept", c_longlong), ("device_bytes", c_size_t)]
+
+
+class scff_request(ctypes.Structure):
+    _fields_ = [("n_atoms", c_int), ("xyz_bohr", P(c_double)), ("n_shells", c_int),
+                ("shell_atom", P(c_int)), ("shell_l", P(c_int)), ("shell_nprim", P(c_int)),
+                ("exps", P(c_double)), ("coefs", P(c_double)), ("normalise", c_int),
+                ("n_states", c_int), ("T", P(c_double)), ("grid", scff_grid),
+                ("precision", c_int), ("screen_eps", c_double), ("spin_factor", c_double),
+                ("f", P(c_float)), ("f2", P(c_float))]
+
+
+class scff_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", c_longlong), ("completed", c_longlong), ("failed", c_longlong),
+                ("cancelled", c_longlong), ("queued", c_longlong), ("inflight", c_longlong),
+                ("admitted_bytes", c_size_t), ("budget_bytes", c_size_t),
+                ("peak_admitted_bytes", c_size_t)]
+
+
+def _fn(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+scff_version = _fn("scff_version", ctypes.c_char_p, [])
+scff_last_error = _fn("scff_last_error", ctypes.c_char_p, [])
+scff_create = _fn("scff_create", c_int, [c_int, c_size_t, P(c_void_p)])
+scff_destroy = _fn("scff_destroy", None, [c_void_p])
+scff_load_molecule = _fn("scff_load_molecule", c_int,
+                         [c_void_p, c_int, P(c_double), c_int, P(c_int), P(c_int), P(c_int),
+                          P(c_double), P(c_double), c_int, P(c_int)])
+scff_load_transitions = _fn("scff_load_transitions", c_int, [c_void_p, c_int, P(c_double)])
+scff_set_options = _fn("scff_set_options", c_int, [c_void_p, c_double, c_double])
+scff_eval_grid = _fn("scff_eval_grid", c_int,
+                     [c_void_p, P(scff_grid), c_int, c_void_p, c_void_p, c_int, c_void_p])
+scff_eval_points = _fn("scff_eval_points", c_int,
+                       [c_void_p, c_int, P(c_double), c_int, c_void_p, c_void_p, c_int, c_void_p])
+scff_query = _fn("scff_query", c_int, [c_void_p, P(scff_info)])
+scff_export_vtensors = _fn("scff_export_vtensors", c_int,
+                           [c_void_p, P(scff_grid), P(c_longlong), c_void_p, c_void_p, c_void_p,
+                            c_void_p])
+scff_server_create = _fn("scff_server_create", c_int, [c_int, c_size_t, c_int, P(c_void_p)])
+scff_server_submit = _fn("scff_server_submit", c_int, [c_void_p, P(scff_request), P(c_ulonglong)])
+scff_server_wait = _fn("scff_server_wait", c_int,
+                       [c_void_p, c_ulonglong, c_longlong, P(c_int), P(c_longlong)])
+scff_server_cancel = _fn("scff_server_cancel", c_int, [c_void_p, c_ulonglong])
+scff_server_stats_get = _fn("scff_server_stats_get", c_int, [c_void_p, P(scff_server_stats)])
+scff_server_destroy = _fn("scff_server_destroy", None, [c_void_p])
+
+
+class ScffError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc != SCFF_OK:
+        raise ScffError(rc, scff_last_error().decode())
+    return rc
+
+
+def _d(a):
+    return a.ctypes.data_as(P(c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(P(c_int))
+
+
+def make_grid(n, qmin, qmax) -> scff_grid:
+    g = scff_grid()
+    for a in range(3):
+        g.n[a] = int(n[a])
+        g.qmin[a] = float(qmin[a])
+        g.qmax[a] = float(qmax[a])
+    return g
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One engine context on one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = c_void_p()
+        check(scff_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.nbf = 0
+        self.n_states = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            scff_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- loads
+    def load_molecule(self, mol, normalise: bool = True) -> int:
+        self._mol_keep = [np.ascontiguousarray(mol.xyz, np.float64),
+                          np.ascontiguousarray(mol.shell_atom, np.int32),
+                          np.ascontiguousarray(mol.shell_l, np.int32),
+                          np.ascontiguousarray(mol.shell_nprim, np.int32),
+                          np.ascontiguousarray(mol.exps, np.float64),
+                          np.ascontiguousarray(mol.coefs, np.float64)]
+        xyz, sa, sl, sn, ex, co = self._mol_keep
+        nbf = c_int()
+        check(scff_load_molecule(self._h, xyz.shape[0], _d(xyz), sl.shape[0], _i(sa), _i(sl), _i(sn),
+                                 _d(ex), _d(co), int(bool(normalise)), ctypes.byref(nbf)))
+        self.nbf = nbf.value
+        return self.nbf
+
+    def load_transitions(self, T):
+        T = np.ascontiguousarray(T, np.float64)
+        if T.ndim == 2:
+            T = T[None]
+        check(scff_load_transitions(self._h, T.shape[0], _d(T)))
+        self.n_states = T.shape[0]
+
+    def set_options(self, screen_eps: float = 0.0, spin_factor: float = 1.0):
+        check(scff_set_options(self._h, float(screen_eps), float(spin_factor)))
+
+    def query(self) -> dict:
+        info = scff_info()
+        check(scff_query(self._h, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in scff_info._fields_}
+
+    # ---- evaluation
+    def eval_grid_host(self, grid, precision="fp32", want_f=True, want_f2=True):
+        """Host outputs: (f complex64 [s,nx,ny,nz] or None, f2 float32 [s,nx,ny,nz] or None)."""
+        n = tuple(grid.n)
+        shape = (self.n_states,) + n
+        f = np.empty(shape + (2,), np.float32) if want_f else None
+        f2 = np.empty(shape, np.float32) if want_f2 else None
+        g = make_grid(grid.n, grid.qmin, grid.qmax)
+        check(scff_eval_grid(self._h, ctypes.byref(g), PRECISIONS[precision],
+                             f.ctypes.data if f is not None else None,
+                             f2.ctypes.data if f2 is not None else None, 0, None))
+        return (f.view(np.complex64)[..., 0] if f is not None else None), f2
+
+    def eval_grid_device(self, grid, f=None, f2=None, precision="fp32", stream=None):
+        """Device outputs into torch tensors f ([s,nx,ny,nz,2] float32) / f2 ([s,nx,ny,nz] float32)."""
+        g = make_grid(grid.n, grid.qmin, grid.qmax)
+        check(scff_eval_grid(self._h, ctypes.byref(g), PRECISIONS[precision],
+                             f.data_ptr() if f is not None else None,
+                             f2.data_ptr() if f2 is not None else None, 1, _stream_ptr(stream)))
+        return f, f2
+
+    def eval_points(self, q, precision="fp32"):
+        q = np.ascontiguousarray(np.atleast_2d(q), np.float64)
+        nq = q.shape[0]
+        f = np.empty((self.n_states, nq, 2), np.float32)
+        f2 = np.empty((self.n_states, nq), np.float32)
+        check(scff_eval_points(self._h, nq, _d(q), PRECISIONS[precision], f.ctypes.data,
+                               f2.ctypes.data, 0, None))
+        return f.view(np.complex64)[..., 0], f2
+
+    def export_vtensors(self, grid):
+        g = make_grid(grid.n, grid.qmin, grid.qmax)
+        nt = c_longlong()
+        check(scff_export_vtensors(self._h, ctypes.byref(g), ctypes.byref(nt), None, None, None, None))
+        R = nt.value
+        vs = [np.empty((R, grid.n[a], 2), np.float32) for a in range(3)]
+        tp = np.empty((self.n_states, R), np.float32)
+        check(scff_export_vtensors(self._h, ctypes.byref(g), ctypes.byref(nt), vs[0].ctypes.data,
+                                   vs[1].ctypes.data, vs[2].ctypes.data, tp.ctypes.data))
+        return [v.view(np.complex64)[..., 0] for v in vs], tp

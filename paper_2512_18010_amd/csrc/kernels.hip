@@ -1,0 +1,409 @@
+// Device kernels of the Cartesian form-factor engine (gfx950 / CDNA4).
+//
+// Hot path (paper Sec. 4 eq. CartesianMethod, Sec. 5.3):
+//
+//   f_s(qx,qy,qz) = sum_k Tp(s,k) G(k,q),
+//   G(k,q)        = sum_{t in terms(k)} Vx_t(qx) Vy_t(qy) Vz_t(qz),
+//
+// where k runs over unique component pairs (mu <= nu), t over their kept
+// primitive-pair terms, and V_t^a are the 1D V-tensors of eq.
+// CartesianVector in monomial form (eq. Ccoefficients).
+//
+//  * vtable_kernel: the 1D tables V[row][n] for every grid value of each
+//    axis (O(rows x N) work, a precompute next to the O(R x N^3) bulk).  They
+//    are evaluated in FP64 (phase q*P with range reduction, Gaussian,
+//    polynomial) and rounded once to FP32: the polynomial can cancel, and
+//    FP32 evaluation would leave errors proportional to its bound rather
+//    than to its value.
+//  * grid_kernel: one workgroup per q-tile of (WAVES x 8) lines (qx,qy) x
+//    (4*QZL) values of qz.  Per chunk of 8 component pairs the tile's
+//    W = Vx*Vy (per line) and Vz (per qz) slices are staged in LDS; every
+//    lane then forms G for 2 lines x QZL qz values of one component pair on
+//    the VALU and feeds it, still in registers, as the B operand of
+//    v_mfma_f32_16x16x4_f32 (A = Tp, 16 states x 4 pairs).  Accumulation is
+//    blocked: MFMA sums run over kFoldChunks chunks and are then added into
+//    a second set of FP32 accumulators, which bounds the rounding error of
+//    the long pair sum.
+//  * points_kernel: the same sum at arbitrary points (VALU only), V
+//    evaluated on the fly.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdlib>
+
+#include "engine.h"
+
+namespace scff {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kFoldChunks = 32;   // 256 component pairs per MFMA accumulation block
+
+// ---------------------------------------------------------------- 1D tables
+
+__device__ __forceinline__ float2 eval_row(const VRowDev& r, double q) {
+    // phase = q * P, reduced to revolutions in [-1/2, 1/2]
+    const double rev = q * r.P * 0.15915494309189535;  // 1/(2 pi)
+    const double red = rev - rint(rev);
+    double s, c;
+    sincospi(2.0 * red, &s, &c);
+    const double q2 = q * q;
+    const double g = exp(-q2 * r.inv4p);
+    // sum_u e_u (i q)^u = (e0 - e2 q^2 + e4 q^4) + i q (e1 - e3 q^2)
+    const double pr = fma(fma(r.e[4], q2, -r.e[2]), q2, r.e[0]);
+    const double pi = q * fma(-r.e[3], q2, r.e[1]);
+    return make_float2((float)(g * (c * pr - s * pi)), (float)(g * (c * pi + s * pr)));
+}
+
+__global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int vstride,
+                              int3 n, double3 qmin, double3 dq, float2* __restrict__ V) {
+    const long long tot = (long long)nrows * vstride;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(i / vstride);
+        const int j = (int)(i - (long long)r * vstride);
+        const VRowDev row = rows[r];
+        const int ax = row.axis;
+        const int na = ax == 0 ? n.x : (ax == 1 ? n.y : n.z);
+        if (j >= na) {
+            V[i] = make_float2(0.f, 0.f);
+            continue;
+        }
+        const double q0 = ax == 0 ? qmin.x : (ax == 1 ? qmin.y : qmin.z);
+        const double d = ax == 0 ? dq.x : (ax == 1 ? dq.y : dq.z);
+        V[i] = eval_row(row, q0 + d * (double)j);
+    }
+}
+
+// ---------------------------------------------------------------- grid kernel
+//
+// Workgroup = 4 waves, tile = 4 qx x 8 qy lines x TZ qz (TZ = 4*QZL).
+// Per chunk of 8 component pairs with npp terms each (npp <= 9), for every
+// term t (index ptl = pair*npp + term):
+//   raw slices  Vx[t][4], Vy[t][8], Vz[t][TZ]   global -> registers -> LDS
+//   W[t][line] = Vx * Vy                        cooperative, in LDS
+// plus the chunk's packed weights Tp[8][16*SB] (LDS).  Thread tid always
+// loads slice `part = tid & 15` of terms ptl = tid/16 + 16j, so no per-item
+// index arithmetic is needed.  The loads of chunk c+1 are issued before the
+// W phase of chunk c and complete under its arithmetic.
+// Lane (kk, ln): pair kk of the current MFMA k-step, 2 lines x QZL qz.
+
+constexpr int kTiles = 4;      // chunks (32 pairs) per FP64 fold of the MFMA sums
+constexpr int kWStride = 34;   // float2 per term row of W (32 lines + pad)
+constexpr int kNPT = kChunk * kMaxTermsPerPair;   // 72 terms per chunk at most
+
+template <int SB, int QZL, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
+    const float2* __restrict__ V, int vstride, const int4* __restrict__ terms,
+    const int* __restrict__ chunk_off, const int* __restrict__ chunk_npp, int n_chunks,
+    const float* __restrict__ Tp, int3 n, int3 ntiles, int n_states, float2* __restrict__ f,
+    float* __restrict__ f2) {
+    constexpr int TZ = 4 * QZL;
+    constexpr int ZSTRIDE = TZ + 2;    // float2 per term row of Z
+    constexpr int ZPARTS = TZ / 2;     // float4 slices of a Z row
+    constexpr int SLOTS = 2 * QZL;     // q values per lane
+    constexpr int SW = 16 * SB;        // padded state count
+    constexpr int NJ = (kNPT + 15) / 16;       // terms per slice-thread
+    constexpr int TPF4 = kChunk * SW / 4;      // float4 of Tp per chunk
+    static_assert(2 + 4 + ZPARTS <= 16, "slices per term");
+
+    __shared__ __align__(16) float2 Xr[kNPT * 4];
+    __shared__ __align__(16) float2 Yr[kNPT * 8];
+    __shared__ __align__(16) float2 Zr[kNPT * ZSTRIDE];
+    __shared__ __align__(16) float2 Wl[kNPT * kWStride];
+    __shared__ __align__(16) float Tpl[kChunk * SW];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int kk = lane >> 4;          // pair within an MFMA k-step
+    const int ln = lane & 15;          // MFMA column (q) / A-row (state) index
+    const int lpair = ln >> 2;         // lines 2*lpair, 2*lpair+1 of the wave
+    const int zgrp = ln & 3;           // qz values zgrp*QZL .. zgrp*QZL+QZL-1
+
+    int b = blockIdx.x;
+    const int tz = b % ntiles.z;
+    b /= ntiles.z;
+    const int ty = b % ntiles.y;
+    const int tx = b / ntiles.y;
+    const int qx0 = tx * 4, qy0 = ty * 8, qz0 = tz * TZ;
+
+    // ---- this thread's slice: axis, offset in the table row, LDS row layout
+    const int part = tid & 15;
+    const int pt0 = tid >> 4;
+    int axis, qoff, lds_stride, lds_off;   // LDS in float4 units
+    float4* lds_base;
+    if (part < 2) {
+        axis = 0; qoff = qx0 + 2 * part; lds_base = reinterpret_cast<float4*>(Xr); lds_stride = 2; lds_off = part;
+    } else if (part < 6) {
+        axis = 1; qoff = qy0 + 2 * (part - 2); lds_base = reinterpret_cast<float4*>(Yr); lds_stride = 4; lds_off = part - 2;
+    } else {
+        const int zp = min(part - 6, ZPARTS - 1);   // idle slices re-read the last Z slice
+        axis = 2; qoff = qz0 + 2 * zp; lds_base = reinterpret_cast<float4*>(Zr); lds_stride = ZSTRIDE / 2; lds_off = zp;
+    }
+    const bool slice_active = part < 6 + ZPARTS;
+
+    float4 pf[NJ];
+    float4 pf_tp;
+    int npp_next = 0;
+
+    // Branch-free: every lane issues all its loads (clamped to valid
+    // addresses) so they are in flight together; only the LDS stores are
+    // masked.  Row ids are loaded first, then all slice loads.
+    auto load_chunk = [&](int c) {
+        const int npp = chunk_npp[c];
+        const int nptl = kChunk * npp;
+        const int* tc = reinterpret_cast<const int*>(terms + chunk_off[c]);
+        int row[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) row[j] = tc[4 * min(pt0 + 16 * j, nptl - 1) + axis];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            pf[j] = *reinterpret_cast<const float4*>(V + (size_t)row[j] * vstride + qoff);
+        pf_tp = reinterpret_cast<const float4*>(Tp + (size_t)c * kChunk * SW)[tid % TPF4];
+        npp_next = npp;
+    };
+    auto store_chunk = [&]() {
+        const int nptl = kChunk * npp_next;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int ptl = pt0 + 16 * j;
+            if (slice_active && ptl < nptl) lds_base[ptl * lds_stride + lds_off] = pf[j];
+        }
+        if (tid < TPF4) reinterpret_cast<float4*>(Tpl)[tid] = pf_tp;
+    };
+
+    floatx4 acc_r[SB][SLOTS], acc_i[SB][SLOTS];
+    double tot_r[SB][SLOTS][4], tot_i[SB][SLOTS][4];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            acc_r[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+            acc_i[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) tot_r[sb][s][i] = tot_i[sb][s][i] = 0.0;
+        }
+
+    if (n_chunks > 0) load_chunk(0);
+    for (int c = 0; c < n_chunks; ++c) {
+        const int npp = npp_next;
+        __syncthreads();                       // previous chunk done with LDS
+        store_chunk();
+        __syncthreads();
+        if (c + 1 < n_chunks) load_chunk(c + 1);
+        // W = Vx * Vy: item = (term, qx) -> 8 lines
+        for (int i = tid; i < kChunk * npp * 4; i += 256) {
+            const int ptl = i >> 2, xq = i & 3;
+            const float2 vx = Xr[ptl * 4 + xq];
+            const float4* yr = reinterpret_cast<const float4*>(Yr + ptl * 8);
+            float4* wd = reinterpret_cast<float4*>(Wl + ptl * kWStride + xq * 8);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const float4 y = yr[h];
+                wd[h] = make_float4(vx.x * y.x - vx.y * y.y, vx.x * y.y + vx.y * y.x,
+                                    vx.x * y.z - vx.y * y.w, vx.x * y.w + vx.y * y.z);
+            }
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int step = 0; step < kChunk / 4; ++step) {
+            const int pair = step * 4 + kk;
+            float a_op[SB];
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb) a_op[sb] = Tpl[pair * SW + sb * 16 + ln];
+            float gr[SLOTS], gi[SLOTS];
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) gr[s] = gi[s] = 0.f;
+            const float2* wp = Wl + (pair * npp) * kWStride + wave * 8 + 2 * lpair;
+            const float2* zp = Zr + (pair * npp) * ZSTRIDE + zgrp * QZL;
+            for (int t = 0; t < npp; ++t) {
+                const float4 w = *reinterpret_cast<const float4*>(wp + t * kWStride);
+                float2 z[QZL];
+#pragma unroll
+                for (int j = 0; j < QZL; j += 2) {
+                    const float4 zz = *reinterpret_cast<const float4*>(zp + t * ZSTRIDE + j);
+                    z[j] = make_float2(zz.x, zz.y);
+                    z[j + 1] = make_float2(zz.z, zz.w);
+                }
+#pragma unroll
+                for (int j = 0; j < QZL; ++j) {
+                    gr[j] = fmaf(w.x, z[j].x, gr[j]);
+                    gr[j] = fmaf(-w.y, z[j].y, gr[j]);
+                    gi[j] = fmaf(w.x, z[j].y, gi[j]);
+                    gi[j] = fmaf(w.y, z[j].x, gi[j]);
+                    gr[QZL + j] = fmaf(w.z, z[j].x, gr[QZL + j]);
+                    gr[QZL + j] = fmaf(-w.w, z[j].y, gr[QZL + j]);
+                    gi[QZL + j] = fmaf(w.z, z[j].y, gi[QZL + j]);
+                    gi[QZL + j] = fmaf(w.w, z[j].x, gi[QZL + j]);
+                }
+            }
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+                    acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_op[sb], gr[s], acc_r[sb][s], 0, 0, 0);
+                    acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_op[sb], gi[s], acc_i[sb][s], 0, 0, 0);
+                }
+        }
+        if ((c + 1) % kTiles == 0 || c + 1 == n_chunks) {
+            // exact fold of the short FP32 MFMA block into FP64 totals
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        tot_r[sb][s][i] += (double)acc_r[sb][s][i];
+                        tot_i[sb][s][i] += (double)acc_i[sb][s][i];
+                    }
+                    acc_r[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    acc_i[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+    }
+
+    // epilogue: lane holds states sb*16 + 4*kk + i for the q values of column ln
+    const int qx = qx0 + wave;
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int a = s / QZL, j = s % QZL;
+            const int qy = qy0 + 2 * lpair + a;
+            const int qz = qz0 + zgrp * QZL + j;
+            if (qx >= n.x || qy >= n.y || qz >= n.z) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int st = sb * 16 + 4 * kk + i;
+                if (st >= n_states) continue;
+                const double vr = tot_r[sb][s][i], vi = tot_i[sb][s][i];
+                const size_t o = (((size_t)st * n.x + qx) * n.y + qy) * n.z + qz;
+                if (f) f[o] = make_float2((float)vr, (float)vi);
+                if (f2) f2[o] = (float)(vr * vr + vi * vi);
+            }
+        }
+}
+
+// ---------------------------------------------------------------- points kernel
+
+template <int SB>
+__global__ __launch_bounds__(64) void points_kernel(
+    const VRowDev* __restrict__ rows, const int4* __restrict__ terms,
+    const int* __restrict__ chunk_off, const int* __restrict__ chunk_npp, int n_chunks,
+    const float* __restrict__ Tp, const double* __restrict__ qpts, int nq, int n_states,
+    float2* __restrict__ f, float* __restrict__ f2) {
+    constexpr int SW = 16 * SB;
+    const int iq = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iq >= nq) return;
+    const double qx = qpts[3 * iq], qy = qpts[3 * iq + 1], qz = qpts[3 * iq + 2];
+    float br[SW], bi[SW], tr_[SW], ti[SW];
+    for (int s = 0; s < SW; ++s) br[s] = bi[s] = tr_[s] = ti[s] = 0.f;
+    for (int c = 0; c < n_chunks; ++c) {
+        const int npp = chunk_npp[c];
+        const int4* tc = terms + chunk_off[c];
+        for (int pair = 0; pair < kChunk; ++pair) {
+            float gr = 0.f, gi = 0.f;
+            for (int t = 0; t < npp; ++t) {
+                const int4 tr = tc[pair * npp + t];
+                if (!tr.w) continue;
+                const float2 vx = eval_row(rows[tr.x], qx);
+                const float2 vy = eval_row(rows[tr.y], qy);
+                const float2 vz = eval_row(rows[tr.z], qz);
+                const float wr = vx.x * vy.x - vx.y * vy.y, wi = vx.x * vy.y + vx.y * vy.x;
+                gr = fmaf(wr, vz.x, fmaf(-wi, vz.y, gr));
+                gi = fmaf(wr, vz.y, fmaf(wi, vz.x, gi));
+            }
+            const float* tp = Tp + (size_t)(c * kChunk + pair) * SW;
+            for (int s = 0; s < n_states; ++s) {
+                br[s] = fmaf(tp[s], gr, br[s]);
+                bi[s] = fmaf(tp[s], gi, bi[s]);
+            }
+        }
+        if ((c + 1) % kFoldChunks == 0)
+            for (int s = 0; s < SW; ++s) {
+                tr_[s] += br[s];
+                ti[s] += bi[s];
+                br[s] = bi[s] = 0.f;
+            }
+    }
+    for (int s = 0; s < n_states; ++s) {
+        const float vr = tr_[s] + br[s], vi = ti[s] + bi[s];
+        const size_t o = (size_t)s * nq + iq;
+        if (f) f[o] = make_float2(vr, vi);
+        if (f2) f2[o] = vr * vr + vi * vi;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int n[3],
+                         const double qmin[3], const double dq[3], float2* V, hipStream_t st) {
+    const long long tot = (long long)nrows * vstride;
+    int blocks = (int)((tot + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(vtable_kernel, dim3(blocks), dim3(256), 0, st, rows, nrows, vstride,
+                       make_int3(n[0], n[1], n[2]), make_double3(qmin[0], qmin[1], qmin[2]),
+                       make_double3(dq[0], dq[1], dq[2]), V);
+    return hipGetLastError();
+}
+
+template <int SB, int QZL, int WPE>
+static hipError_t launch_grid_t(const float2* V, int vstride, const int4* terms, const int* coff,
+                                const int* cnpp, int n_chunks, const float* Tp, const int n[3],
+                                int n_states, float2* f, float* f2, hipStream_t st) {
+    const int3 nn = make_int3(n[0], n[1], n[2]);
+    const int3 nt = make_int3((n[0] + 3) / 4, (n[1] + 7) / 8, (n[2] + 4 * QZL - 1) / (4 * QZL));
+    const long long blocks = (long long)nt.x * nt.y * nt.z;
+    hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE>), dim3((unsigned)blocks), dim3(256), 0, st, V, vstride,
+                       terms, coff, cnpp, n_chunks, Tp, nn, nt, n_states, f, f2);
+    return hipGetLastError();
+}
+
+// Row stride of the 1D tables: every tile may read up to 16 values past the
+// last grid point of an axis (zero padding written by vtable_kernel).
+int vtable_stride(const int n[3]) {
+    int m = n[0] > n[1] ? n[0] : n[1];
+    m = m > n[2] ? m : n[2];
+    return ((m + 15) / 16) * 16 + 16;
+}
+
+hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride,
+                       const int4* terms, const int* coff, const int* cnpp, int n_chunks,
+                       const float* Tp, const uint32_t* tp_bf, const int n[3], int n_states,
+                       float2* f, float* f2, hipStream_t st) {
+    (void)tp_bf;
+    if (precision != 0) return hipErrorNotSupported;
+    if (vstride < vtable_stride(n)) return hipErrorInvalidValue;
+    static int variant = -1;
+    if (variant < 0) {
+        const char* e = getenv("SCFF_GRID_VARIANT");
+        variant = e ? atoi(e) : 0;
+    }
+    if (state_blocks == 1) {
+        if (variant == 1) return launch_grid_t<1, 4, 1>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+        if (variant == 3) return launch_grid_t<1, 2, 3>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+        if (variant == 4) return launch_grid_t<1, 2, 2>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+        return launch_grid_t<1, 4, 2>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+    }
+    if (variant == 1) return launch_grid_t<2, 2, 1>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+    if (variant == 5) return launch_grid_t<2, 1, 2>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+    return launch_grid_t<2, 2, 2>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+}
+
+hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
+                         const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
+                         int n_states, float2* f, float* f2, hipStream_t st) {
+    const int blocks = (nq + 63) / 64;
+    if (state_blocks == 1)
+        hipLaunchKernelGGL((points_kernel<1>), dim3(blocks), dim3(64), 0, st, rows, terms, coff, cnpp,
+                           n_chunks, Tp, q, nq, n_states, f, f2);
+    else
+        hipLaunchKernelGGL((points_kernel<2>), dim3(blocks), dim3(64), 0, st, rows, terms, coff, cnpp,
+                           n_chunks, Tp, q, nq, n_states, f, f2);
+    return hipGetLastError();
+}
+
+}  // namespace scff

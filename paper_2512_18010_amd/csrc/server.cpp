@@ -1,0 +1,390 @@
+// Continuous-batching request server of the form-factor engine.
+//
+// Pipeline per request:
+//   submit    copy the caller's inputs, assign a ticket, queue for prep
+//   prep      (host worker pool) basis, pair precompute, screening and
+//             packing; the exact device footprint is known afterwards
+//   admit     (scheduler) strictly in ticket order: the head request starts
+//             when its footprint fits the HBM budget next to everything in
+//             flight and a run slot is free; requests arriving meanwhile
+//             queue behind it, so no request starves
+//   run       (run slot, one HIP stream each) upload, 1D tables, fused
+//             generator + MFMA kernel, copy to the caller's host buffers;
+//             several requests run at once and their kernels overlap on
+//             the device
+//   complete  release the footprint, record latency, wake waiters
+// A failing request records its own status and never affects others.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/scarff.h"
+#include "engine.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class St { Queued, Ready, Running, Done, Cancelled };
+
+struct Req {
+    unsigned long long ticket = 0;
+    // owned copies of the inputs
+    std::vector<double> xyz, exps, coefs, T;
+    std::vector<int> sh_atom, sh_l, sh_nprim;
+    int n_atoms = 0, n_shells = 0, normalise = 1, n_states = 0, precision = 0;
+    scff_grid grid{};
+    double eps = 0.0, spin = 1.0;
+    float* f = nullptr;
+    float* f2 = nullptr;
+    // execution state
+    scff_ctx* ctx = nullptr;
+    size_t bytes = 0;
+    St state = St::Queued;
+    int status = SCFF_OK;
+    bool waited = false;
+    Clock::time_point t_submit, t_done;
+};
+
+}  // namespace
+
+struct scff_server {
+    int device = 0;
+    bool fake = false;   // scheduler test mode: no device work
+    size_t budget = 0;
+    int max_inflight = 1;
+    std::mutex mu;
+    std::condition_variable cv_prep, cv_sched, cv_run, cv_done;
+    std::deque<unsigned long long> prep_q;     // tickets waiting for prep
+    std::deque<unsigned long long> admit_q;    // tickets in submit order, not yet admitted
+    std::deque<unsigned long long> run_q;      // admitted, waiting for a run slot thread
+    std::map<unsigned long long, std::unique_ptr<Req>> reqs;
+    unsigned long long next_ticket = 1;
+    size_t admitted = 0, peak_admitted = 0;
+    int inflight = 0;
+    long long n_submitted = 0, n_completed = 0, n_failed = 0, n_cancelled = 0;
+    bool stop = false;
+    std::vector<std::thread> threads;
+};
+
+namespace {
+
+int sfail(int code, const std::string& m) {
+    scff::set_error(m);
+    return code;
+}
+
+void finish(scff_server* s, Req* r, int status) {
+    // caller holds s->mu
+    r->status = status;
+    r->state = St::Done;
+    r->t_done = Clock::now();
+    if (status == SCFF_OK)
+        ++s->n_completed;
+    else
+        ++s->n_failed;
+    s->cv_done.notify_all();
+}
+
+void prep_loop(scff_server* s) {
+    for (;;) {
+        unsigned long long t;
+        Req* r;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_prep.wait(lk, [&] { return s->stop || !s->prep_q.empty(); });
+            if (s->stop) return;
+            t = s->prep_q.front();
+            s->prep_q.pop_front();
+            r = s->reqs[t].get();
+            if (r->state == St::Cancelled) continue;
+        }
+        int rc = SCFF_OK;
+        size_t bytes = 0;
+        scff_ctx* c = nullptr;
+        std::string err;
+        if (!s->fake) {
+            rc = scff_create(s->device, 0, &c);
+        } else {
+            rc = SCFF_OK;
+        }
+        if (rc == SCFF_OK && !s->fake) {
+            rc = scff_load_molecule(c, r->n_atoms, r->xyz.data(), r->n_shells, r->sh_atom.data(),
+                                    r->sh_l.data(), r->sh_nprim.data(), r->exps.data(), r->coefs.data(),
+                                    r->normalise, nullptr);
+            if (rc == SCFF_OK) rc = scff_load_transitions(c, r->n_states, r->T.data());
+            if (rc == SCFF_OK) rc = scff_set_options(c, r->eps, r->spin);
+            if (rc == SCFF_OK) rc = scff::ctx_prepare(c, &r->grid, &bytes);
+        } else if (rc == SCFF_OK) {
+            // scheduler test mode: footprint of the outputs only
+            bytes = (size_t)r->grid.n[0] * r->grid.n[1] * r->grid.n[2] * (size_t)r->n_states * 12;
+        }
+        if (rc != SCFF_OK) err = scff_last_error();
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (rc != SCFF_OK) {
+            if (c) scff_destroy(c);
+            scff::set_error(err);
+            // remove from the admission queue and fail alone
+            for (auto it = s->admit_q.begin(); it != s->admit_q.end(); ++it)
+                if (*it == t) {
+                    s->admit_q.erase(it);
+                    break;
+                }
+            finish(s, r, rc);
+        } else if (r->state == St::Cancelled) {
+            if (c) scff_destroy(c);
+        } else {
+            r->ctx = c;
+            r->bytes = bytes;
+            r->state = St::Ready;
+        }
+        s->cv_sched.notify_all();
+    }
+}
+
+void sched_loop(scff_server* s) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        if (s->stop) return;
+        bool progressed = false;
+        while (!s->admit_q.empty()) {
+            const unsigned long long t = s->admit_q.front();
+            Req* r = s->reqs[t].get();
+            if (r->state == St::Cancelled) {
+                s->admit_q.pop_front();
+                progressed = true;
+                continue;
+            }
+            if (r->state == St::Done) {   // failed in prep
+                s->admit_q.pop_front();
+                progressed = true;
+                continue;
+            }
+            if (r->state != St::Ready) break;                 // head not prepared yet
+            if (r->bytes > s->budget) {                       // can never fit
+                s->admit_q.pop_front();
+                if (r->ctx) scff_destroy(r->ctx);
+                r->ctx = nullptr;
+                scff::set_error("request footprint exceeds the server's HBM budget");
+                finish(s, r, SCFF_ENOMEM);
+                progressed = true;
+                continue;
+            }
+            if (s->inflight >= s->max_inflight || s->admitted + r->bytes > s->budget) break;
+            s->admit_q.pop_front();
+            r->state = St::Running;
+            s->admitted += r->bytes;
+            if (s->admitted > s->peak_admitted) s->peak_admitted = s->admitted;
+            ++s->inflight;
+            s->run_q.push_back(t);
+            s->cv_run.notify_one();
+            progressed = true;
+        }
+        if (!progressed) s->cv_sched.wait(lk);
+    }
+}
+
+void run_loop(scff_server* s) {
+    hipStream_t st = nullptr;
+    if (!s->fake) {
+        (void)hipSetDevice(s->device);
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    }
+    for (;;) {
+        Req* r;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_run.wait(lk, [&] { return s->stop || !s->run_q.empty(); });
+            if (s->stop && s->run_q.empty()) break;
+            r = s->reqs[s->run_q.front()].get();
+            s->run_q.pop_front();
+        }
+        int rc = SCFF_OK;
+        std::string err;
+        if (!s->fake) {
+            rc = scff_eval_grid(r->ctx, &r->grid, r->precision, r->f, r->f2, 0, st);
+            if (rc != SCFF_OK) err = scff_last_error();
+            scff_destroy(r->ctx);
+            r->ctx = nullptr;
+        } else {
+            std::this_thread::sleep_for(std::chrono::milliseconds(2));
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->admitted -= r->bytes;
+        --s->inflight;
+        if (rc != SCFF_OK) scff::set_error(err);
+        finish(s, r, rc);
+        s->cv_sched.notify_all();
+    }
+    if (st) (void)hipStreamDestroy(st);
+}
+
+template <class T>
+void copy_in(std::vector<T>& dst, const T* src, size_t n) {
+    dst.assign(src, src + n);
+}
+
+}  // namespace
+
+extern "C" {
+
+int scff_server_create(int device, size_t hbm_budget_bytes, int max_inflight, scff_server** out) {
+    if (!out) return sfail(SCFF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_inflight < 1 || max_inflight > 64) return sfail(SCFF_EINVAL, "max_inflight must be in 1..64");
+    const bool fake = (device == -1);
+    if (!fake) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return sfail(SCFF_EDEVICE, "no HIP device available");
+        if (device < 0 || device >= n) return sfail(SCFF_EINVAL, "device index out of range");
+    }
+    scff_server* s = new scff_server();
+    s->device = fake ? 0 : device;
+    s->fake = fake;
+    s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)64 << 30;
+    s->max_inflight = max_inflight;
+    const int n_prep = 4;
+    for (int i = 0; i < n_prep; ++i) s->threads.emplace_back(prep_loop, s);
+    s->threads.emplace_back(sched_loop, s);
+    for (int i = 0; i < max_inflight; ++i) s->threads.emplace_back(run_loop, s);
+    *out = s;
+    return SCFF_OK;
+}
+
+int scff_server_submit(scff_server* s, const scff_request* q, unsigned long long* ticket) {
+    if (!s || !q || !ticket) return sfail(SCFF_EINVAL, "NULL argument");
+    if (q->n_atoms <= 0 || q->n_shells <= 0 || !q->xyz_bohr || !q->shell_atom || !q->shell_l ||
+        !q->shell_nprim || !q->exps || !q->coefs || !q->T)
+        return sfail(SCFF_EINVAL, "malformed request (sizes or NULL arrays)");
+    if (q->n_states < 1 || q->n_states > scff::kMaxStates) return sfail(SCFF_EINVAL, "n_states must be in 1..32");
+    if (!q->f && !q->f2) return sfail(SCFF_EINVAL, "request has no output buffer");
+    int nprim = 0, nbf = 0;
+    for (int i = 0; i < q->n_shells; ++i) {
+        if (q->shell_nprim[i] < 1 || q->shell_nprim[i] > 32) return sfail(SCFF_EINVAL, "shell_nprim out of range");
+        if (q->shell_l[i] < 0 || q->shell_l[i] > 2) return sfail(SCFF_EINVAL, "shell_l must be 0..2");
+        nprim += q->shell_nprim[i];
+        nbf += (q->shell_l[i] + 1) * (q->shell_l[i] + 2) / 2;
+    }
+    auto r = std::make_unique<Req>();
+    copy_in(r->xyz, q->xyz_bohr, (size_t)3 * q->n_atoms);
+    copy_in(r->sh_atom, q->shell_atom, q->n_shells);
+    copy_in(r->sh_l, q->shell_l, q->n_shells);
+    copy_in(r->sh_nprim, q->shell_nprim, q->n_shells);
+    copy_in(r->exps, q->exps, nprim);
+    copy_in(r->coefs, q->coefs, nprim);
+    copy_in(r->T, q->T, (size_t)q->n_states * nbf * nbf);
+    r->n_atoms = q->n_atoms;
+    r->n_shells = q->n_shells;
+    r->normalise = q->normalise;
+    r->n_states = q->n_states;
+    r->precision = q->precision;
+    r->grid = q->grid;
+    r->eps = q->screen_eps;
+    r->spin = q->spin_factor;
+    r->f = q->f;
+    r->f2 = q->f2;
+    r->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    const unsigned long long t = s->next_ticket++;
+    r->ticket = t;
+    s->reqs[t] = std::move(r);
+    s->prep_q.push_back(t);
+    s->admit_q.push_back(t);
+    ++s->n_submitted;
+    *ticket = t;
+    s->cv_prep.notify_one();
+    return SCFF_OK;
+}
+
+int scff_server_wait(scff_server* s, unsigned long long ticket, long long timeout_ns, int* status,
+                     long long* latency_ns) {
+    if (!s) return sfail(SCFF_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end() || it->second->waited) return sfail(SCFF_EINVAL, "unknown ticket");
+    Req* r = it->second.get();
+    auto done = [&] { return r->state == St::Done || r->state == St::Cancelled; };
+    if (timeout_ns < 0)
+        s->cv_done.wait(lk, done);
+    else if (!s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done))
+        return sfail(SCFF_EBUSY, "request not finished");
+    const int st = r->state == St::Cancelled ? SCFF_ECANCELLED : r->status;
+    if (status) *status = st;
+    if (latency_ns)
+        *latency_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_done - r->t_submit).count();
+    s->reqs.erase(it);
+    return SCFF_OK;
+}
+
+int scff_server_cancel(scff_server* s, unsigned long long ticket) {
+    if (!s) return sfail(SCFF_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return sfail(SCFF_EINVAL, "unknown ticket");
+    Req* r = it->second.get();
+    if (r->state == St::Running || r->state == St::Done) return sfail(SCFF_EBUSY, "request already running or finished");
+    r->state = St::Cancelled;
+    r->t_done = Clock::now();
+    if (r->ctx) {
+        scff_destroy(r->ctx);
+        r->ctx = nullptr;
+    }
+    ++s->n_cancelled;
+    s->cv_done.notify_all();
+    s->cv_sched.notify_all();
+    return SCFF_OK;
+}
+
+int scff_server_stats_get(scff_server* s, scff_server_stats* o) {
+    if (!s || !o) return sfail(SCFF_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    o->submitted = s->n_submitted;
+    o->completed = s->n_completed;
+    o->failed = s->n_failed;
+    o->cancelled = s->n_cancelled;
+    o->queued = (long long)s->admit_q.size();
+    o->inflight = s->inflight;
+    o->admitted_bytes = s->admitted;
+    o->budget_bytes = s->budget;
+    o->peak_admitted_bytes = s->peak_admitted;
+    return SCFF_OK;
+}
+
+void scff_server_destroy(scff_server* s) {
+    if (!s) return;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        // cancel everything not yet running, let running requests finish
+        for (auto& kv : s->reqs)
+            if (kv.second->state == St::Queued || kv.second->state == St::Ready) {
+                kv.second->state = St::Cancelled;
+                if (kv.second->ctx) {
+                    scff_destroy(kv.second->ctx);
+                    kv.second->ctx = nullptr;
+                }
+            }
+        s->admit_q.clear();
+        s->cv_done.wait(lk, [&] { return s->inflight == 0 && s->run_q.empty(); });
+        s->stop = true;
+    }
+    s->cv_prep.notify_all();
+    s->cv_sched.notify_all();
+    s->cv_run.notify_all();
+    s->cv_done.notify_all();
+    for (auto& t : s->threads) t.join();
+    for (auto& kv : s->reqs)
+        if (kv.second->ctx) scff_destroy(kv.second->ctx);
+    delete s;
+}
+
+}  // extern "C"

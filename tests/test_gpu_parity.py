@@ -1,0 +1,128 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Small cases are compared element by element over whole grids that span
+several tiles and ragged tails; the full benchmark-size workloads are run
+in the launch configuration the benchmark times and compared on a seeded
+sample of grid points (plus the grid's |f|^2 maximum), with the tolerance
+of the precision (peak-normalised |f|^2: 1e-6 FP32, 1e-4 split-BF16).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workload as wl
+from tests.metrics import TOL_F2, errors
+
+pytestmark = pytest.mark.gpu
+
+NTH = min(16, os.cpu_count() or 1)
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch  # noqa: F401  (initialises HIP the same way the benchmark does)
+    from paper_2512_18010_amd import binding
+    ctx = binding.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def run_grid(eng, W, precision="fp32", eps=0.0, spin=1.0):
+    eng.load_molecule(W.mol)
+    eng.load_transitions(W.T)
+    eng.set_options(eps, spin)
+    f, f2 = eng.eval_grid_host(W.grid, precision)
+    return f, f2
+
+
+def check(name, f_gpu, f2_gpu, f_ref, precision):
+    e = errors(f_gpu, f_ref)
+    # |f|^2 output must be consistent with f
+    np.testing.assert_allclose(f2_gpu, np.abs(f_gpu) ** 2, rtol=2e-6, atol=1e-12 * np.abs(f_gpu).max() ** 2)
+    log(f"[{name}] {precision}: max peak-normalised |f|^2 err {e['f2_peak_norm'].max():.3e}, "
+        f"complex {e['complex'].max():.3e}, rel(big) {e['f2_rel_big'].max():.3e}")
+    assert e["f2_peak_norm"].max() <= TOL_F2[precision], e["f2_peak_norm"]
+    return e
+
+
+@pytest.mark.parametrize("precision", ["fp32"])
+def test_small_full_grid_ragged(eng, oracle_mod, precision):
+    """Config-0 molecule on a ragged 13 x 11 x 37 grid: every element vs the oracle."""
+    W = wl.make_config(0)
+    W.grid = wl.Grid(n=(13, 11, 37), qmin=(-5.0, -4.0, -5.5), qmax=(5.0, 4.5, 5.0))
+    log("case small_full_grid_ragged", W.grid.n)
+    f, f2 = run_grid(eng, W, precision)
+    ref = oracle_mod.eval_grid(W.mol, W.T, W.grid, n_threads=NTH)
+    check("cfg0 13x11x37", f, f2, ref, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32"])
+def test_multi_state_full_grid(eng, oracle_mod, precision):
+    """A 24-state case (two MFMA row blocks) on a small ragged grid."""
+    rng = np.random.Generator(np.random.PCG64(99))
+    mol = wl.make_molecule(rng, 3, 2, layout="box", box_A=3.0)
+    T = wl.make_transitions(rng, mol.nbf, wl.n_occupied(mol.Z), 24)
+    W = wl.Workload("24 states", mol, T, wl.Grid(n=(9, 10, 21), qmin=(-6.0,) * 3, qmax=(6.0,) * 3), 99)
+    log("case multi_state_full_grid", W.grid.n, mol.nbf)
+    f, f2 = run_grid(eng, W, precision)
+    ref = oracle_mod.eval_grid(W.mol, W.T, W.grid, n_threads=NTH)
+    check("24 states 9x10x21", f, f2, ref, precision)
+
+
+def sampled_parity(eng, oracle_mod, cfg, precision, n_sample, eps=0.0):
+    W = wl.make_config(cfg)
+    log(f"case sampled cfg{cfg} {precision} eps={eps}", W.grid.n)
+    f, f2 = run_grid(eng, W, precision, eps=eps)
+    info = eng.query()
+    log(f"  K={info['pairs_kept']} R={info['prim_comp_pairs_kept']}")
+    idx = wl.sample_grid_indices(W.grid, n_sample, seed=1234 + cfg)
+    flat2 = f2.reshape(f2.shape[0], -1)
+    idx = np.unique(np.concatenate([idx, flat2.argmax(axis=1)]))
+    pts = W.grid.points()[idx]
+    ref = oracle_mod.eval_points(W.mol, W.T, pts, n_threads=NTH)
+    fs = f.reshape(f.shape[0], -1)[:, idx]
+    f2s = flat2[:, idx]
+    # the peak of the reference is taken over the sample, which contains the
+    # GPU grid maximum of every state
+    return check(f"cfg{cfg} sampled {len(idx)}", fs, f2s, ref, precision)
+
+
+def test_config1_sampled(eng, oracle_mod):
+    sampled_parity(eng, oracle_mod, 1, "fp32", 256)
+
+
+def test_config2_sampled(eng, oracle_mod):
+    sampled_parity(eng, oracle_mod, 2, "fp32", 128)
+
+
+def test_config3_sampled_screened(eng, oracle_mod):
+    sampled_parity(eng, oracle_mod, 3, "fp32", 48, eps=1e-9)
+
+
+def test_conjugate_symmetry_on_gpu(eng):
+    """f(-q) = f(q)* on the symmetric grid (real T)."""
+    W = wl.make_config(0)
+    W.grid = wl.Grid(n=(16, 17, 24), qmin=(-5.0,) * 3, qmax=(5.0,) * 3)
+    f, _ = run_grid(eng, W)
+    g = np.conj(f[:, ::-1, ::-1, ::-1])
+    scale = np.abs(f).max()
+    assert np.abs(f - g).max() <= 1e-6 * scale
+
+
+def test_points_parity(eng, oracle_mod):
+    W = wl.make_config(0)
+    eng.load_molecule(W.mol)
+    eng.load_transitions(W.T)
+    eng.set_options(0.0, 1.0)
+    rng = np.random.Generator(np.random.PCG64(5))
+    q = np.concatenate([np.zeros((1, 3)), rng.uniform(-6, 6, size=(300, 3))])
+    f, f2 = eng.eval_points(q)
+    ref = oracle_mod.eval_points(W.mol, W.T, q, n_threads=NTH)
+    check("cfg0 points", f, f2, ref, "fp32")
