@@ -97,7 +97,7 @@ void scff_destroy(scff_ctx* ctx);
  *   xyz_bohr     [n_atoms*3]     atom positions
  *   shell_atom   [n_shells]      atom index of each shell
  *   shell_l      [n_shells]      0, 1 or 2
- *   shell_nprim  [n_shells]      primitives per shell (1..16)
+ *   shell_nprim  [n_shells]      primitives per shell (1..32)
  *   exps, coefs  [sum nprim]     exponents alpha_k > 0 (bohr^-2) and
  *                                contraction coefficients d_k, concatenated
  *                                in shell order
@@ -118,6 +118,14 @@ int scff_load_molecule(scff_ctx* ctx, int n_atoms, const double* xyz_bohr, int n
  * packs T_{mu nu} + T_{nu mu} per unique pair.
  */
 int scff_load_transitions(scff_ctx* ctx, int n_states, const double* T);
+
+/*
+ * Same as scff_load_transitions with T already in device memory of the
+ * context's device: T_dev [n_states][nbf][nbf] FP64, copied on hip_stream
+ * (asynchronous; the caller keeps T_dev valid until the stream reaches the
+ * copy).  T_dev is not checked for non-finite entries.
+ */
+int scff_load_transitions_device(scff_ctx* ctx, int n_states, const double* T_dev, void* hip_stream);
 
 /*
  * Options.  screen_eps >= 0: pair screening threshold (paper Sec. 5.3,
@@ -153,6 +161,17 @@ int scff_eval_grid(scff_ctx* ctx, const scff_grid* grid, int precision, float* f
  */
 int scff_eval_points(scff_ctx* ctx, int n_q, const double* q, int precision, float* f,
                      float* f2, int out_on_device, void* hip_stream);
+
+/*
+ * Per-kernel timing.  With enable = 1 the context records HIP events (on the
+ * stream of the call) around the pair precompute, the 1D-table kernel and
+ * the fused grid kernel of each evaluation; scff_last_timing waits for the
+ * last evaluation's events and reports those durations in milliseconds
+ * (prep_ms is 0 when that evaluation reused an existing precompute).  Off
+ * by default.  Any pointer may be NULL.
+ */
+int scff_set_timing(scff_ctx* ctx, int enable);
+int scff_last_timing(scff_ctx* ctx, float* prep_ms, float* vtable_ms, float* grid_ms);
 
 /* Sizes and screening statistics of the loaded problem. */
 int scff_query(scff_ctx* ctx, scff_info* info);

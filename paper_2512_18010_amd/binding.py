@@ -78,12 +78,15 @@ scff_load_molecule = _fn("scff_load_molecule", c_int,
                          [c_void_p, c_int, P(c_double), c_int, P(c_int), P(c_int), P(c_int),
                           P(c_double), P(c_double), c_int, P(c_int)])
 scff_load_transitions = _fn("scff_load_transitions", c_int, [c_void_p, c_int, P(c_double)])
+scff_load_transitions_device = _fn("scff_load_transitions_device", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 scff_set_options = _fn("scff_set_options", c_int, [c_void_p, c_double, c_double])
 scff_eval_grid = _fn("scff_eval_grid", c_int,
                      [c_void_p, P(scff_grid), c_int, c_void_p, c_void_p, c_int, c_void_p])
 scff_eval_points = _fn("scff_eval_points", c_int,
                        [c_void_p, c_int, P(c_double), c_int, c_void_p, c_void_p, c_int, c_void_p])
 scff_query = _fn("scff_query", c_int, [c_void_p, P(scff_info)])
+scff_set_timing = _fn("scff_set_timing", c_int, [c_void_p, c_int])
+scff_last_timing = _fn("scff_last_timing", c_int, [c_void_p, P(c_float), P(c_float), P(c_float)])
 scff_export_vtensors = _fn("scff_export_vtensors", c_int,
                            [c_void_p, P(scff_grid), P(c_longlong), c_void_p, c_void_p, c_void_p,
                             c_void_p])
@@ -184,8 +187,23 @@ class Context:
         check(scff_load_transitions(self._h, T.shape[0], _d(T)))
         self.n_states = T.shape[0]
 
+    def load_transitions_device(self, T_dev, stream=None):
+        """T_dev: a contiguous float64 device tensor [n_states, nbf, nbf] (e.g. torch on 'cuda')."""
+        ns = int(T_dev.shape[0])
+        check(scff_load_transitions_device(self._h, ns, ctypes.c_void_p(T_dev.data_ptr()), _stream_ptr(stream)))
+        self.n_states = ns
+
     def set_options(self, screen_eps: float = 0.0, spin_factor: float = 1.0):
         check(scff_set_options(self._h, float(screen_eps), float(spin_factor)))
+
+    def set_timing(self, enable: bool = True):
+        check(scff_set_timing(self._h, int(bool(enable))))
+
+    def last_timing(self):
+        """(prep_ms, vtable_ms, grid_ms) of the last timed evaluation (HIP events on its stream)."""
+        p, a, b = c_float(), c_float(), c_float()
+        check(scff_last_timing(self._h, ctypes.byref(p), ctypes.byref(a), ctypes.byref(b)))
+        return p.value, a.value, b.value
 
     def query(self) -> dict:
         info = scff_info()

@@ -4,8 +4,11 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "../../include/scarff.h"
 
@@ -22,21 +25,12 @@ constexpr int kStateBlock = 16;
 constexpr int kMaxStates = 32;
 constexpr int kMaxPrim = 32;
 
-// One 1D V-tensor row: a (primitive pair, axis, power pair) triple.  On a
+// One 1D V-tensor row is a (primitive pair, axis, power pair) triple.  On a
 // q value of its axis it evaluates
 //   V(q) = exp(-q^2/(4p)) * exp(i q P) * sum_u e[u] (i q)^u ,
 // where every q-independent factor of the pair (contraction coefficients,
-// primitive normalisation on this axis, sqrt(pi/p) and the Gaussian product
-// prefactor; on the x row also the remaining axes' prefactors) is folded
-// into e[].
-struct VRow {
-    double p;        // alpha + beta
-    double P;        // product centre on this axis
-    double e[5];     // polynomial coefficients, u = 0..deg
-    int axis;
-    int deg;         // i + j
-};
-
+// primitive normalisation on this axis, and on the x row the Gaussian
+// product prefactor with (pi/p)^{3/2}) is folded into e[].
 // Device copy of a row.  The 1D tables are built from it in FP64 and rounded
 // once to FP32 (phase argument, range reduction, Gaussian and polynomial).
 struct VRowDev {
@@ -47,61 +41,77 @@ struct VRowDev {
     int axis;
 };
 
-struct Term {        // one (component pair, primitive pair) term
-    int row[3];
-    double bound;    // q-independent bound of |V^x V^y V^z| over all q
+// A device allocation owned by a context.
+struct DeviceBuffer {
+    void* p = nullptr;
+    size_t bytes = 0;
 };
 
-struct CompPair {
-    int mu, nu;
-    int first_term, n_terms;
+struct PrepShell {
+    int atom, l, nprim, off;
 };
 
+// Host-side view of a loaded molecule: validated basis plus the integer
+// tables that lay out rows, component pairs and terms (no arithmetic of the
+// method beyond normalisation constants).
 struct Basis {
     int n_atoms = 0, n_shells = 0, nbf = 0;
     std::vector<double> xyz;
     std::vector<int> sh_atom, sh_l, sh_nprim, sh_off, sh_bf0;
     std::vector<double> exps, coefs;
     std::vector<double> cnorm;   // contracted normalisation per AO
-    std::vector<int> bf_shell;   // shell of each AO
-    std::vector<int> bf_pw;      // 3 powers per AO
+    std::vector<double> n1d;     // per primitive, 1D normalisation for powers 0..2
     bool normalise = true;
+    // layout tables
+    int n_sp = 0, n_cp = 0;
+    long long n_rows = 0, n_terms = 0;
+    std::vector<PrepShell> shells;
+    std::vector<int> sp;          // 4 ints per shell pair: sA, sB, row_off, term_off
+    std::vector<int> sp_cp;       // first component pair of each shell pair
+    std::vector<int> cp_first;    // first term of each component pair
+    std::vector<int> cp_nterms;   // primitive pairs of each component pair
 };
 
-struct PairData {               // q- and T-independent pair precompute
-    std::vector<VRow> rows;
-    std::vector<Term> terms;
-    std::vector<CompPair> cps;
-    long long shell_pairs = 0;
-    long long prim_pairs_total = 0;   // sum over component pairs of primitive pairs
+// Device pointers the precompute reads.
+struct PrepInputs {
+    const PrepShell* shells;
+    const int4* sp;
+    const int* sp_cp;
+    const int* bf0;
+    const int* cp_first;
+    const int* cp_nterms;
+    const double* xyz;
+    const double* exps;
+    const double* coefs;
+    const double* n1d;
+    const double* cnorm;
+    const double* T;
+    int nbf, n_states, n_sp, n_cp;
+    long long n_rows_all, n_terms_all;
+    double eps, spin;
 };
 
-// Result of screening + packing for one (molecule, T, options) state.
-struct Packed {
-    int n_states = 0;
-    int state_blocks = 1;              // 16-row MFMA blocks (1 or 2)
-    int n_vpairs = 0;                  // virtual component pairs (padded to kChunk)
-    int n_chunks = 0;
-    std::vector<int> chunk_off;        // offset of chunk c in `terms`
-    std::vector<int> chunk_npp;        // terms per virtual pair in chunk c
-    std::vector<int> terms;            // [chunk][kChunk][npp] x 4 ints (rowx,rowy,rowz,valid)
-    std::vector<VRowDev> rows;         // compacted rows referenced by kept terms
-    std::vector<float> tp;             // [n_vpairs][16*state_blocks]
-    std::vector<uint16_t> tp_hi, tp_lo;   // split-BF16 copies of tp
-    long long pairs_kept = 0;          // K
-    long long terms_kept = 0;          // R
-    long long pairs_total = 0;
+// Device buffers of the precompute; rows/slots/cnpp/coff/tp32/tpbf are what
+// the evaluation kernels consume.
+struct PrepWork {
+    DeviceBuffer rows_all, rowsum, trow, tbound, wt, cpmn, tp64, bsum, part, small, nk, nv, vbase,
+        tmp, key, val, vinfo, tmp2, cnpp, csize, coff, tmp3, slots, tp32, tpbf, row_used, newid, tmp4,
+        rows;
 };
 
-// ---- host precompute (precompute.cpp) ----
+struct PrepResult {
+    int n_vpairs = 0, n_chunks = 0, n_rows = 0, state_blocks = 1;
+    long long n_slots = 0, pairs_kept = 0, terms_kept = 0;
+};
+
+// ---- host side of the precompute (precompute.cpp) ----
 std::string build_basis(Basis& b, int n_atoms, const double* xyz, int n_shells,
                         const int* shell_atom, const int* shell_l, const int* shell_nprim,
                         const double* exps, const double* coefs, int normalise);
-void build_pairs(const Basis& b, PairData& pd);
-std::string pack(const Basis& b, const PairData& pd, int n_states, const double* T,
-                 double screen_eps, double spin_factor, Packed& out);
-uint16_t bf16_rne(float x);
-float bf16_to_float(uint16_t h);
+
+// ---- device precompute (prep.hip) ----
+hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStream_t st,
+                    const std::function<hipError_t(DeviceBuffer&, size_t)>& alloc);
 
 // ---- runtime.cpp ----
 // Thread-local message returned by scff_last_error().

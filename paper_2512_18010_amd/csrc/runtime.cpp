@@ -6,7 +6,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,11 +15,11 @@
 namespace scff {
 hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int n[3],
                          const double qmin[3], const double dq[3], float2* V, hipStream_t st);
+int vtable_stride(const int n[3]);
 hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride,
                        const int4* terms, const int* coff, const int* cnpp, int n_chunks,
                        const float* Tp, const uint32_t* tp_bf, const int n[3], int n_states,
                        float2* f, float* f2, hipStream_t st);
-int vtable_stride(const int n[3]);
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
                          const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
                          int n_states, float2* f, float* f2, hipStream_t st);
@@ -34,6 +33,33 @@ thread_local std::string g_err;
 
 void scff::set_error(const std::string& msg) { g_err = msg; }
 
+// Timing events: precompute start/end, 1D tables start, grid kernel start/end.
+enum { EV_PREP0, EV_PREP1, EV_VT0, EV_GRID0, EV_GRID1, EV_N };
+
+struct scff_ctx {
+    int device = 0;
+    size_t budget = 0;   // 0 = unlimited
+    size_t used = 0;
+    Basis basis;
+    bool have_mol = false;
+    int n_states = 0;
+    bool have_T = false;
+    double eps = 0.0, spin = 1.0;
+    // molecule tables on the device
+    DeviceBuffer d_shells, d_sp, d_sp_cp, d_bf0, d_cp_first, d_cp_nterms, d_xyz, d_exps, d_coefs,
+        d_n1d, d_cnorm, d_T;
+    // precompute results and evaluation buffers
+    PrepWork prep;
+    PrepResult pres;
+    bool prepared = false;
+    DeviceBuffer d_vtab, d_f, d_f2, d_q;
+    int vtab_rows = 0, vtab_stride = 0;
+    // timing
+    bool timing = false;
+    hipEvent_t ev[EV_N] = {};
+    bool ev_recorded = false, ev_prep = false;
+};
+
 namespace {
 
 int fail(int code, const std::string& msg) {
@@ -46,35 +72,7 @@ int ok() {
     return SCFF_OK;
 }
 
-// One device allocation owned by a context.
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-};
-
-}  // namespace
-
-struct scff_ctx {
-    int device = 0;
-    size_t budget = 0;   // 0 = unlimited
-    size_t used = 0;
-    Basis basis;
-    PairData pairs;
-    bool have_mol = false;
-    std::vector<double> T;
-    int n_states = 0;
-    bool have_T = false;
-    double eps = 0.0, spin = 1.0;
-    Packed packed;
-    bool packed_valid = false;   // host packing matches molecule/T/options
-    bool uploaded = false;       // device copies match `packed`
-    DevBuf d_rows, d_terms, d_coff, d_cnpp, d_tp, d_tpbf, d_vtab, d_f, d_f2, d_q;
-    int vtab_rows = 0, vtab_stride = 0;
-};
-
-namespace {
-
-void dev_free(scff_ctx* c, DevBuf& b) {
+void dev_free(scff_ctx* c, DeviceBuffer& b) {
     if (b.p) {
         (void)hipFree(b.p);
         c->used -= b.bytes;
@@ -84,62 +82,85 @@ void dev_free(scff_ctx* c, DevBuf& b) {
 }
 
 // Ensure `b` holds at least `bytes`; keeps the old buffer if large enough.
-int dev_reserve(scff_ctx* c, DevBuf& b, size_t bytes) {
+hipError_t dev_reserve_raw(scff_ctx* c, DeviceBuffer& b, size_t bytes) {
     if (bytes == 0) bytes = 256;
-    if (b.p && b.bytes >= bytes) return SCFF_OK;
+    if (b.p && b.bytes >= bytes) return hipSuccess;
     const size_t old = b.bytes;
-    if (c->budget && c->used - old + bytes > c->budget)
-        return fail(SCFF_ENOMEM, "HBM budget exceeded: need " + std::to_string(c->used - old + bytes) +
-                                     " bytes, budget " + std::to_string(c->budget));
+    if (c->budget && c->used - old + bytes > c->budget) return hipErrorOutOfMemory;
     dev_free(c, b);
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) return fail(SCFF_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return e;
     b.p = p;
     b.bytes = bytes;
     c->used += bytes;
+    return hipSuccess;
+}
+
+int dev_reserve(scff_ctx* c, DeviceBuffer& b, size_t bytes) {
+    hipError_t e = dev_reserve_raw(c, b, bytes);
+    if (e == hipErrorOutOfMemory)
+        return fail(SCFF_ENOMEM, "HBM budget or device memory exceeded (need " + std::to_string(bytes) +
+                                     " more bytes, context holds " + std::to_string(c->used) + ")");
+    if (e != hipSuccess) return fail(SCFF_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
     return SCFF_OK;
 }
 
 int hip_check(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return fail(SCFF_ENOMEM, std::string(what) + ": out of device memory or HBM budget");
     if (e != hipSuccess) return fail(SCFF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
     return SCFF_OK;
 }
 
-int upload(scff_ctx* c, DevBuf& b, const void* src, size_t bytes, hipStream_t st) {
+int upload_sync(scff_ctx* c, DeviceBuffer& b, const void* src, size_t bytes) {
     int rc = dev_reserve(c, b, bytes);
     if (rc) return rc;
-    if (bytes) return hip_check(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, st), "upload");
+    if (bytes) return hip_check(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice), "upload");
     return SCFF_OK;
 }
 
-int ensure_packed(scff_ctx* c, hipStream_t st) {
+int set_device(scff_ctx* c) { return hip_check(hipSetDevice(c->device), "hipSetDevice"); }
+
+int record(scff_ctx* c, int which, hipStream_t st) {
+    if (!c->timing) return SCFF_OK;
+    return hip_check(hipEventRecord(c->ev[which], st), "event record");
+}
+
+int ensure_prepared(scff_ctx* c, hipStream_t st) {
     if (!c->have_mol) return fail(SCFF_ESTATE, "no molecule loaded");
     if (!c->have_T) return fail(SCFF_ESTATE, "no transitions loaded");
-    if (!c->packed_valid) {
-        Packed pk;
-        std::string err = pack(c->basis, c->pairs, c->n_states, c->T.data(), c->eps, c->spin, pk);
-        if (!err.empty()) return fail(SCFF_EINVAL, err);
-        c->packed = std::move(pk);
-        c->packed_valid = true;
-        c->uploaded = false;
-    }
-    if (!c->uploaded) {
-        const Packed& p = c->packed;
-        int rc;
-        if ((rc = upload(c, c->d_rows, p.rows.data(), p.rows.size() * sizeof(VRowDev), st))) return rc;
-        if ((rc = upload(c, c->d_terms, p.terms.data(), p.terms.size() * sizeof(int), st))) return rc;
-        if ((rc = upload(c, c->d_coff, p.chunk_off.data(), p.chunk_off.size() * sizeof(int), st))) return rc;
-        if ((rc = upload(c, c->d_cnpp, p.chunk_npp.data(), p.chunk_npp.size() * sizeof(int), st))) return rc;
-        if ((rc = upload(c, c->d_tp, p.tp.data(), p.tp.size() * sizeof(float), st))) return rc;
-        // split-BF16 operand: per entry (hi | lo << 16)
-        std::vector<uint32_t> bf(p.tp.size());
-        for (size_t i = 0; i < bf.size(); ++i) bf[i] = (uint32_t)p.tp_hi[i] | ((uint32_t)p.tp_lo[i] << 16);
-        if ((rc = upload(c, c->d_tpbf, bf.data(), bf.size() * sizeof(uint32_t), st))) return rc;
-        // the host vectors above must stay alive until the copies finish
-        if ((rc = hip_check(hipStreamSynchronize(st), "upload sync"))) return rc;
-        c->uploaded = true;
-    }
+    if (c->prepared) return SCFF_OK;
+    const Basis& b = c->basis;
+    PrepInputs in{};
+    in.shells = (const PrepShell*)c->d_shells.p;
+    in.sp = (const int4*)c->d_sp.p;
+    in.sp_cp = (const int*)c->d_sp_cp.p;
+    in.bf0 = (const int*)c->d_bf0.p;
+    in.cp_first = (const int*)c->d_cp_first.p;
+    in.cp_nterms = (const int*)c->d_cp_nterms.p;
+    in.xyz = (const double*)c->d_xyz.p;
+    in.exps = (const double*)c->d_exps.p;
+    in.coefs = (const double*)c->d_coefs.p;
+    in.n1d = (const double*)c->d_n1d.p;
+    in.cnorm = (const double*)c->d_cnorm.p;
+    in.T = (const double*)c->d_T.p;
+    in.nbf = b.nbf;
+    in.n_states = c->n_states;
+    in.n_sp = b.n_sp;
+    in.n_cp = b.n_cp;
+    in.n_rows_all = b.n_rows;
+    in.n_terms_all = b.n_terms;
+    in.eps = c->eps;
+    in.spin = c->spin;
+    PrepResult res;
+    int rc;
+    if ((rc = record(c, EV_PREP0, st))) return rc;
+    hipError_t e = run_prep(in, c->prep, res, st, [c](DeviceBuffer& buf, size_t n) { return dev_reserve_raw(c, buf, n); });
+    if (e != hipSuccess) return hip_check(e, "pair precompute");
+    if ((rc = record(c, EV_PREP1, st))) return rc;
+    c->ev_prep = c->timing;
+    c->pres = res;
+    c->prepared = true;
     return SCFF_OK;
 }
 
@@ -155,7 +176,7 @@ int validate_grid(const scff_grid* g) {
 
 // 1D tables for the grid axes
 int build_vtables(scff_ctx* c, const scff_grid* g, hipStream_t st) {
-    const int nrows = (int)c->packed.rows.size();
+    const int nrows = c->pres.n_rows;
     const int stride = vtable_stride(g->n);
     int rc = dev_reserve(c, c->d_vtab, (size_t)nrows * stride * sizeof(float2));
     if (rc) return rc;
@@ -163,32 +184,57 @@ int build_vtables(scff_ctx* c, const scff_grid* g, hipStream_t st) {
     for (int a = 0; a < 3; ++a) dq[a] = g->n[a] > 1 ? (g->qmax[a] - g->qmin[a]) / (g->n[a] - 1) : 0.0;
     c->vtab_rows = nrows;
     c->vtab_stride = stride;
-    return hip_check(launch_vtable((const VRowDev*)c->d_rows.p, nrows, stride, g->n, g->qmin, dq,
+    return hip_check(launch_vtable((const VRowDev*)c->prep.rows.p, nrows, stride, g->n, g->qmin, dq,
                                    (float2*)c->d_vtab.p, st),
                      "vtable kernel launch");
 }
 
-int set_device(scff_ctx* c) { return hip_check(hipSetDevice(c->device), "hipSetDevice"); }
+int check_precision(int precision) {
+    if (precision != SCFF_FP32 && precision != SCFF_BF16X3) return fail(SCFF_EINVAL, "unknown precision");
+    return SCFF_OK;
+}
+
+void free_all(scff_ctx* c) {
+    for (DeviceBuffer* b : {&c->d_shells, &c->d_sp, &c->d_sp_cp, &c->d_bf0, &c->d_cp_first, &c->d_cp_nterms,
+                            &c->d_xyz, &c->d_exps, &c->d_coefs, &c->d_n1d, &c->d_cnorm, &c->d_T, &c->d_vtab,
+                            &c->d_f, &c->d_f2, &c->d_q})
+        dev_free(c, *b);
+    PrepWork& w = c->prep;
+    for (DeviceBuffer* b : {&w.rows_all, &w.rowsum, &w.trow, &w.tbound, &w.wt, &w.cpmn, &w.tp64, &w.bsum,
+                            &w.part, &w.small, &w.nk, &w.nv, &w.vbase, &w.tmp, &w.key, &w.val, &w.vinfo,
+                            &w.tmp2, &w.cnpp, &w.csize, &w.coff, &w.tmp3, &w.slots, &w.tp32, &w.tpbf,
+                            &w.row_used, &w.newid, &w.tmp4, &w.rows})
+        dev_free(c, *b);
+}
+
+int copy_out(const float2* df, float* f, const float* df2, float* f2, size_t nout, hipStream_t st) {
+    int rc;
+    if (f && (rc = hip_check(hipMemcpyAsync(f, df, nout * sizeof(float2), hipMemcpyDeviceToHost, st), "D2H f")))
+        return rc;
+    if (f2 && (rc = hip_check(hipMemcpyAsync(f2, df2, nout * sizeof(float), hipMemcpyDeviceToHost, st), "D2H f2")))
+        return rc;
+    return SCFF_OK;
+}
 
 }  // namespace
 
-// Pack, upload and report the device bytes an evaluation on grid g will hold
-// (pair data, 1D tables and host-output staging for f and |f|^2).
+// Precompute a context's problem and report the device bytes an evaluation
+// on g holds in total (precompute buffers, 1D tables, output staging).
 int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, size_t* bytes_needed) {
     int rc = validate_grid(g);
     if (rc) return rc;
     if ((rc = set_device(c))) return rc;
-    if ((rc = ensure_packed(c, nullptr))) return rc;
+    if ((rc = ensure_prepared(c, nullptr))) return rc;
     const size_t npts = (size_t)g->n[0] * g->n[1] * g->n[2];
     const int stride = vtable_stride(g->n);
-    *bytes_needed = c->used + c->packed.rows.size() * (size_t)stride * sizeof(float2) +
+    *bytes_needed = c->used + (size_t)c->pres.n_rows * stride * sizeof(float2) +
                     npts * (size_t)c->n_states * (sizeof(float2) + sizeof(float));
     return ok();
 }
 
 extern "C" {
 
-const char* scff_version(void) { return "scarff-mi355x 0.1 (gfx950)"; }
+const char* scff_version(void) { return "scarff-mi355x 0.2 (gfx950)"; }
 
 const char* scff_last_error(void) { return g_err.c_str(); }
 
@@ -211,9 +257,9 @@ void scff_destroy(scff_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&c->d_rows, &c->d_terms, &c->d_coff, &c->d_cnpp, &c->d_tp, &c->d_tpbf,
-                      &c->d_vtab, &c->d_f, &c->d_f2, &c->d_q})
-        dev_free(c, *b);
+    free_all(c);
+    for (hipEvent_t& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -225,16 +271,24 @@ int scff_load_molecule(scff_ctx* c, int n_atoms, const double* xyz, int n_shells
     std::string err = build_basis(b, n_atoms, xyz, n_shells, shell_atom, shell_l, shell_nprim, exps,
                                   coefs, normalise);
     if (!err.empty()) return fail(SCFF_EINVAL, err);
-    PairData pd;
-    build_pairs(b, pd);
-    if (c->have_T && b.nbf != c->basis.nbf) {
-        c->have_T = false;
-        c->T.clear();
-    }
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    // upload the molecule tables (small host arrays)
+    if ((rc = upload_sync(c, c->d_shells, b.shells.data(), b.shells.size() * sizeof(PrepShell)))) return rc;
+    if ((rc = upload_sync(c, c->d_sp, b.sp.data(), b.sp.size() * sizeof(int)))) return rc;
+    if ((rc = upload_sync(c, c->d_sp_cp, b.sp_cp.data(), b.sp_cp.size() * sizeof(int)))) return rc;
+    if ((rc = upload_sync(c, c->d_bf0, b.sh_bf0.data(), b.sh_bf0.size() * sizeof(int)))) return rc;
+    if ((rc = upload_sync(c, c->d_cp_first, b.cp_first.data(), b.cp_first.size() * sizeof(int)))) return rc;
+    if ((rc = upload_sync(c, c->d_cp_nterms, b.cp_nterms.data(), b.cp_nterms.size() * sizeof(int)))) return rc;
+    if ((rc = upload_sync(c, c->d_xyz, b.xyz.data(), b.xyz.size() * sizeof(double)))) return rc;
+    if ((rc = upload_sync(c, c->d_exps, b.exps.data(), b.exps.size() * sizeof(double)))) return rc;
+    if ((rc = upload_sync(c, c->d_coefs, b.coefs.data(), b.coefs.size() * sizeof(double)))) return rc;
+    if ((rc = upload_sync(c, c->d_n1d, b.n1d.data(), b.n1d.size() * sizeof(double)))) return rc;
+    if ((rc = upload_sync(c, c->d_cnorm, b.cnorm.data(), b.cnorm.size() * sizeof(double)))) return rc;
+    if (c->have_T && b.nbf != c->basis.nbf) c->have_T = false;
     c->basis = std::move(b);
-    c->pairs = std::move(pd);
     c->have_mol = true;
-    c->packed_valid = false;
+    c->prepared = false;
     if (nbf_out) *nbf_out = c->basis.nbf;
     return ok();
 }
@@ -247,10 +301,31 @@ int scff_load_transitions(scff_ctx* c, int n_states, const double* T) {
     const size_t n = (size_t)n_states * c->basis.nbf * c->basis.nbf;
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(T[i])) return fail(SCFF_EINVAL, "non-finite entry in T");
-    c->T.assign(T, T + n);
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    if ((rc = upload_sync(c, c->d_T, T, n * sizeof(double)))) return rc;
     c->n_states = n_states;
     c->have_T = true;
-    c->packed_valid = false;
+    c->prepared = false;
+    return ok();
+}
+
+int scff_load_transitions_device(scff_ctx* c, int n_states, const double* T_dev, void* hip_stream) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (!c->have_mol) return fail(SCFF_ESTATE, "load a molecule before its transitions");
+    if (n_states < 1 || n_states > kMaxStates) return fail(SCFF_EINVAL, "n_states must be in 1..32");
+    if (!T_dev) return fail(SCFF_EINVAL, "T is NULL");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    const size_t n = (size_t)n_states * c->basis.nbf * c->basis.nbf;
+    if ((rc = dev_reserve(c, c->d_T, n * sizeof(double)))) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(c->d_T.p, T_dev, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                       (hipStream_t)hip_stream),
+                        "device copy of T")))
+        return rc;
+    c->n_states = n_states;
+    c->have_T = true;
+    c->prepared = false;
     return ok();
 }
 
@@ -259,7 +334,7 @@ int scff_set_options(scff_ctx* c, double screen_eps, double spin_factor) {
     if (!(screen_eps >= 0.0) || !std::isfinite(screen_eps) || screen_eps >= 1.0)
         return fail(SCFF_EINVAL, "screen_eps must be in [0, 1)");
     if (!std::isfinite(spin_factor)) return fail(SCFF_EINVAL, "spin_factor must be finite");
-    if (screen_eps != c->eps || spin_factor != c->spin) c->packed_valid = false;
+    if (screen_eps != c->eps || spin_factor != c->spin) c->prepared = false;
     c->eps = screen_eps;
     c->spin = spin_factor;
     return ok();
@@ -268,23 +343,19 @@ int scff_set_options(scff_ctx* c, double screen_eps, double spin_factor) {
 int scff_query(scff_ctx* c, scff_info* info) {
     if (!c || !info) return fail(SCFF_EINVAL, "NULL argument");
     std::memset(info, 0, sizeof(*info));
-    info->nbf = c->basis.nbf;
-    info->n_shells = c->basis.n_shells;
+    const Basis& b = c->basis;
+    info->nbf = b.nbf;
+    info->n_shells = b.n_shells;
     info->n_states = c->have_T ? c->n_states : 0;
-    info->shell_pairs_total = c->pairs.shell_pairs;
-    info->pairs_total = (long long)c->pairs.cps.size();
-    info->prim_pairs_total = c->pairs.prim_pairs_total;
-    if (c->have_mol && c->have_T && !c->packed_valid) {
-        Packed pk;
-        std::string err = pack(c->basis, c->pairs, c->n_states, c->T.data(), c->eps, c->spin, pk);
-        if (!err.empty()) return fail(SCFF_EINVAL, err);
-        c->packed = std::move(pk);
-        c->packed_valid = true;
-        c->uploaded = false;
-    }
-    if (c->packed_valid) {
-        info->pairs_kept = c->packed.pairs_kept;
-        info->prim_comp_pairs_kept = c->packed.terms_kept;
+    info->shell_pairs_total = b.n_sp;
+    info->pairs_total = b.n_cp;
+    info->prim_pairs_total = b.n_terms;
+    if (c->have_mol && c->have_T) {
+        int rc;
+        if ((rc = set_device(c))) return rc;
+        if ((rc = ensure_prepared(c, nullptr))) return rc;
+        info->pairs_kept = c->pres.pairs_kept;
+        info->prim_comp_pairs_kept = c->pres.terms_kept;
     }
     info->device_bytes = c->used;
     return ok();
@@ -295,13 +366,13 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
     if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
     int rc = validate_grid(g);
     if (rc) return rc;
-    if (precision != SCFF_FP32 && precision != SCFF_BF16X3) return fail(SCFF_EINVAL, "unknown precision");
+    if ((rc = check_precision(precision))) return rc;
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
-    if ((rc = ensure_packed(c, st))) return rc;
+    c->ev_prep = false;
+    if ((rc = ensure_prepared(c, st))) return rc;
     const size_t npts = (size_t)g->n[0] * g->n[1] * g->n[2];
     const size_t nout = npts * (size_t)c->n_states;
-    if ((rc = build_vtables(c, g, st))) return rc;
     float2* df = (float2*)f;
     float* df2 = f2;
     if (!out_on_device) {
@@ -310,20 +381,50 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
         df = f ? (float2*)c->d_f.p : nullptr;
         df2 = f2 ? (float*)c->d_f2.p : nullptr;
     }
-    const Packed& p = c->packed;
+    if ((rc = record(c, EV_VT0, st))) return rc;
+    if ((rc = build_vtables(c, g, st))) return rc;
+    if ((rc = record(c, EV_GRID0, st))) return rc;
+    const PrepResult& p = c->pres;
     rc = hip_check(launch_grid(p.state_blocks, precision, (const float2*)c->d_vtab.p, c->vtab_stride,
-                               (const int4*)c->d_terms.p, (const int*)c->d_coff.p,
-                               (const int*)c->d_cnpp.p, p.n_chunks, (const float*)c->d_tp.p,
-                               (const uint32_t*)c->d_tpbf.p, g->n, c->n_states, df, df2, st),
+                               (const int4*)c->prep.slots.p, (const int*)c->prep.coff.p,
+                               (const int*)c->prep.cnpp.p, p.n_chunks, (const float*)c->prep.tp32.p,
+                               (const uint32_t*)c->prep.tpbf.p, g->n, c->n_states, df, df2, st),
                    "grid kernel launch");
     if (rc) return rc;
+    if ((rc = record(c, EV_GRID1, st))) return rc;
+    c->ev_recorded = c->timing;
     if (!out_on_device) {
-        if (f && (rc = hip_check(hipMemcpyAsync(f, df, nout * sizeof(float2), hipMemcpyDeviceToHost, st), "D2H f")))
-            return rc;
-        if (f2 && (rc = hip_check(hipMemcpyAsync(f2, df2, nout * sizeof(float), hipMemcpyDeviceToHost, st), "D2H f2")))
-            return rc;
+        if ((rc = copy_out(df, f, df2, f2, nout, st))) return rc;
         if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
     }
+    return ok();
+}
+
+int scff_set_timing(scff_ctx* c, int enable) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    if (enable && !c->ev[0])
+        for (hipEvent_t& e : c->ev)
+            if ((rc = hip_check(hipEventCreate(&e), "hipEventCreate"))) return rc;
+    c->timing = enable != 0;
+    c->ev_recorded = false;
+    return ok();
+}
+
+int scff_last_timing(scff_ctx* c, float* prep_ms, float* vtable_ms, float* grid_ms) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (!c->timing || !c->ev_recorded) return fail(SCFF_ESTATE, "no timed evaluation recorded");
+    int rc;
+    if ((rc = hip_check(hipEventSynchronize(c->ev[EV_GRID1]), "event sync"))) return rc;
+    float a = 0.f, b = 0.f, p = 0.f;
+    if (c->ev_prep && (rc = hip_check(hipEventElapsedTime(&p, c->ev[EV_PREP0], c->ev[EV_PREP1]), "elapsed")))
+        return rc;
+    if ((rc = hip_check(hipEventElapsedTime(&a, c->ev[EV_VT0], c->ev[EV_GRID0]), "elapsed"))) return rc;
+    if ((rc = hip_check(hipEventElapsedTime(&b, c->ev[EV_GRID0], c->ev[EV_GRID1]), "elapsed"))) return rc;
+    if (prep_ms) *prep_ms = c->ev_prep ? p : 0.0f;
+    if (vtable_ms) *vtable_ms = a;
+    if (grid_ms) *grid_ms = b;
     return ok();
 }
 
@@ -332,14 +433,17 @@ int scff_eval_points(scff_ctx* c, int n_q, const double* q, int precision, float
     if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
     if (n_q < 1 || n_q > (1 << 24)) return fail(SCFF_EINVAL, "n_q must be in 1..2^24");
     if (!q) return fail(SCFF_EINVAL, "q is NULL");
-    if (precision != SCFF_FP32 && precision != SCFF_BF16X3) return fail(SCFF_EINVAL, "unknown precision");
+    int rc;
+    if ((rc = check_precision(precision))) return rc;
     for (int i = 0; i < 3 * n_q; ++i)
         if (!std::isfinite(q[i])) return fail(SCFF_EINVAL, "non-finite q");
-    int rc;
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
-    if ((rc = ensure_packed(c, st))) return rc;
-    if ((rc = upload(c, c->d_q, q, (size_t)n_q * 3 * sizeof(double), st))) return rc;
+    if ((rc = ensure_prepared(c, st))) return rc;
+    if ((rc = dev_reserve(c, c->d_q, (size_t)n_q * 3 * sizeof(double)))) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(c->d_q.p, q, (size_t)n_q * 3 * sizeof(double), hipMemcpyHostToDevice, st),
+                        "upload q")))
+        return rc;
     const size_t nout = (size_t)n_q * c->n_states;
     float2* df = (float2*)f;
     float* df2 = f2;
@@ -349,20 +453,15 @@ int scff_eval_points(scff_ctx* c, int n_q, const double* q, int precision, float
         df = f ? (float2*)c->d_f.p : nullptr;
         df2 = f2 ? (float*)c->d_f2.p : nullptr;
     }
-    const Packed& p = c->packed;
-    rc = hip_check(launch_points(p.state_blocks, (const VRowDev*)c->d_rows.p, (const int4*)c->d_terms.p,
-                                 (const int*)c->d_coff.p, (const int*)c->d_cnpp.p, p.n_chunks,
-                                 (const float*)c->d_tp.p, (const double*)c->d_q.p, n_q, c->n_states,
+    const PrepResult& p = c->pres;
+    rc = hip_check(launch_points(p.state_blocks, (const VRowDev*)c->prep.rows.p, (const int4*)c->prep.slots.p,
+                                 (const int*)c->prep.coff.p, (const int*)c->prep.cnpp.p, p.n_chunks,
+                                 (const float*)c->prep.tp32.p, (const double*)c->d_q.p, n_q, c->n_states,
                                  df, df2, st),
                    "points kernel launch");
     if (rc) return rc;
-    if (!out_on_device) {
-        if (f && (rc = hip_check(hipMemcpyAsync(f, df, nout * sizeof(float2), hipMemcpyDeviceToHost, st), "D2H f")))
-            return rc;
-        if (f2 && (rc = hip_check(hipMemcpyAsync(f2, df2, nout * sizeof(float), hipMemcpyDeviceToHost, st), "D2H f2")))
-            return rc;
-    }
-    // the uploaded q must outlive the kernel; the caller's q is host memory we copied from
+    if (!out_on_device && (rc = copy_out(df, f, df2, f2, nout, st))) return rc;
+    // the host q array was copied asynchronously: finish before returning
     if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
     return ok();
 }
@@ -374,24 +473,34 @@ int scff_export_vtensors(scff_ctx* c, const scff_grid* g, long long* n_terms_out
     if (rc) return rc;
     if ((rc = set_device(c))) return rc;
     hipStream_t st = nullptr;
-    if ((rc = ensure_packed(c, st))) return rc;
-    const Packed& p = c->packed;
+    if ((rc = ensure_prepared(c, st))) return rc;
+    const PrepResult& p = c->pres;
     *n_terms_out = p.terms_kept;
     if (!vx && !vy && !vz && !tp) return ok();
     if ((rc = build_vtables(c, g, st))) return rc;
-    std::vector<float2> V((size_t)c->vtab_rows * c->vtab_stride);
-    if ((rc = hip_check(hipMemcpyAsync(V.data(), c->d_vtab.p, V.size() * sizeof(float2), hipMemcpyDeviceToHost, st),
-                        "D2H vtab")))
-        return rc;
-    if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
     const int SW = kStateBlock * p.state_blocks;
+    std::vector<float2> V((size_t)c->vtab_rows * c->vtab_stride);
+    std::vector<int> slots((size_t)p.n_slots * 4), coff(p.n_chunks), cnpp(p.n_chunks);
+    std::vector<float> tp32((size_t)p.n_vpairs * SW);
+    struct Cp {
+        void* dst;
+        const void* src;
+        size_t n;
+    } cps[] = {{V.data(), c->d_vtab.p, V.size() * sizeof(float2)},
+               {slots.data(), c->prep.slots.p, slots.size() * sizeof(int)},
+               {coff.data(), c->prep.coff.p, coff.size() * sizeof(int)},
+               {cnpp.data(), c->prep.cnpp.p, cnpp.size() * sizeof(int)},
+               {tp32.data(), c->prep.tp32.p, tp32.size() * sizeof(float)}};
+    for (const Cp& x : cps)
+        if ((rc = hip_check(hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, st), "D2H export"))) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
     long long t = 0;
     float* outs[3] = {vx, vy, vz};
     for (int ch = 0; ch < p.n_chunks; ++ch) {
-        const int npp = p.chunk_npp[ch];
+        const int npp = cnpp[ch];
         for (int j = 0; j < kChunk; ++j)
             for (int k = 0; k < npp; ++k) {
-                const int* tr = &p.terms[4 * ((size_t)p.chunk_off[ch] + (size_t)j * npp + k)];
+                const int* tr = &slots[4 * ((size_t)coff[ch] + (size_t)j * npp + k)];
                 if (!tr[3]) continue;
                 for (int a = 0; a < 3; ++a) {
                     if (!outs[a]) continue;
@@ -403,8 +512,8 @@ int scff_export_vtensors(scff_ctx* c, const scff_grid* g, long long* n_terms_out
                     }
                 }
                 if (tp)
-                    for (int s = 0; s < p.n_states; ++s)
-                        tp[(size_t)s * p.terms_kept + t] = p.tp[(size_t)(ch * kChunk + j) * SW + s];
+                    for (int s = 0; s < c->n_states; ++s)
+                        tp[(size_t)s * p.terms_kept + t] = tp32[(size_t)(ch * kChunk + j) * SW + s];
                 ++t;
             }
     }
