@@ -223,13 +223,16 @@ typedef struct {
     long long submitted, completed, failed, cancelled;
     long long queued, inflight;
     size_t admitted_bytes, budget_bytes, peak_admitted_bytes;
+    long long peak_inflight;
 } scff_server_stats;
 
 /* Create a server on `device`.  Requests are admitted while the device
  * bytes of all in-flight requests fit `hbm_budget_bytes` (0 = 64 GiB) and at
  * most `max_inflight` requests run at once (1..64).  Requests that do not
  * fit wait in FIFO order.  A request larger than the whole budget fails
- * with SCFF_ENOMEM. */
+ * with SCFF_ENOMEM.  device = -1 selects a scheduler test mode that touches
+ * no GPU: requests are validated, admitted and completed exactly as above,
+ * but nothing is computed and their outputs are left untouched. */
 int scff_server_create(int device, size_t hbm_budget_bytes, int max_inflight,
                        scff_server** out);
 

@@ -60,7 +60,7 @@ class scff_server_stats(ctypes.Structure):
     _fields_ = [("submitted", c_longlong), ("completed", c_longlong), ("failed", c_longlong),
                 ("cancelled", c_longlong), ("queued", c_longlong), ("inflight", c_longlong),
                 ("admitted_bytes", c_size_t), ("budget_bytes", c_size_t),
-                ("peak_admitted_bytes", c_size_t)]
+                ("peak_admitted_bytes", c_size_t), ("peak_inflight", c_longlong)]
 
 
 def _fn(name, res, args):
@@ -250,3 +250,79 @@ class Context:
         check(scff_export_vtensors(self._h, ctypes.byref(g), ctypes.byref(nt), vs[0].ctypes.data,
                                    vs[1].ctypes.data, vs[2].ctypes.data, tp.ctypes.data))
         return [v.view(np.complex64)[..., 0] for v in vs], tp
+
+
+class Server:
+    """Continuous-batching request server (scff_server_*).  device = -1 is the
+    scheduler test mode (no GPU work; outputs are left untouched)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 4):
+        h = c_void_p()
+        check(scff_server_create(int(device), int(hbm_budget_bytes), int(max_inflight), ctypes.byref(h)))
+        self._h = h
+        self._outs = {}
+
+    def submit(self, mol, T, grid, precision="fp32", screen_eps=0.0, spin_factor=1.0,
+               want_f=True, want_f2=True, normalise=True, precision_code=None) -> int:
+        T = np.ascontiguousarray(T, np.float64)
+        if T.ndim == 2:
+            T = T[None]
+        arrs = [np.ascontiguousarray(mol.xyz, np.float64), np.ascontiguousarray(mol.shell_atom, np.int32),
+                np.ascontiguousarray(mol.shell_l, np.int32), np.ascontiguousarray(mol.shell_nprim, np.int32),
+                np.ascontiguousarray(mol.exps, np.float64), np.ascontiguousarray(mol.coefs, np.float64)]
+        shape = (T.shape[0],) + tuple(grid.n)
+        f = np.zeros(shape + (2,), np.float32) if want_f else None
+        f2 = np.zeros(shape, np.float32) if want_f2 else None
+        r = scff_request()
+        r.n_atoms = arrs[0].shape[0]
+        r.xyz_bohr = _d(arrs[0])
+        r.n_shells = arrs[2].shape[0]
+        r.shell_atom, r.shell_l, r.shell_nprim = _i(arrs[1]), _i(arrs[2]), _i(arrs[3])
+        r.exps, r.coefs = _d(arrs[4]), _d(arrs[5])
+        r.normalise = int(bool(normalise))
+        r.n_states = T.shape[0]
+        r.T = _d(T)
+        r.grid = make_grid(grid.n, grid.qmin, grid.qmax)
+        r.precision = PRECISIONS[precision] if precision_code is None else int(precision_code)
+        r.screen_eps = float(screen_eps)
+        r.spin_factor = float(spin_factor)
+        r.f = f.ctypes.data_as(P(c_float)) if f is not None else None
+        r.f2 = f2.ctypes.data_as(P(c_float)) if f2 is not None else None
+        t = c_ulonglong()
+        check(scff_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._outs[t.value] = (f, f2)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ns: int = -1):
+        """(status, latency_ns, f complex64 or None, f2 or None); raises ScffError(SCFF_EBUSY) on timeout."""
+        status, lat = c_int(), c_longlong()
+        check(scff_server_wait(self._h, c_ulonglong(ticket), c_longlong(timeout_ns), ctypes.byref(status),
+                               ctypes.byref(lat)))
+        f, f2 = self._outs.pop(ticket, (None, None))
+        fc = f.view(np.complex64)[..., 0] if f is not None else None
+        return status.value, lat.value, fc, f2
+
+    def cancel(self, ticket: int):
+        check(scff_server_cancel(self._h, c_ulonglong(ticket)))
+
+    def stats(self) -> dict:
+        st = scff_server_stats()
+        check(scff_server_stats_get(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in scff_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            scff_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -53,6 +53,7 @@ struct Req {
     St state = St::Queued;
     int status = SCFF_OK;
     bool waited = false;
+    int queue_refs = 0;   // prep_q / admit_q entries still naming this ticket
     Clock::time_point t_submit, t_done;
 };
 
@@ -71,7 +72,7 @@ struct scff_server {
     std::map<unsigned long long, std::unique_ptr<Req>> reqs;
     unsigned long long next_ticket = 1;
     size_t admitted = 0, peak_admitted = 0;
-    int inflight = 0;
+    int inflight = 0, peak_inflight = 0;
     long long n_submitted = 0, n_completed = 0, n_failed = 0, n_cancelled = 0;
     bool stop = false;
     std::vector<std::thread> threads;
@@ -82,6 +83,19 @@ namespace {
 int sfail(int code, const std::string& m) {
     scff::set_error(m);
     return code;
+}
+
+// caller holds s->mu: drop one queue reference; erase a request that was
+// already handed back to its waiter and is no longer queued anywhere
+void unref(scff_server* s, unsigned long long t) {
+    auto it = s->reqs.find(t);
+    if (it == s->reqs.end()) return;
+    if (--it->second->queue_refs <= 0 && it->second->waited) s->reqs.erase(it);
+}
+
+Req* lookup(scff_server* s, unsigned long long t) {
+    auto it = s->reqs.find(t);
+    return it == s->reqs.end() ? nullptr : it->second.get();
 }
 
 void finish(scff_server* s, Req* r, int status) {
@@ -106,22 +120,38 @@ void prep_loop(scff_server* s) {
             if (s->stop) return;
             t = s->prep_q.front();
             s->prep_q.pop_front();
-            r = s->reqs[t].get();
-            if (r->state == St::Cancelled) continue;
+            r = lookup(s, t);
+            if (!r) continue;
+            if (r->state == St::Cancelled) {
+                unref(s, t);
+                continue;
+            }
+            ++r->queue_refs;   // held while prep runs unlocked
         }
         int rc = SCFF_OK;
         size_t bytes = 0;
         scff_ctx* c = nullptr;
         std::string err;
-        if (!s->fake) {
-            rc = scff_create(s->device, 0, &c);
-        } else {
-            rc = SCFF_OK;
+        // validation common to both modes (host only)
+        {
+            scff::Basis bchk;
+            std::string e2 = scff::build_basis(bchk, r->n_atoms, r->xyz.data(), r->n_shells, r->sh_atom.data(),
+                                               r->sh_l.data(), r->sh_nprim.data(), r->exps.data(),
+                                               r->coefs.data(), r->normalise);
+            if (e2.empty() && r->precision != SCFF_FP32 && r->precision != SCFF_BF16X3) e2 = "unknown precision";
+            for (int a = 0; e2.empty() && a < 3; ++a)
+                if (r->grid.n[a] < 1 || r->grid.n[a] > 4096) e2 = "grid n must be in 1..4096";
+            if (!e2.empty()) {
+                rc = SCFF_EINVAL;
+                scff::set_error(e2);
+            }
         }
         if (rc == SCFF_OK && !s->fake) {
-            rc = scff_load_molecule(c, r->n_atoms, r->xyz.data(), r->n_shells, r->sh_atom.data(),
-                                    r->sh_l.data(), r->sh_nprim.data(), r->exps.data(), r->coefs.data(),
-                                    r->normalise, nullptr);
+            rc = scff_create(s->device, 0, &c);
+            if (rc == SCFF_OK)
+                rc = scff_load_molecule(c, r->n_atoms, r->xyz.data(), r->n_shells, r->sh_atom.data(),
+                                        r->sh_l.data(), r->sh_nprim.data(), r->exps.data(), r->coefs.data(),
+                                        r->normalise, nullptr);
             if (rc == SCFF_OK) rc = scff_load_transitions(c, r->n_states, r->T.data());
             if (rc == SCFF_OK) rc = scff_set_options(c, r->eps, r->spin);
             if (rc == SCFF_OK) rc = scff::ctx_prepare(c, &r->grid, &bytes);
@@ -138,9 +168,10 @@ void prep_loop(scff_server* s) {
             for (auto it = s->admit_q.begin(); it != s->admit_q.end(); ++it)
                 if (*it == t) {
                     s->admit_q.erase(it);
+                    unref(s, t);
                     break;
                 }
-            finish(s, r, rc);
+            if (r->state != St::Cancelled) finish(s, r, rc);
         } else if (r->state == St::Cancelled) {
             if (c) scff_destroy(c);
         } else {
@@ -148,6 +179,8 @@ void prep_loop(scff_server* s) {
             r->bytes = bytes;
             r->state = St::Ready;
         }
+        unref(s, t);   // the prep reference
+        unref(s, t);   // the prep_q entry
         s->cv_sched.notify_all();
     }
 }
@@ -159,20 +192,17 @@ void sched_loop(scff_server* s) {
         bool progressed = false;
         while (!s->admit_q.empty()) {
             const unsigned long long t = s->admit_q.front();
-            Req* r = s->reqs[t].get();
-            if (r->state == St::Cancelled) {
+            Req* r = lookup(s, t);
+            if (!r || r->state == St::Cancelled || r->state == St::Done) {   // cancelled / failed in prep
                 s->admit_q.pop_front();
-                progressed = true;
-                continue;
-            }
-            if (r->state == St::Done) {   // failed in prep
-                s->admit_q.pop_front();
+                unref(s, t);
                 progressed = true;
                 continue;
             }
             if (r->state != St::Ready) break;                 // head not prepared yet
             if (r->bytes > s->budget) {                       // can never fit
                 s->admit_q.pop_front();
+                unref(s, t);
                 if (r->ctx) scff_destroy(r->ctx);
                 r->ctx = nullptr;
                 scff::set_error("request footprint exceeds the server's HBM budget");
@@ -182,10 +212,12 @@ void sched_loop(scff_server* s) {
             }
             if (s->inflight >= s->max_inflight || s->admitted + r->bytes > s->budget) break;
             s->admit_q.pop_front();
+            unref(s, t);
             r->state = St::Running;
             s->admitted += r->bytes;
             if (s->admitted > s->peak_admitted) s->peak_admitted = s->admitted;
             ++s->inflight;
+            if (s->inflight > s->peak_inflight) s->peak_inflight = s->inflight;
             s->run_q.push_back(t);
             s->cv_run.notify_one();
             progressed = true;
@@ -206,8 +238,9 @@ void run_loop(scff_server* s) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_run.wait(lk, [&] { return s->stop || !s->run_q.empty(); });
             if (s->stop && s->run_q.empty()) break;
-            r = s->reqs[s->run_q.front()].get();
+            r = lookup(s, s->run_q.front());
             s->run_q.pop_front();
+            if (!r) continue;
         }
         int rc = SCFF_OK;
         std::string err;
@@ -297,6 +330,7 @@ int scff_server_submit(scff_server* s, const scff_request* q, unsigned long long
     std::lock_guard<std::mutex> lk(s->mu);
     const unsigned long long t = s->next_ticket++;
     r->ticket = t;
+    r->queue_refs = 2;   // prep_q + admit_q
     s->reqs[t] = std::move(r);
     s->prep_q.push_back(t);
     s->admit_q.push_back(t);
@@ -322,7 +356,8 @@ int scff_server_wait(scff_server* s, unsigned long long ticket, long long timeou
     if (status) *status = st;
     if (latency_ns)
         *latency_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_done - r->t_submit).count();
-    s->reqs.erase(it);
+    r->waited = true;
+    if (r->queue_refs <= 0) s->reqs.erase(it);
     return SCFF_OK;
 }
 
@@ -357,6 +392,7 @@ int scff_server_stats_get(scff_server* s, scff_server_stats* o) {
     o->admitted_bytes = s->admitted;
     o->budget_bytes = s->budget;
     o->peak_admitted_bytes = s->peak_admitted;
+    o->peak_inflight = s->peak_inflight;
     return SCFF_OK;
 }
 

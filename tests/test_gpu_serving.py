@@ -1,0 +1,65 @@
+"""Serving on the GPU: requests admitted while others run, overlapping on the
+device; every result is the same alone and in the mix, and matches the oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workload as wl
+from tests.metrics import TOL_F2, errors
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def requests(seed, n):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        n_heavy = int(rng.integers(2, 9))
+        mol = wl.make_molecule(rng, n_heavy, int(round(0.8 * n_heavy)), layout="box",
+                               box_A=12.0 * (n_heavy / 30.0) ** (1 / 3) + 1.0)
+        ns = int(rng.integers(1, 25))
+        N = int(rng.integers(16, 41))
+        qm = float(rng.uniform(5.0, 8.0))
+        T = wl.make_transitions(rng, mol.nbf, wl.n_occupied(mol.Z), ns)
+        out.append((mol, T, wl.Grid(n=(N, N + 1, N - 1), qmin=(-qm,) * 3, qmax=(qm,) * 3)))
+    return out
+
+
+def test_alone_vs_mix_identical_and_correct(oracle_mod):
+    import torch  # noqa: F401
+    from paper_2512_18010_amd import binding
+    reqs = requests(2024, 8)
+    alone = []
+    with binding.Server(0, 0, max_inflight=4) as srv:
+        for k, (mol, T, g) in enumerate(reqs):
+            log(f"alone {k}: nbf={mol.nbf} states={T.shape[0]} grid={g.n}")
+            t = srv.submit(mol, T, g, screen_eps=1e-9)
+            status, lat, f, f2 = srv.wait(t)
+            assert status == binding.SCFF_OK
+            alone.append((f.copy(), f2.copy()))
+        log("mix: submitting all")
+        tickets = [srv.submit(mol, T, g, screen_eps=1e-9) for (mol, T, g) in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    log("stats", st)
+    assert st["peak_inflight"] >= 2, "requests should overlap on the device"
+    for k, ((fa, f2a), (status, lat, fm, f2m)) in enumerate(zip(alone, mixed)):
+        assert status == binding.SCFF_OK
+        assert np.array_equal(fa, fm) and np.array_equal(f2a, f2m), f"request {k} differs alone vs mix"
+    # correctness of two of them against the oracle on sampled points
+    for k in (0, 3):
+        mol, T, g = reqs[k]
+        idx = wl.sample_grid_indices(g, 40, seed=k)
+        idx = np.unique(np.concatenate([idx, alone[k][1].reshape(T.shape[0], -1).argmax(axis=1)]))
+        ref = oracle_mod.eval_points(mol, T, g.points()[idx], n_threads=min(16, os.cpu_count() or 1))
+        f = alone[k][0].reshape(T.shape[0], -1)[:, idx]
+        e = errors(f, ref)
+        log(f"request {k}: peak-normalised |f|^2 error {e['f2_peak_norm'].max():.3e}")
+        assert e["f2_peak_norm"].max() <= TOL_F2["fp32"]
