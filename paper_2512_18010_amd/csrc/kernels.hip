@@ -80,17 +80,30 @@ __global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int v
 // Workgroup = 4 waves, tile = 4 qx x 8 qy lines x TZ qz (TZ = 4*QZL).
 // Per chunk of 8 component pairs with npp terms each (npp <= 9), for every
 // term t (index ptl = pair*npp + term):
-//   raw slices  Vx[t][4], Vy[t][8], Vz[t][TZ]   global -> registers -> LDS
+//   raw slices  Vx[t][4], Vy[t][8], Vz[t][TZ]   global -> LDS by direct DMA
 //   W[t][line] = Vx * Vy                        cooperative, in LDS
-// plus the chunk's packed weights Tp[8][16*SB] (LDS).  Thread tid always
-// loads slice `part = tid & 15` of terms ptl = tid/16 + 16j, so no per-item
-// index arithmetic is needed.  The loads of chunk c+1 are issued before the
-// W phase of chunk c and complete under its arithmetic.
+// plus the chunk's packed weights Tp[8][16*SB] (DMA as well).  The raw
+// buffers are double-buffered: the DMA for chunk c+1 is issued at the start
+// of chunk c and completes under chunk c's W phase and main loop; the row
+// ids it needs were loaded one chunk earlier.  Thread tid always moves slice
+// `part = tid & 15` of terms ptl = tid/16 + 16j, so the LDS destination of a
+// wave's DMA is contiguous (lane * 16 bytes), as the instruction requires.
 // Lane (kk, ln): pair kk of the current MFMA k-step, 2 lines x QZL qz.
 
 constexpr int kTiles = 4;      // chunks (32 pairs) per FP64 fold of the MFMA sums
 constexpr int kWStride = 34;   // float2 per term row of W (32 lines + pad)
 constexpr int kNPT = kChunk * kMaxTermsPerPair;   // 72 terms per chunk at most
+constexpr int kParts = 16;     // float4 slices per term row of the raw buffer
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// LDS-only barrier: prior LDS reads/writes of this wave complete, DMA may
+// still be in flight.
+__device__ __forceinline__ void barrier_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// Full barrier: this wave's DMA into LDS has landed as well.
+__device__ __forceinline__ void barrier_dma() {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 template <int SB, int QZL, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
@@ -99,22 +112,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const float* __restrict__ Tp, int3 n, int3 ntiles, int n_states, float2* __restrict__ f,
     float* __restrict__ f2) {
     constexpr int TZ = 4 * QZL;
-    constexpr int ZSTRIDE = TZ + 2;    // float2 per term row of Z
     constexpr int ZPARTS = TZ / 2;     // float4 slices of a Z row
     constexpr int SLOTS = 2 * QZL;     // q values per lane
     constexpr int SW = 16 * SB;        // padded state count
-    constexpr int NJ = (kNPT + 15) / 16;       // terms per slice-thread
-    constexpr int TPF4 = kChunk * SW / 4;      // float4 of Tp per chunk
-    static_assert(2 + 4 + ZPARTS <= 16, "slices per term");
+    constexpr int NJ = (kNPT + 15) / 16;       // term groups per slice-thread (5)
+    constexpr int TPF4 = kChunk * SW / 4;      // float4 of Tp per chunk (32 or 64)
+    static_assert(2 + 4 + ZPARTS <= kParts, "slices per term");
+    static_assert(TPF4 <= 64, "Tp block per chunk fits one wave");
 
-    __shared__ __align__(16) float2 Xr[kNPT * 4];
-    __shared__ __align__(16) float2 Yr[kNPT * 8];
-    __shared__ __align__(16) float2 Zr[kNPT * ZSTRIDE];
+    __shared__ __align__(16) float4 R0[kNPT * kParts];
+    __shared__ __align__(16) float4 R1[kNPT * kParts];
+    __shared__ __align__(16) float T0[kChunk * SW];
+    __shared__ __align__(16) float T1[kChunk * SW];
     __shared__ __align__(16) float2 Wl[kNPT * kWStride];
-    __shared__ __align__(16) float Tpl[kChunk * SW];
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int kk = lane >> 4;          // pair within an MFMA k-step
     const int ln = lane & 15;          // MFMA column (q) / A-row (state) index
@@ -128,49 +141,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const int tx = b / ntiles.y;
     const int qx0 = tx * 4, qy0 = ty * 8, qz0 = tz * TZ;
 
-    // ---- this thread's slice: axis, offset in the table row, LDS row layout
+    // ---- this thread's slice: axis and offset of its 16 bytes in a table row
     const int part = tid & 15;
     const int pt0 = tid >> 4;
-    int axis, qoff, lds_stride, lds_off;   // LDS in float4 units
-    float4* lds_base;
+    int axis, qoff;
     if (part < 2) {
-        axis = 0; qoff = qx0 + 2 * part; lds_base = reinterpret_cast<float4*>(Xr); lds_stride = 2; lds_off = part;
+        axis = 0; qoff = qx0 + 2 * part;
     } else if (part < 6) {
-        axis = 1; qoff = qy0 + 2 * (part - 2); lds_base = reinterpret_cast<float4*>(Yr); lds_stride = 4; lds_off = part - 2;
+        axis = 1; qoff = qy0 + 2 * (part - 2);
     } else {
-        const int zp = min(part - 6, ZPARTS - 1);   // idle slices re-read the last Z slice
-        axis = 2; qoff = qz0 + 2 * zp; lds_base = reinterpret_cast<float4*>(Zr); lds_stride = ZSTRIDE / 2; lds_off = zp;
+        axis = 2; qoff = qz0 + 2 * min(part - 6, ZPARTS - 1);   // idle slices re-read a valid Z slice
     }
-    const bool slice_active = part < 6 + ZPARTS;
 
-    float4 pf[NJ];
-    float4 pf_tp;
-    int npp_next = 0;
-
-    // Branch-free: every lane issues all its loads (clamped to valid
-    // addresses) so they are in flight together; only the LDS stores are
-    // masked.  Row ids are loaded first, then all slice loads.
-    auto load_chunk = [&](int c) {
-        const int npp = chunk_npp[c];
-        const int nptl = kChunk * npp;
+    // row ids of the slices of chunk c (loaded one chunk ahead of the DMA)
+    int rid[NJ];
+    auto load_rows = [&](int c) {
+        const int nptl = kChunk * chunk_npp[c];
         const int* tc = reinterpret_cast<const int*>(terms + chunk_off[c]);
-        int row[NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) row[j] = tc[4 * min(pt0 + 16 * j, nptl - 1) + axis];
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            pf[j] = *reinterpret_cast<const float4*>(V + (size_t)row[j] * vstride + qoff);
-        pf_tp = reinterpret_cast<const float4*>(Tp + (size_t)c * kChunk * SW)[tid % TPF4];
-        npp_next = npp;
+        for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(pt0 + 16 * j, nptl - 1) + axis];
     };
-    auto store_chunk = [&]() {
-        const int nptl = kChunk * npp_next;
+    // DMA of chunk c's raw slices and Tp block into buffer (R, T)
+    auto issue_dma = [&](int c, float4* R, float* T) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const int ptl = pt0 + 16 * j;
-            if (slice_active && ptl < nptl) lds_base[ptl * lds_stride + lds_off] = pf[j];
+            // wave w of term group j covers terms 16j + 4w .. 16j + 4w + 3
+            if (16 * j + 4 * wave < kNPT) {
+                const float2* src = V + (size_t)rid[j] * vstride + qoff;
+                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)(R + (16 * j + 4 * wave) * kParts), 16, 0, 0);
+            }
         }
-        if (tid < TPF4) reinterpret_cast<float4*>(Tpl)[tid] = pf_tp;
+        if (wave == 0 && lane < TPF4) {
+            const float* src = Tp + (size_t)c * kChunk * SW + 4 * lane;
+            __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)T, 16, 0, 0);
+        }
     };
 
     floatx4 acc_r[SB][SLOTS], acc_i[SB][SLOTS];
@@ -185,18 +189,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             for (int i = 0; i < 4; ++i) tot_r[sb][s][i] = tot_i[sb][s][i] = 0.0;
         }
 
-    if (n_chunks > 0) load_chunk(0);
-    for (int c = 0; c < n_chunks; ++c) {
-        const int npp = npp_next;
-        __syncthreads();                       // previous chunk done with LDS
-        store_chunk();
-        __syncthreads();
-        if (c + 1 < n_chunks) load_chunk(c + 1);
+    auto chunk_body = [&](int c, const float4* R, const float* T) {
+        const int npp = chunk_npp[c];
         // W = Vx * Vy: item = (term, qx) -> 8 lines
         for (int i = tid; i < kChunk * npp * 4; i += 256) {
             const int ptl = i >> 2, xq = i & 3;
-            const float2 vx = Xr[ptl * 4 + xq];
-            const float4* yr = reinterpret_cast<const float4*>(Yr + ptl * 8);
+            const float2 vx = reinterpret_cast<const float2*>(R + ptl * kParts)[xq];
+            const float4* yr = R + ptl * kParts + 2;
             float4* wd = reinterpret_cast<float4*>(Wl + ptl * kWStride + xq * 8);
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
@@ -205,25 +204,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
                                     vx.x * y.z - vx.y * y.w, vx.x * y.w + vx.y * y.z);
             }
         }
-        __syncthreads();
-
+        barrier_lds();
 #pragma unroll
         for (int step = 0; step < kChunk / 4; ++step) {
             const int pair = step * 4 + kk;
             float a_op[SB];
 #pragma unroll
-            for (int sb = 0; sb < SB; ++sb) a_op[sb] = Tpl[pair * SW + sb * 16 + ln];
+            for (int sb = 0; sb < SB; ++sb) a_op[sb] = T[pair * SW + sb * 16 + ln];
             float gr[SLOTS], gi[SLOTS];
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) gr[s] = gi[s] = 0.f;
             const float2* wp = Wl + (pair * npp) * kWStride + wave * 8 + 2 * lpair;
-            const float2* zp = Zr + (pair * npp) * ZSTRIDE + zgrp * QZL;
+            const float2* zp = reinterpret_cast<const float2*>(R + (pair * npp) * kParts + 6) + zgrp * QZL;
             for (int t = 0; t < npp; ++t) {
                 const float4 w = *reinterpret_cast<const float4*>(wp + t * kWStride);
                 float2 z[QZL];
 #pragma unroll
                 for (int j = 0; j < QZL; j += 2) {
-                    const float4 zz = *reinterpret_cast<const float4*>(zp + t * ZSTRIDE + j);
+                    const float4 zz = *reinterpret_cast<const float4*>(zp + t * (2 * kParts) + j);
                     z[j] = make_float2(zz.x, zz.y);
                     z[j + 1] = make_float2(zz.z, zz.w);
                 }
@@ -262,6 +260,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
                     acc_i[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
         }
+    };
+
+    if (n_chunks > 0) {
+        load_rows(0);
+        issue_dma(0, R0, T0);
+        if (n_chunks > 1) load_rows(1);
+    }
+    // two chunks per iteration so each buffer is a distinct LDS object
+    for (int c = 0; c < n_chunks; c += 2) {
+        barrier_dma();                                  // chunk c landed in R0/T0; Wl and R1 are free
+        if (c + 1 < n_chunks) {
+            issue_dma(c + 1, R1, T1);
+            if (c + 2 < n_chunks) load_rows(c + 2);
+        }
+        chunk_body(c, R0, T0);
+        if (c + 1 >= n_chunks) break;
+        barrier_dma();                                  // chunk c+1 landed in R1/T1; Wl and R0 are free
+        if (c + 2 < n_chunks) {
+            issue_dma(c + 2, R0, T0);
+            if (c + 3 < n_chunks) load_rows(c + 3);
+        }
+        chunk_body(c + 1, R1, T1);
     }
 
     // epilogue: lane holds states sb*16 + 4*kk + i for the q values of column ln

@@ -191,24 +191,40 @@ __global__ void terms_kernel(const PrepShell* __restrict__ sh, const int4* __res
 }
 
 __global__ void tot_kernel(const double* __restrict__ part, int nsp, int ns, double* __restrict__ tot) {
-    // one block; thread st sums its column in fixed order, 4 partial chains
-    for (int st = threadIdx.x; st < ns; st += blockDim.x) {
-        double a[4] = {0, 0, 0, 0};
-        for (int i = 0; i < nsp; ++i) a[i & 3] += part[(size_t)i * ns + st];
-        tot[st] = (a[0] + a[1]) + (a[2] + a[3]);
+    // one block of 256 threads per state: fixed-order strided partial sums,
+    // then a fixed-shape tree (deterministic)
+    __shared__ double red[256];
+    for (int st = blockIdx.x; st < ns; st += gridDim.x) {
+        double a = 0.0;
+        for (int i = threadIdx.x; i < nsp; i += blockDim.x) a += part[(size_t)i * ns + st];
+        red[threadIdx.x] = a;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tot[st] = red[0];
+        __syncthreads();
+    }
+}
+
+// per component pair: m_k = max_s |Tp(s,k)| / tot_s
+__global__ void pairmax_kernel(const double* __restrict__ tp64, const double* __restrict__ tot, int ns, int ncp,
+                               double* __restrict__ mk) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ncp; k += gridDim.x * blockDim.x) {
+        double m = 0.0;
+        for (int st = 0; st < ns; ++st)
+            if (tot[st] > 0.0) m = fmax(m, fabs(tp64[(size_t)k * ns + st]) / tot[st]);
+        mk[k] = m;
     }
 }
 
 __global__ void weight_kernel(const int4* __restrict__ trow, const double* __restrict__ tbound,
-                              const double* __restrict__ tp64, const double* __restrict__ tot, int ns,
-                              long long nterms, double* __restrict__ w, unsigned int* __restrict__ hist) {
+                              const double* __restrict__ mk, long long nterms, double* __restrict__ w,
+                              unsigned int* __restrict__ hist) {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nterms;
          t += (long long)gridDim.x * blockDim.x) {
-        const int cp = trow[t].w;
-        double mk = 0.0;
-        for (int st = 0; st < ns; ++st)
-            if (tot[st] > 0.0) mk = fmax(mk, fabs(tp64[(size_t)cp * ns + st]) / tot[st]);
-        const double x = mk * tbound[t];
+        const double x = mk[trow[t].w] * tbound[t];
         w[t] = x;
         if (x > 0.0) {
             int e;
@@ -220,21 +236,28 @@ __global__ void weight_kernel(const int4* __restrict__ trow, const double* __res
 }
 
 __global__ void thresh_kernel(const unsigned int* __restrict__ hist, double eps, double* __restrict__ thr) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (!(eps > 0.0)) {
-        thr[0] = -1.0;   // no screening: keep every term, zero or not
-        return;
+    // one wave: per-bin upper bounds, an inclusive prefix sum in fixed order,
+    // then the last bin whose prefix stays <= eps
+    __shared__ double pre[kHistBins];
+    const int lane = threadIdx.x;
+    for (int b = lane; b < kHistBins; b += blockDim.x) pre[b] = (double)hist[b] * ldexp(1.0, b - kHistBias);
+    __syncthreads();
+    if (lane == 0) {
+        if (!(eps > 0.0)) {
+            thr[0] = -1.0;   // no screening: keep every term, zero or not
+            return;
+        }
+        double sum = 0.0;
+        int best = -1;   // drop terms whose exponent bin is <= best
+        for (int b = 0; b < kHistBins; ++b) {
+            if (hist[b] == 0) continue;
+            if (sum + pre[b] > eps) break;
+            sum += pre[b];
+            best = b;
+        }
+        // w < 2^(best - bias) exactly when its frexp exponent bin is <= best
+        thr[0] = best < 0 ? 0.0 : ldexp(1.0, best - kHistBias);
     }
-    double sum = 0.0;
-    int best = -1;   // bin index: drop terms with exponent bin <= best
-    for (int b = 0; b < kHistBins; ++b) {
-        const double add = (double)hist[b] * ldexp(1.0, b - kHistBias);
-        if (sum + add > eps) break;
-        sum += add;
-        best = b;
-    }
-    // w < 2^(best - bias) exactly when its frexp exponent bin is <= best
-    thr[0] = best < 0 ? 0.0 : ldexp(1.0, best - kHistBias);
 }
 
 __device__ __forceinline__ bool term_kept(double w, double thr) {
@@ -404,13 +427,15 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
                        (int4*)w.trow.p, (double*)w.tbound.p, (int2*)w.cpmn.p, (double*)w.tp64.p,
                        (double*)w.bsum.p, (double*)w.part.p);
     CK(hipGetLastError());
-    hipLaunchKernelGGL(tot_kernel, dim3(1), dim3(64), 0, st, (const double*)w.part.p, NSP, ns, tot);
+    hipLaunchKernelGGL(tot_kernel, dim3(ns), dim3(256), 0, st, (const double*)w.part.p, NSP, ns, tot);
+    CK(hipGetLastError());
+    hipLaunchKernelGGL(pairmax_kernel, dim3(blocks_for(NCP, 256)), dim3(256), 0, st, (const double*)w.tp64.p,
+                       (const double*)tot, ns, NCP, (double*)w.bsum.p);
     CK(hipGetLastError());
     hipLaunchKernelGGL(weight_kernel, dim3(blocks_for(NT, 256)), dim3(256), 0, st, (const int4*)w.trow.p,
-                       (const double*)w.tbound.p, (const double*)w.tp64.p, (const double*)tot, ns, NT,
-                       (double*)w.wt.p, hist);
+                       (const double*)w.tbound.p, (const double*)w.bsum.p, NT, (double*)w.wt.p, hist);
     CK(hipGetLastError());
-    hipLaunchKernelGGL(thresh_kernel, dim3(1), dim3(1), 0, st, (const unsigned*)hist, in.eps, thr);
+    hipLaunchKernelGGL(thresh_kernel, dim3(1), dim3(64), 0, st, (const unsigned*)hist, in.eps, thr);
     CK(hipGetLastError());
     hipLaunchKernelGGL(count_kernel, dim3(blocks_for(NCP, 256)), dim3(256), 0, st, in.cp_first,
                        in.cp_nterms, (const double*)w.wt.p, (const double*)thr, NCP, (int*)w.nk.p,
