@@ -77,6 +77,101 @@ def cpu_baseline(W, seconds: float, threads: int):
                       f"FP64 direct sum, {dt:.1f} s"}
 
 
+def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, n_warm: int,
+                      max_inflight: int, budget_gb: float, log=None):
+    """Request serving: a seeded pool of mixed requests (2-30 heavy atoms,
+    1-24 transitions, N^3 grids with N in 32..96, q_max in [5, 8]).
+    1. saturated rate mu: closed loop, 2 * max_inflight requests outstanding;
+    2. open-loop Poisson arrivals at 0.5, 0.8 and 0.95 mu.
+    Latency = result in host memory - submission (the server's steady clock);
+    each arrival draws a request from the pool."""
+    import threading
+    import workload as wl
+    from paper_2512_18010_amd import binding
+
+    rng = np.random.Generator(np.random.PCG64(5000))
+    pool = [wl.make_serving_request(rng) for _ in range(n_pool)]
+    qt = [w.T.shape[0] * w.grid.n_points for w in pool]
+    srv = binding.Server(0, int(budget_gb * (1 << 30)), max_inflight)
+
+    def submit(i):
+        w = pool[i]
+        return srv.submit(w.mol, w.T, w.grid, precision=precision)
+
+    def run_closed(n, seed):
+        pick = np.random.Generator(np.random.PCG64(seed)).integers(0, n_pool, size=n)
+        out, lat, pending = [], [], []
+        t0 = time.perf_counter()
+        k = 0
+        while k < n or pending:
+            while k < n and len(pending) < 2 * max_inflight:
+                pending.append((srv.submit(pool[pick[k]].mol, pool[pick[k]].T, pool[pick[k]].grid,
+                                           precision=precision), pick[k]))
+                k += 1
+            t, i = pending.pop(0)
+            st, ns, _, _ = srv.wait(t)
+            if st != 0:
+                raise RuntimeError(f"serving request failed with status {st}")
+            lat.append(ns * 1e-6)
+            out.append(i)
+        dt = time.perf_counter() - t0
+        return dt, lat, out
+
+    run_closed(n_warm, 4999)
+    dt, lat, done = run_closed(n_sat, 5100)
+    mu = n_sat / dt
+    res = {"precision": precision, "pool": n_pool, "max_inflight": max_inflight, "budget_gb": budget_gb,
+           "saturated": {"requests": n_sat, "req_per_s": mu, "q_t_per_s": sum(qt[i] for i in done) / dt,
+                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))},
+           "rates": []}
+    if log:
+        log(f"serving {precision}: saturated {mu:.2f} req/s")
+    for ri, frac in enumerate((0.5, 0.8, 0.95)):
+        lam = frac * mu
+        g = np.random.Generator(np.random.PCG64(5000 + ri + 1))
+        arrivals = np.cumsum(g.exponential(1.0 / lam, size=n_per_rate))
+        pick = g.integers(0, n_pool, size=n_per_rate)
+        tickets = [None] * n_per_rate
+        ready = threading.Semaphore(0)
+        late = [0.0]
+
+        def producer():
+            t0 = time.perf_counter()
+            for j in range(n_per_rate):
+                d = arrivals[j] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                else:
+                    late[0] = max(late[0], -d)
+                tickets[j] = submit(pick[j])
+                ready.release()
+
+        th = threading.Thread(target=producer)
+        t0 = time.perf_counter()
+        th.start()
+        lat = []
+        for j in range(n_per_rate):
+            ready.acquire()
+            st, ns, _, _ = srv.wait(tickets[j])
+            if st != 0:
+                raise RuntimeError(f"serving request failed with status {st}")
+            lat.append(ns * 1e-6)
+        dt = time.perf_counter() - t0
+        th.join()
+        res["rates"].append({"lambda_frac": frac, "lambda_req_per_s": lam, "requests": n_per_rate,
+                             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                             "throughput_req_per_s": n_per_rate / dt,
+                             "q_t_per_s": sum(qt[i] for i in pick) / dt,
+                             "max_submit_lag_ms": float(late[0] * 1e3)})
+        if log:
+            r = res["rates"][-1]
+            log(f"serving {precision}: lambda {frac:.2f} mu -> p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms, "
+                f"{r['throughput_req_per_s']:.2f} req/s")
+    res["server_stats"] = {k: v for k, v in srv.stats().items() if k.startswith("peak") or k in ("completed", "failed")}
+    srv.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +183,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-points", type=int, default=48, help="oracle-checked grid points (0 = skip)")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the split-BF16 comparison run")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--serve-pool", type=int, default=24, help="distinct requests in the serving pool")
+    ap.add_argument("--serve-sat", type=int, default=48, help="requests of the closed-loop saturation run")
+    ap.add_argument("--serve-requests", type=int, default=96, help="requests per Poisson arrival rate")
+    ap.add_argument("--serve-warmup", type=int, default=8)
+    ap.add_argument("--serve-inflight", type=int, default=4)
+    ap.add_argument("--serve-precisions", default="fp32,bf16x3")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -111,50 +214,33 @@ def main():
     f2 = torch.empty((ns,) + n, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def step():
-        ctx.load_molecule(W.mol)
-        ctx.load_transitions_device(T_dev, stream)
-        ctx.set_options(args.screen_eps, 1.0)
-        ctx.eval_grid_device(W.grid, f, f2, precision=args.precision, stream=stream)
+    def timed(precision, steps, warmup):
+        """Whole-path steps with inputs resident in HBM; HIP events per stage."""
+        def step():
+            ctx.load_molecule(W.mol)
+            ctx.load_transitions_device(T_dev, stream)
+            ctx.set_options(args.screen_eps, 1.0)
+            ctx.eval_grid_device(W.grid, f, f2, precision=precision, stream=stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stages = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-        stages.append(ctx.last_timing())   # HIP events of this step's kernels, on `stream`
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall / args.steps * 1e3
-    info = ctx.query()
-    K, R = info["pairs_kept"], info["prim_comp_pairs_kept"]
-    st = np.array(stages)
-    prep_ms, vt_ms, grid_ms = (float(np.mean(st[:, i])) for i in range(3))
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        stages = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+            stages.append(ctx.last_timing())   # HIP events of this step's kernels, on `stream`
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = np.array(stages)
+        prep_ms, vt_ms, grid_ms = (float(np.mean(st[:, i])) for i in range(3))
+        return {"ms_per_step": wall / steps * 1e3, "precompute_ms": prep_ms, "vtables_ms": vt_ms,
+                "grid_kernel_ms": grid_ms}
 
-    # roofline of the fused grid kernel
-    gen_flops = 8.0 * R * nq                    # one complex MAC per (pair, prim pair, q)
-    con_flops = 4.0 * K * ns * nq               # real Tp x complex G per (pair, q, transition)
-    t_valu = gen_flops / PEAK_FP32_VECTOR
-    t_mfma = con_flops * (3 if args.precision == "bf16x3" else 1) / (
-        PEAK_BF16_MFMA if args.precision == "bf16x3" else PEAK_FP32_MFMA)
-    grid_s = grid_ms * 1e-3
-    achieved = gen_flops / grid_s
-    wkey = f"cfg{args.config}/eps{args.screen_eps:g}"
-    traffic = measured_traffic(wkey, args.precision)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
-            "kernel": "grid_kernel", "kernel_ms": grid_ms,
-            "algorithmic": {"generator_flops": gen_flops, "contraction_flops": con_flops,
-                            "t_valu_ms": t_valu * 1e3, "t_mfma_ms": t_mfma * 1e3,
-                            "t_star_ms": max(t_valu, t_mfma) * 1e3,
-                            "frac_of_t_star": max(t_valu, t_mfma) / grid_s,
-                            "mfma_achieved_tflops": con_flops / grid_s / 1e12}}
-
-    # accuracy on a seeded sample against the FP64 oracle (outside the timed region)
-    errors = None
-    if args.check_points > 0:
+    def check_errors():
+        """Accuracy of the last step on a seeded sample against the FP64 oracle."""
+        if args.check_points <= 0:
+            return None
         import oracle
         from tests.metrics import errors as err_fn
         idx = wl.sample_grid_indices(W.grid, args.check_points, seed=4242)
@@ -164,8 +250,57 @@ def main():
         fs = fh[:, idx, 0] + 1j * fh[:, idx, 1]
         ref = oracle.eval_points(W.mol, W.T, W.grid.points()[idx], n_threads=min(16, os.cpu_count() or 1))
         e = err_fn(fs, ref)
-        errors = {"points": int(len(idx)), "max_f2_peak_normalised": float(e["f2_peak_norm"].max()),
-                  "max_complex": float(e["complex"].max())}
+        return {"points": int(len(idx)), "max_f2_peak_normalised": float(e["f2_peak_norm"].max()),
+                "max_complex": float(e["complex"].max())}
+
+    main_run = timed(args.precision, args.steps, args.warmup)
+    ms_per_step, grid_ms = main_run["ms_per_step"], main_run["grid_kernel_ms"]
+    prep_ms, vt_ms = main_run["precompute_ms"], main_run["vtables_ms"]
+    errors = check_errors()
+    info = ctx.query()
+    K, R = info["pairs_kept"], info["prim_comp_pairs_kept"]
+
+    # roofline of the fused grid kernel
+    gen_flops = 8.0 * R * nq                    # one complex MAC per (pair, prim pair, q)
+    con_flops = 4.0 * K * ns * nq               # real Tp x complex G per (pair, q, transition)
+    t_valu = gen_flops / PEAK_FP32_VECTOR
+
+    def t_mfma(precision):
+        return con_flops * (3 if precision == "bf16x3" else 1) / (
+            PEAK_BF16_MFMA if precision == "bf16x3" else PEAK_FP32_MFMA)
+
+    grid_s = grid_ms * 1e-3
+    achieved = gen_flops / grid_s
+    wkey = f"cfg{args.config}/eps{args.screen_eps:g}"
+    traffic = measured_traffic(wkey, args.precision)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
+            "kernel": "grid_kernel", "kernel_ms": grid_ms,
+            "algorithmic": {"generator_flops": gen_flops, "contraction_flops": con_flops,
+                            "t_valu_ms": t_valu * 1e3, "t_mfma_ms": t_mfma(args.precision) * 1e3,
+                            "t_star_ms": max(t_valu, t_mfma(args.precision)) * 1e3,
+                            "frac_of_t_star": max(t_valu, t_mfma(args.precision)) / grid_s,
+                            "mfma_achieved_tflops": con_flops / grid_s / 1e12}}
+
+    # the other contraction precision on the same workload (FP32 vs split-BF16)
+    other = None
+    if not args.no_bf16:
+        oprec = "bf16x3" if args.precision == "fp32" else "fp32"
+        o = timed(oprec, max(3, args.steps // 2), 1)
+        o["errors_vs_oracle"] = check_errors()
+        o["precision"] = oprec
+        o["value"] = ns * nq / (o["ms_per_step"] * 1e-3)
+        o["kernel_only_value"] = ns * nq / (o["grid_kernel_ms"] * 1e-3)
+        o["t_star_ms"] = max(t_valu, t_mfma(oprec)) * 1e3
+        other = o
+
+    serving = None
+    if not args.no_serving:
+        serving = []
+        for prec in [p for p in args.serve_precisions.split(",") if p]:
+            serving.append(serving_benchmark(prec, args.serve_pool, args.serve_sat, args.serve_requests,
+                                             args.serve_warmup, args.serve_inflight, 64.0,
+                                             log=lambda m: print(m, file=sys.stderr, flush=True)))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -194,6 +329,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "errors_vs_oracle": errors,
+        "other_precision": other,
+        "serving": serving,
     }
     print(json.dumps(out))
 

@@ -74,6 +74,8 @@ typedef struct {
     long long prim_pairs_total;       /* sum over component pairs of prim pairs */
     long long prim_comp_pairs_kept;   /* R: (component pair, prim pair) terms kept */
     size_t device_bytes;              /* device memory held by the context    */
+    long long work_chunks;            /* packed groups of 8 (virtual) pairs the
+                                         grid kernel steps through per tile */
 } scff_info;
 
 /* Version string of the library, static storage. */

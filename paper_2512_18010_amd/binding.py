@@ -44,7 +44,8 @@ class scff_info(ctypes.Structure):
     _fields_ = [("nbf", c_int), ("n_shells", c_int), ("n_states", c_int),
                 ("shell_pairs_total", c_longlong), ("pairs_total", c_longlong),
                 ("pairs_kept", c_longlong), ("prim_pairs_total", c_longlong),
-                ("prim_comp_pairs_kept", c_longlong), ("device_bytes", c_size_t)]
+                ("prim_comp_pairs_kept", c_longlong), ("device_bytes", c_size_t),
+                ("work_chunks", c_longlong)]
 
 
 class scff_request(ctypes.Structure):
@@ -271,8 +272,8 @@ class Server:
                 np.ascontiguousarray(mol.shell_l, np.int32), np.ascontiguousarray(mol.shell_nprim, np.int32),
                 np.ascontiguousarray(mol.exps, np.float64), np.ascontiguousarray(mol.coefs, np.float64)]
         shape = (T.shape[0],) + tuple(grid.n)
-        f = np.zeros(shape + (2,), np.float32) if want_f else None
-        f2 = np.zeros(shape, np.float32) if want_f2 else None
+        f = np.empty(shape + (2,), np.float32) if want_f else None
+        f2 = np.empty(shape, np.float32) if want_f2 else None
         r = scff_request()
         r.n_atoms = arrs[0].shape[0]
         r.xyz_bohr = _d(arrs[0])

@@ -30,12 +30,30 @@
 
 #include <cstdint>
 #include <cstdlib>
+#include <type_traits>
 
 #include "engine.h"
 
 namespace scff {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int uintx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values -> two round-to-nearest-even BF16 in one dword (a in the low half).
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2{a, b}, bf16x2));
+}
+// Split-BF16 of two values: hi = RNE(g), lo = RNE(g - hi); g - hi is exact in FP32.
+__device__ __forceinline__ void split_bf16(float g0, float g1, uint32_t& hi, uint32_t& lo) {
+    hi = pack_bf16(g0, g1);
+    lo = pack_bf16(g0 - __uint_as_float(hi << 16), g1 - __uint_as_float(hi & 0xffff0000u));
+}
+__device__ __forceinline__ shortx4 bf16x4_of(uint32_t lo_k, uint32_t hi_k) {
+    return __builtin_bit_cast(shortx4, uintx2{lo_k, hi_k});
+}
 
 constexpr int kFoldChunks = 32;   // 256 component pairs per MFMA accumulation block
 
@@ -97,19 +115,36 @@ constexpr int kParts = 16;     // float4 slices per term row of the raw buffer
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+template <typename T>
+__device__ __forceinline__ uint32_t lds_addr(T* p) { return (uint32_t)(uintptr_t)(lds_void_t*)p; }
+
+// 16 bytes per lane from sbase + voff (sbase wave-uniform, voff per lane) to
+// LDS at lds_byte + 16 * lane (lds_byte wave-uniform).  Issued as inline
+// assembly so that the compiler does not treat every later LDS read as a
+// possible alias of the in-flight copy (it would then wait for all outstanding
+// vector-memory operations before each of them); completion is awaited
+// explicitly by barrier_dma.
+__device__ __forceinline__ void dma_b128(uint32_t voff, const void* sbase, uint32_t lds_byte) {
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_byte);
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(sbase), "{m0}"(m0) : "memory");
+}
+
 // LDS-only barrier: prior LDS reads/writes of this wave complete, DMA may
 // still be in flight.
 __device__ __forceinline__ void barrier_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-// Full barrier: this wave's DMA into LDS has landed as well.
+// Full barrier: this wave's DMA into LDS has landed as well.  The wait is the
+// compiler's own s_waitcnt (vmcnt(0) lgkmcnt(0)), so it knows that every
+// earlier vector-memory load is complete here.
 __device__ __forceinline__ void barrier_dma() {
-    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0070);
+    asm volatile("s_barrier" ::: "memory");
 }
 
-template <int SB, int QZL, int WPE>
+template <int SB, int QZL, int WPE, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
     const float2* __restrict__ V, int vstride, const int4* __restrict__ terms,
     const int* __restrict__ chunk_off, const int* __restrict__ chunk_npp, int n_chunks,
-    const float* __restrict__ Tp, int3 n, int3 ntiles, int n_states, float2* __restrict__ f,
+    const uint32_t* __restrict__ Tp, int3 n, int3 ntiles, int n_states, float2* __restrict__ f,
     float* __restrict__ f2) {
     constexpr int TZ = 4 * QZL;
     constexpr int ZPARTS = TZ / 2;     // float4 slices of a Z row
@@ -122,8 +157,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 
     __shared__ __align__(16) float4 R0[kNPT * kParts];
     __shared__ __align__(16) float4 R1[kNPT * kParts];
-    __shared__ __align__(16) float T0[kChunk * SW];
-    __shared__ __align__(16) float T1[kChunk * SW];
+    // Tp words: FP32 bits, or (BF) hi | lo << 16 split-BF16 halves
+    __shared__ __align__(16) uint32_t T0[kChunk * SW];
+    __shared__ __align__(16) uint32_t T1[kChunk * SW];
     __shared__ __align__(16) float2 Wl[kNPT * kWStride];
 
     const int tid = threadIdx.x;
@@ -162,18 +198,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(pt0 + 16 * j, nptl - 1) + axis];
     };
     // DMA of chunk c's raw slices and Tp block into buffer (R, T)
-    auto issue_dma = [&](int c, float4* R, float* T) {
+    // the chunk's Tp block: wave 0, one float4 per lane
+    auto issue_tp = [&](int c, uint32_t tbase) {
+        if (wave == 0 && lane < TPF4) dma_b128(16u * lane, Tp + (size_t)c * kChunk * SW, tbase);
+    };
+    auto issue_dma = [&](uint32_t rbase) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             // wave w of term group j covers terms 16j + 4w .. 16j + 4w + 3
-            if (16 * j + 4 * wave < kNPT) {
-                const float2* src = V + (size_t)rid[j] * vstride + qoff;
-                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)(R + (16 * j + 4 * wave) * kParts), 16, 0, 0);
-            }
-        }
-        if (wave == 0 && lane < TPF4) {
-            const float* src = Tp + (size_t)c * kChunk * SW + 4 * lane;
-            __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)T, 16, 0, 0);
+            if (16 * j + 4 * wave < kNPT)
+                dma_b128(8u * (__umul24(rid[j], vstride) + qoff), V, rbase + (16 * j + 4 * wave) * kParts * 16);
         }
     };
 
@@ -188,8 +222,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 #pragma unroll
             for (int i = 0; i < 4; ++i) tot_r[sb][s][i] = tot_i[sb][s][i] = 0.0;
         }
+    // BF: packed split-BF16 operands of one 16-pair MFMA group.  k = 4*kk + j,
+    // j = 2*half + step: the two chunks of a main-loop iteration fill one group.
+    uint32_t bhr[SLOTS][2], blr[SLOTS][2], bhi[SLOTS][2], bli[SLOTS][2];
+    uint32_t ah[SB][2], al[SB][2];
+    float g0r[SLOTS], g0i[SLOTS];
+    uint32_t u0[SB];
+    auto mfma_group = [&]() {
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) {
+            const shortx4 Ah = bf16x4_of(ah[sb][0], ah[sb][1]), Al = bf16x4_of(al[sb][0], al[sb][1]);
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const shortx4 Bhr = bf16x4_of(bhr[s][0], bhr[s][1]), Blr = bf16x4_of(blr[s][0], blr[s][1]);
+                const shortx4 Bhi = bf16x4_of(bhi[s][0], bhi[s][1]), Bli = bf16x4_of(bli[s][0], bli[s][1]);
+                // hi*lo + lo*hi first, then hi*hi, into one FP32 accumulator
+                acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Blr, acc_r[sb][s], 0, 0, 0);
+                acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Bli, acc_i[sb][s], 0, 0, 0);
+                acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Al, Bhr, acc_r[sb][s], 0, 0, 0);
+                acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Al, Bhi, acc_i[sb][s], 0, 0, 0);
+                acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Bhr, acc_r[sb][s], 0, 0, 0);
+                acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Bhi, acc_i[sb][s], 0, 0, 0);
+            }
+        }
+    };
 
-    auto chunk_body = [&](int c, const float4* R, const float* T) {
+    auto chunk_body = [&](int c, const float4* R, const uint32_t* T, auto half_tag) {
+        constexpr int H = decltype(half_tag)::value;
         const int npp = chunk_npp[c];
         // W = Vx * Vy: item = (term, qx) -> 8 lines
         for (int i = tid; i < kChunk * npp * 4; i += 256) {
@@ -208,7 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 #pragma unroll
         for (int step = 0; step < kChunk / 4; ++step) {
             const int pair = step * 4 + kk;
-            float a_op[SB];
+            uint32_t a_op[SB];
 #pragma unroll
             for (int sb = 0; sb < SB; ++sb) a_op[sb] = T[pair * SW + sb * 16 + ln];
             float gr[SLOTS], gi[SLOTS];
@@ -237,15 +296,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
                     gi[QZL + j] = fmaf(w.w, z[j].x, gi[QZL + j]);
                 }
             }
+            if constexpr (!BF) {
 #pragma unroll
-            for (int sb = 0; sb < SB; ++sb)
+                for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+                    for (int s = 0; s < SLOTS; ++s) {
+                        const float a = __uint_as_float(a_op[sb]);
+                        acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gr[s], acc_r[sb][s], 0, 0, 0);
+                        acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gi[s], acc_i[sb][s], 0, 0, 0);
+                    }
+            } else if (step == 0) {
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
-                    acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_op[sb], gr[s], acc_r[sb][s], 0, 0, 0);
-                    acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_op[sb], gi[s], acc_i[sb][s], 0, 0, 0);
+                    g0r[s] = gr[s];
+                    g0i[s] = gi[s];
                 }
+#pragma unroll
+                for (int sb = 0; sb < SB; ++sb) u0[sb] = a_op[sb];
+            } else {
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+                    split_bf16(g0r[s], gr[s], bhr[s][H], blr[s][H]);
+                    split_bf16(g0i[s], gi[s], bhi[s][H], bli[s][H]);
+                }
+#pragma unroll
+                for (int sb = 0; sb < SB; ++sb) {
+                    ah[sb][H] = (u0[sb] & 0xffffu) | (a_op[sb] << 16);
+                    al[sb][H] = (u0[sb] >> 16) | (a_op[sb] & 0xffff0000u);
+                }
+            }
         }
-        if ((c + 1) % kTiles == 0 || c + 1 == n_chunks) {
+        if constexpr (BF) {
+            if (H == 1) mfma_group();
+        } else if ((c + 1) % kTiles == 0 || c + 1 == n_chunks) {
             // exact fold of the short FP32 MFMA block into FP64 totals
 #pragma unroll
             for (int sb = 0; sb < SB; ++sb)
@@ -264,24 +347,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 
     if (n_chunks > 0) {
         load_rows(0);
-        issue_dma(0, R0, T0);
+        issue_tp(0, lds_addr(T0));
+        issue_dma(lds_addr(R0));
         if (n_chunks > 1) load_rows(1);
     }
     // two chunks per iteration so each buffer is a distinct LDS object
     for (int c = 0; c < n_chunks; c += 2) {
         barrier_dma();                                  // chunk c landed in R0/T0; Wl and R1 are free
         if (c + 1 < n_chunks) {
-            issue_dma(c + 1, R1, T1);
+            issue_tp(c + 1, lds_addr(T1));
+            issue_dma(lds_addr(R1));
             if (c + 2 < n_chunks) load_rows(c + 2);
         }
-        chunk_body(c, R0, T0);
+        chunk_body(c, R0, T0, std::integral_constant<int, 0>{});
         if (c + 1 >= n_chunks) break;
         barrier_dma();                                  // chunk c+1 landed in R1/T1; Wl and R0 are free
         if (c + 2 < n_chunks) {
-            issue_dma(c + 2, R0, T0);
+            issue_tp(c + 2, lds_addr(T0));
+            issue_dma(lds_addr(R0));
             if (c + 3 < n_chunks) load_rows(c + 3);
         }
-        chunk_body(c + 1, R1, T1);
+        chunk_body(c + 1, R1, T1, std::integral_constant<int, 1>{});
+    }
+    if constexpr (BF) {
+        if (n_chunks & 1) {   // last group holds one chunk: k-steps 2, 3 are zero
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) bhr[s][1] = blr[s][1] = bhi[s][1] = bli[s][1] = 0u;
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb) ah[sb][1] = al[sb][1] = 0u;
+            mfma_group();
+        }
     }
 
     // epilogue: lane holds states sb*16 + 4*kk + i for the q values of column ln
@@ -298,7 +393,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             for (int i = 0; i < 4; ++i) {
                 const int st = sb * 16 + 4 * kk + i;
                 if (st >= n_states) continue;
-                const double vr = tot_r[sb][s][i], vi = tot_i[sb][s][i];
+                const double vr = BF ? (double)acc_r[sb][s][i] : tot_r[sb][s][i];
+                const double vi = BF ? (double)acc_i[sb][s][i] : tot_i[sb][s][i];
                 const size_t o = (((size_t)st * n.x + qx) * n.y + qy) * n.z + qz;
                 if (f) f[o] = make_float2((float)vr, (float)vi);
                 if (f2) f2[o] = (float)(vr * vr + vi * vi);
@@ -370,14 +466,14 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
     return hipGetLastError();
 }
 
-template <int SB, int QZL, int WPE>
+template <int SB, int QZL, int WPE, bool BF>
 static hipError_t launch_grid_t(const float2* V, int vstride, const int4* terms, const int* coff,
-                                const int* cnpp, int n_chunks, const float* Tp, const int n[3],
+                                const int* cnpp, int n_chunks, const uint32_t* Tp, const int n[3],
                                 int n_states, float2* f, float* f2, hipStream_t st) {
     const int3 nn = make_int3(n[0], n[1], n[2]);
     const int3 nt = make_int3((n[0] + 3) / 4, (n[1] + 7) / 8, (n[2] + 4 * QZL - 1) / (4 * QZL));
     const long long blocks = (long long)nt.x * nt.y * nt.z;
-    hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE>), dim3((unsigned)blocks), dim3(256), 0, st, V, vstride,
+    hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE, BF>), dim3((unsigned)blocks), dim3(256), 0, st, V, vstride,
                        terms, coff, cnpp, n_chunks, Tp, nn, nt, n_states, f, f2);
     return hipGetLastError();
 }
@@ -394,23 +490,35 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
                        const int4* terms, const int* coff, const int* cnpp, int n_chunks,
                        const float* Tp, const uint32_t* tp_bf, const int n[3], int n_states,
                        float2* f, float* f2, hipStream_t st) {
-    (void)tp_bf;
-    if (precision != 0) return hipErrorNotSupported;
+    if (precision != 0 && precision != 1) return hipErrorInvalidValue;
     if (vstride < vtable_stride(n)) return hipErrorInvalidValue;
     static int variant = -1;
     if (variant < 0) {
         const char* e = getenv("SCFF_GRID_VARIANT");
         variant = e ? atoi(e) : 0;
     }
-    if (state_blocks == 1) {
-        if (variant == 1) return launch_grid_t<1, 4, 1>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
-        if (variant == 3) return launch_grid_t<1, 2, 3>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
-        if (variant == 4) return launch_grid_t<1, 2, 2>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
-        return launch_grid_t<1, 4, 2>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+    const uint32_t* tp32 = reinterpret_cast<const uint32_t*>(Tp);
+#define SCFF_GRID(SB_, QZL_, WPE_, BF_) \
+    return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, terms, coff, cnpp, n_chunks, BF_ ? tp_bf : tp32, n, \
+                                               n_states, f, f2, st)
+    if (precision == 1) {
+        if (state_blocks == 1) {
+            if (variant == 1) SCFF_GRID(1, 2, 2, true);
+            SCFF_GRID(1, 4, 2, true);
+        }
+        if (variant == 1) SCFF_GRID(2, 4, 2, true);
+        SCFF_GRID(2, 2, 2, true);
     }
-    if (variant == 1) return launch_grid_t<2, 2, 1>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
-    if (variant == 5) return launch_grid_t<2, 1, 2>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
-    return launch_grid_t<2, 2, 2>(V, vstride, terms, coff, cnpp, n_chunks, Tp, n, n_states, f, f2, st);
+    if (state_blocks == 1) {
+        if (variant == 1) SCFF_GRID(1, 4, 1, false);
+        if (variant == 3) SCFF_GRID(1, 2, 3, false);
+        if (variant == 4) SCFF_GRID(1, 2, 2, false);
+        SCFF_GRID(1, 4, 2, false);
+    }
+    if (variant == 1) SCFF_GRID(2, 2, 1, false);
+    if (variant == 5) SCFF_GRID(2, 1, 2, false);
+    SCFF_GRID(2, 2, 2, false);
+#undef SCFF_GRID
 }
 
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,

@@ -178,6 +178,9 @@ int validate_grid(const scff_grid* g) {
 int build_vtables(scff_ctx* c, const scff_grid* g, hipStream_t st) {
     const int nrows = c->pres.n_rows;
     const int stride = vtable_stride(g->n);
+    // the grid kernel addresses the tables with 32-bit byte offsets
+    if ((size_t)nrows * stride * sizeof(float2) > 0xffffffffull)
+        return fail(SCFF_EINVAL, "1D tables of this grid exceed 4 GiB: evaluate it in slabs");
     int rc = dev_reserve(c, c->d_vtab, (size_t)nrows * stride * sizeof(float2));
     if (rc) return rc;
     double dq[3];
@@ -356,6 +359,7 @@ int scff_query(scff_ctx* c, scff_info* info) {
         if ((rc = ensure_prepared(c, nullptr))) return rc;
         info->pairs_kept = c->pres.pairs_kept;
         info->prim_comp_pairs_kept = c->pres.terms_kept;
+        info->work_chunks = c->pres.n_chunks;
     }
     info->device_bytes = c->used;
     return ok();

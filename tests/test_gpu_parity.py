@@ -52,7 +52,7 @@ def check(name, f_gpu, f2_gpu, f_ref, precision):
     return e
 
 
-@pytest.mark.parametrize("precision", ["fp32"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_small_full_grid_ragged(eng, oracle_mod, precision):
     """Config-0 molecule on a ragged 13 x 11 x 37 grid: every element vs the oracle."""
     W = wl.make_config(0)
@@ -63,7 +63,7 @@ def test_small_full_grid_ragged(eng, oracle_mod, precision):
     check("cfg0 13x11x37", f, f2, ref, precision)
 
 
-@pytest.mark.parametrize("precision", ["fp32"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_multi_state_full_grid(eng, oracle_mod, precision):
     """A 24-state case (two MFMA row blocks) on a small ragged grid."""
     rng = np.random.Generator(np.random.PCG64(99))
@@ -94,16 +94,45 @@ def sampled_parity(eng, oracle_mod, cfg, precision, n_sample, eps=0.0):
     return check(f"cfg{cfg} sampled {len(idx)}", fs, f2s, ref, precision)
 
 
-def test_config1_sampled(eng, oracle_mod):
-    sampled_parity(eng, oracle_mod, 1, "fp32", 256)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_config1_sampled(eng, oracle_mod, precision):
+    sampled_parity(eng, oracle_mod, 1, precision, 256)
 
 
 def test_config2_sampled(eng, oracle_mod):
     sampled_parity(eng, oracle_mod, 2, "fp32", 128)
 
 
-def test_config3_sampled_screened(eng, oracle_mod):
-    sampled_parity(eng, oracle_mod, 3, "fp32", 48, eps=1e-9)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_config3_sampled_screened(eng, oracle_mod, precision):
+    sampled_parity(eng, oracle_mod, 3, precision, 48, eps=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_odd_and_even_chunk_counts(eng, oracle_mod, precision):
+    """The split-BF16 path pairs chunks into 16-pair MFMA groups; an odd
+    number of chunks leaves a half group.  Screening thresholds are swept
+    until both parities have been seen, each checked against the oracle."""
+    W = wl.make_config(0)
+    W.grid = wl.Grid(n=(8, 9, 17), qmin=(-5.0,) * 3, qmax=(5.0,) * 3)
+    ref = oracle_mod.eval_grid(W.mol, W.T, W.grid, n_threads=NTH)
+    seen = set()
+    for eps in (0.0, 1e-14, 1e-13, 1e-12, 1e-11, 1e-10, 3e-10, 1e-9, 3e-9, 1e-8):
+        eng.load_molecule(W.mol)
+        eng.load_transitions(W.T)
+        eng.set_options(eps, 1.0)
+        nch = eng.query()["work_chunks"]
+        if nch % 2 in seen:
+            continue
+        seen.add(nch % 2)
+        f, f2 = eng.eval_grid_host(W.grid, precision)
+        e = errors(f, ref)
+        log(f"[chunks={nch} eps={eps:g}] {precision}: peak-normalised |f|^2 err {e['f2_peak_norm'].max():.3e}")
+        # the screening error is part of the budget here; eps <= 1e-8 keeps it well below 1e-6
+        assert e["f2_peak_norm"].max() <= TOL_F2[precision]
+        if len(seen) == 2:
+            break
+    assert seen == {0, 1}, seen
 
 
 def test_conjugate_symmetry_on_gpu(eng):
