@@ -153,6 +153,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     constexpr int NJ = (kNPT + 15) / 16;       // term groups per slice-thread (5)
     constexpr int TPF4 = kChunk * SW / 4;      // float4 of Tp per chunk (32 or 64)
     static_assert(2 + 4 + ZPARTS <= kParts, "slices per term");
+    static_assert(QZL % 2 == 0, "q_z values per lane come in float4 pairs");
+    // software prefetch of the next term's LDS slices (12 VGPRs): only where
+    // the register budget has room for it (not next to the FP64 fold totals)
+    constexpr bool PF = BF;
     static_assert(TPF4 <= 64, "Tp block per chunk fits one wave");
 
     __shared__ __align__(16) float4 R0[kNPT * kParts];
@@ -226,8 +230,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     // j = 2*half + step: the two chunks of a main-loop iteration fill one group.
     uint32_t bhr[SLOTS][2], blr[SLOTS][2], bhi[SLOTS][2], bli[SLOTS][2];
     uint32_t ah[SB][2], al[SB][2];
-    float g0r[SLOTS], g0i[SLOTS];
-    uint32_t u0[SB];
     auto mfma_group = [&]() {
 #pragma unroll
         for (int sb = 0; sb < SB; ++sb) {
@@ -264,66 +266,93 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             }
         }
         barrier_lds();
+        // G of one component pair for this lane's 2 lines x QZL q_z values,
+        // G = sum_t W_t(line) Vz_t(qz).  The first term initialises G; the
+        // slices of term t+1 are read from LDS while the FMAs of term t run.
+        auto gen = [&](int pair, float (&gr)[SLOTS], float (&gi)[SLOTS]) {
+            const float2* wp = Wl + (pair * npp) * kWStride + wave * 8 + 2 * lpair;
+            const float2* zp = reinterpret_cast<const float2*>(R + (pair * npp) * kParts + 6) + zgrp * QZL;
+            auto load = [&](int t, float4& w, float4 (&zz)[QZL / 2]) {
+                w = *reinterpret_cast<const float4*>(wp + t * kWStride);
+#pragma unroll
+                for (int j = 0; j < QZL / 2; ++j) zz[j] = *reinterpret_cast<const float4*>(zp + t * (2 * kParts) + 2 * j);
+            };
+            auto zval = [&](const float4 (&zz)[QZL / 2], int j) {
+                return (j & 1) ? make_float2(zz[j >> 1].z, zz[j >> 1].w) : make_float2(zz[j >> 1].x, zz[j >> 1].y);
+            };
+            auto fma_term = [&](const float4& w, const float4 (&zz)[QZL / 2]) {
+#pragma unroll
+                for (int j = 0; j < QZL; ++j) {
+                    const float2 z = zval(zz, j);
+                    gr[j] = fmaf(w.x, z.x, gr[j]);
+                    gr[j] = fmaf(-w.y, z.y, gr[j]);
+                    gi[j] = fmaf(w.x, z.y, gi[j]);
+                    gi[j] = fmaf(w.y, z.x, gi[j]);
+                    gr[QZL + j] = fmaf(w.z, z.x, gr[QZL + j]);
+                    gr[QZL + j] = fmaf(-w.w, z.y, gr[QZL + j]);
+                    gi[QZL + j] = fmaf(w.z, z.y, gi[QZL + j]);
+                    gi[QZL + j] = fmaf(w.w, z.x, gi[QZL + j]);
+                }
+            };
+            float4 wa, za[QZL / 2], wb, zb[QZL / 2];
+            load(0, wa, za);
+            if (PF && npp > 1) load(1, wb, zb);
+#pragma unroll
+            for (int j = 0; j < QZL; ++j) {   // the first term initialises G
+                const float2 z = zval(za, j);
+                gr[j] = fmaf(-wa.y, z.y, wa.x * z.x);
+                gi[j] = fmaf(wa.y, z.x, wa.x * z.y);
+                gr[QZL + j] = fmaf(-wa.w, z.y, wa.z * z.x);
+                gi[QZL + j] = fmaf(wa.w, z.x, wa.z * z.y);
+            }
+            if constexpr (PF) {
+                // ping-pong register sets: (wb, zb) holds term t, (wa, za) term t+1
+                int t = 1;
+                for (; t + 1 < npp; t += 2) {
+                    load(t + 1, wa, za);
+                    fma_term(wb, zb);
+                    load(min(t + 2, npp - 1), wb, zb);   // clamped: no conditional register set
+                    fma_term(wa, za);
+                }
+                if (t < npp) fma_term(wb, zb);
+            } else {
+                for (int t = 1; t < npp; ++t) {
+                    load(t, wa, za);
+                    fma_term(wa, za);
+                }
+            }
+        };
+        // two MFMA k-steps of 4 pairs each; lane (kk, ln) handles pair 4*step + kk
+        float gr[2][SLOTS], gi[2][SLOTS];
+        uint32_t a_op[2][SB];
 #pragma unroll
         for (int step = 0; step < kChunk / 4; ++step) {
             const int pair = step * 4 + kk;
-            uint32_t a_op[SB];
 #pragma unroll
-            for (int sb = 0; sb < SB; ++sb) a_op[sb] = T[pair * SW + sb * 16 + ln];
-            float gr[SLOTS], gi[SLOTS];
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) gr[s] = gi[s] = 0.f;
-            const float2* wp = Wl + (pair * npp) * kWStride + wave * 8 + 2 * lpair;
-            const float2* zp = reinterpret_cast<const float2*>(R + (pair * npp) * kParts + 6) + zgrp * QZL;
-            for (int t = 0; t < npp; ++t) {
-                const float4 w = *reinterpret_cast<const float4*>(wp + t * kWStride);
-                float2 z[QZL];
-#pragma unroll
-                for (int j = 0; j < QZL; j += 2) {
-                    const float4 zz = *reinterpret_cast<const float4*>(zp + t * (2 * kParts) + j);
-                    z[j] = make_float2(zz.x, zz.y);
-                    z[j + 1] = make_float2(zz.z, zz.w);
-                }
-#pragma unroll
-                for (int j = 0; j < QZL; ++j) {
-                    gr[j] = fmaf(w.x, z[j].x, gr[j]);
-                    gr[j] = fmaf(-w.y, z[j].y, gr[j]);
-                    gi[j] = fmaf(w.x, z[j].y, gi[j]);
-                    gi[j] = fmaf(w.y, z[j].x, gi[j]);
-                    gr[QZL + j] = fmaf(w.z, z[j].x, gr[QZL + j]);
-                    gr[QZL + j] = fmaf(-w.w, z[j].y, gr[QZL + j]);
-                    gi[QZL + j] = fmaf(w.z, z[j].y, gi[QZL + j]);
-                    gi[QZL + j] = fmaf(w.w, z[j].x, gi[QZL + j]);
-                }
-            }
+            for (int sb = 0; sb < SB; ++sb) a_op[step][sb] = T[pair * SW + sb * 16 + ln];
+            gen(pair, gr[step], gi[step]);
             if constexpr (!BF) {
 #pragma unroll
                 for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
                     for (int s = 0; s < SLOTS; ++s) {
-                        const float a = __uint_as_float(a_op[sb]);
-                        acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gr[s], acc_r[sb][s], 0, 0, 0);
-                        acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gi[s], acc_i[sb][s], 0, 0, 0);
+                        const float a = __uint_as_float(a_op[step][sb]);
+                        acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gr[step][s], acc_r[sb][s], 0, 0, 0);
+                        acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gi[step][s], acc_i[sb][s], 0, 0, 0);
                     }
-            } else if (step == 0) {
+            }
+        }
+        if constexpr (BF) {
+            // k-steps j = 2H, 2H+1 of the group: split G and pack Tp halves
 #pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    g0r[s] = gr[s];
-                    g0i[s] = gi[s];
-                }
+            for (int s = 0; s < SLOTS; ++s) {
+                split_bf16(gr[0][s], gr[1][s], bhr[s][H], blr[s][H]);
+                split_bf16(gi[0][s], gi[1][s], bhi[s][H], bli[s][H]);
+            }
 #pragma unroll
-                for (int sb = 0; sb < SB; ++sb) u0[sb] = a_op[sb];
-            } else {
-#pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    split_bf16(g0r[s], gr[s], bhr[s][H], blr[s][H]);
-                    split_bf16(g0i[s], gi[s], bhi[s][H], bli[s][H]);
-                }
-#pragma unroll
-                for (int sb = 0; sb < SB; ++sb) {
-                    ah[sb][H] = (u0[sb] & 0xffffu) | (a_op[sb] << 16);
-                    al[sb][H] = (u0[sb] >> 16) | (a_op[sb] & 0xffff0000u);
-                }
+            for (int sb = 0; sb < SB; ++sb) {
+                ah[sb][H] = (a_op[0][sb] & 0xffffu) | (a_op[1][sb] << 16);
+                al[sb][H] = (a_op[0][sb] >> 16) | (a_op[1][sb] & 0xffff0000u);
             }
         }
         if constexpr (BF) {
@@ -516,7 +545,6 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
         SCFF_GRID(1, 4, 2, false);
     }
     if (variant == 1) SCFF_GRID(2, 2, 1, false);
-    if (variant == 5) SCFF_GRID(2, 1, 2, false);
     SCFF_GRID(2, 2, 2, false);
 #undef SCFF_GRID
 }
