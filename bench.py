@@ -78,7 +78,7 @@ def cpu_baseline(W, seconds: float, threads: int):
 
 
 def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, n_warm: int,
-                      max_inflight: int, budget_gb: float, log=None):
+                      max_inflight: int, budget_gb: float, screen_eps: float, log=None):
     """Request serving: a seeded pool of mixed requests (2-30 heavy atoms,
     1-24 transitions, N^3 grids with N in 32..96, q_max in [5, 8]).
     1. saturated rate mu: closed loop, 2 * max_inflight requests outstanding;
@@ -96,7 +96,7 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
 
     def submit(i):
         w = pool[i]
-        return srv.submit(w.mol, w.T, w.grid, precision=precision)
+        return srv.submit(w.mol, w.T, w.grid, precision=precision, screen_eps=screen_eps)
 
     def run_closed(n, seed):
         pick = np.random.Generator(np.random.PCG64(seed)).integers(0, n_pool, size=n)
@@ -105,8 +105,7 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
         k = 0
         while k < n or pending:
             while k < n and len(pending) < 2 * max_inflight:
-                pending.append((srv.submit(pool[pick[k]].mol, pool[pick[k]].T, pool[pick[k]].grid,
-                                           precision=precision), pick[k]))
+                pending.append((submit(pick[k]), pick[k]))
                 k += 1
             t, i = pending.pop(0)
             st, ns, _, _ = srv.wait(t)
@@ -120,7 +119,8 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
     run_closed(n_warm, 4999)
     dt, lat, done = run_closed(n_sat, 5100)
     mu = n_sat / dt
-    res = {"precision": precision, "pool": n_pool, "max_inflight": max_inflight, "budget_gb": budget_gb,
+    res = {"precision": precision, "screen_eps": screen_eps, "pool": n_pool, "max_inflight": max_inflight,
+           "budget_gb": budget_gb,
            "saturated": {"requests": n_sat, "req_per_s": mu, "q_t_per_s": sum(qt[i] for i in done) / dt,
                          "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))},
            "rates": []}
@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=8)
     ap.add_argument("--serve-inflight", type=int, default=4)
     ap.add_argument("--serve-precisions", default="fp32,bf16x3")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the measurement, run one plain device copy of this many MiB (a known-size "
+                         "kernel for calibrating hardware byte counters in the same profiled run)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -299,8 +302,16 @@ def main():
         serving = []
         for prec in [p for p in args.serve_precisions.split(",") if p]:
             serving.append(serving_benchmark(prec, args.serve_pool, args.serve_sat, args.serve_requests,
-                                             args.serve_warmup, args.serve_inflight, 64.0,
+                                             args.serve_warmup, args.serve_inflight, 64.0, args.screen_eps,
                                              log=lambda m: print(m, file=sys.stderr, flush=True)))
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

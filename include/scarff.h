@@ -74,8 +74,9 @@ typedef struct {
     long long prim_pairs_total;       /* sum over component pairs of prim pairs */
     long long prim_comp_pairs_kept;   /* R: (component pair, prim pair) terms kept */
     size_t device_bytes;              /* device memory held by the context    */
-    long long work_chunks;            /* packed groups of 8 (virtual) pairs the
-                                         grid kernel steps through per tile */
+    long long work_units;             /* units of 8 packed (virtual) pairs    */
+    long long work_chunks;            /* staging steps of the grid kernel per
+                                         tile: runs of 1-4 units, <= 72 terms */
 } scff_info;
 
 /* Version string of the library, static storage. */

@@ -45,7 +45,7 @@ class scff_info(ctypes.Structure):
                 ("shell_pairs_total", c_longlong), ("pairs_total", c_longlong),
                 ("pairs_kept", c_longlong), ("prim_pairs_total", c_longlong),
                 ("prim_comp_pairs_kept", c_longlong), ("device_bytes", c_size_t),
-                ("work_chunks", c_longlong)]
+                ("work_units", c_longlong), ("work_chunks", c_longlong)]
 
 
 class scff_request(ctypes.Structure):

@@ -18,8 +18,13 @@ namespace scff {
 // pair with more terms is split into several virtual pairs that share its
 // packed transition weight, so any contraction length is supported.
 constexpr int kMaxTermsPerPair = 9;
-// Component pairs processed per staging step of the grid kernel.
+// Component pairs per unit: the layout granule of packed weights and term
+// slots, and one pair of MFMA k-steps (4 pairs each) of the grid kernel.
 constexpr int kChunk = 8;
+// The grid kernel stages whole chunks of consecutive units that share a term
+// count npp: at most kMaxUnitsPerChunk units and kMaxChunkTerms terms.
+constexpr int kMaxUnitsPerChunk = 4;
+constexpr int kMaxChunkTerms = kChunk * kMaxTermsPerPair;   // 72
 // States per MFMA row block.
 constexpr int kStateBlock = 16;
 constexpr int kMaxStates = 32;
@@ -91,16 +96,18 @@ struct PrepInputs {
     double eps, spin;
 };
 
-// Device buffers of the precompute; rows/slots/cnpp/coff/tp32/tpbf are what
-// the evaluation kernels consume.
+// Device buffers of the precompute; rows/slots/cnpp/coff/chunks/tp32/tpbf are
+// what the evaluation kernels consume.  cnpp/coff are per unit (terms per
+// pair, first slot); chunks holds (first unit, units) per grid-kernel chunk.
 struct PrepWork {
     DeviceBuffer rows_all, rowsum, trow, tbound, wt, cpmn, tp64, bsum, part, small, nk, nv, vbase,
         tmp, key, val, vinfo, tmp2, cnpp, csize, coff, tmp3, slots, tp32, tpbf, row_used, newid, tmp4,
-        rows;
+        rows, uhist, chunks;
+    std::vector<int> chunk_host;   // staging of the chunk table (kept until the next prep)
 };
 
 struct PrepResult {
-    int n_vpairs = 0, n_chunks = 0, n_rows = 0, state_blocks = 1;
+    int n_vpairs = 0, n_units = 0, n_chunks = 0, n_rows = 0, state_blocks = 1;
     long long n_slots = 0, pairs_kept = 0, terms_kept = 0;
 };
 

@@ -96,11 +96,13 @@ __global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int v
 // ---------------------------------------------------------------- grid kernel
 //
 // Workgroup = 4 waves, tile = 4 qx x 8 qy lines x TZ qz (TZ = 4*QZL).
-// Per chunk of 8 component pairs with npp terms each (npp <= 9), for every
-// term t (index ptl = pair*npp + term):
+// The packed pairs come in units of 8 component pairs with npp terms each
+// (npp <= 9); a chunk is a run of 1..4 consecutive units with the same npp
+// and at most 72 terms (up to 32 pairs when npp <= 2).  Per chunk, for every
+// term t (index ptl = (unit*8 + pair)*npp + term):
 //   raw slices  Vx[t][4], Vy[t][8], Vz[t][TZ]   global -> LDS by direct DMA
 //   W[t][line] = Vx * Vy                        cooperative, in LDS
-// plus the chunk's packed weights Tp[8][16*SB] (DMA as well).  The raw
+// plus the chunk's packed weights Tp[pairs][16*SB] (DMA as well).  The raw
 // buffers are double-buffered: the DMA for chunk c+1 is issued at the start
 // of chunk c and completes under chunk c's W phase and main loop; the row
 // ids it needs were loaded one chunk earlier.  Thread tid always moves slice
@@ -108,9 +110,9 @@ __global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int v
 // wave's DMA is contiguous (lane * 16 bytes), as the instruction requires.
 // Lane (kk, ln): pair kk of the current MFMA k-step, 2 lines x QZL qz.
 
-constexpr int kTiles = 4;      // chunks (32 pairs) per FP64 fold of the MFMA sums
+constexpr int kFoldUnits = 4;  // units (32 pairs) per FP64 fold of the FP32 MFMA sums
 constexpr int kWStride = 34;   // float2 per term row of W (32 lines + pad)
-constexpr int kNPT = kChunk * kMaxTermsPerPair;   // 72 terms per chunk at most
+constexpr int kNPT = kMaxChunkTerms;   // 72 terms per chunk at most
 constexpr int kParts = 16;     // float4 slices per term row of the raw buffer
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -143,27 +145,27 @@ __device__ __forceinline__ void barrier_dma() {
 template <int SB, int QZL, int WPE, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
     const float2* __restrict__ V, int vstride, const int4* __restrict__ terms,
-    const int* __restrict__ chunk_off, const int* __restrict__ chunk_npp, int n_chunks,
-    const uint32_t* __restrict__ Tp, int3 n, int3 ntiles, int n_states, float2* __restrict__ f,
-    float* __restrict__ f2) {
+    const int4* __restrict__ chunks, int n_chunks, const uint32_t* __restrict__ Tp, int3 n, int3 ntiles,
+    int n_states, float2* __restrict__ f, float* __restrict__ f2) {
     constexpr int TZ = 4 * QZL;
     constexpr int ZPARTS = TZ / 2;     // float4 slices of a Z row
     constexpr int SLOTS = 2 * QZL;     // q values per lane
     constexpr int SW = 16 * SB;        // padded state count
     constexpr int NJ = (kNPT + 15) / 16;       // term groups per slice-thread (5)
-    constexpr int TPF4 = kChunk * SW / 4;      // float4 of Tp per chunk (32 or 64)
+    constexpr int TPW = kMaxUnitsPerChunk * kChunk * SW;   // Tp words per chunk at most
     static_assert(2 + 4 + ZPARTS <= kParts, "slices per term");
     static_assert(QZL % 2 == 0, "q_z values per lane come in float4 pairs");
+    static_assert(TPW / 4 <= 256, "Tp block per chunk fits one DMA per thread");
     // software prefetch of the next term's LDS slices (12 VGPRs): only where
-    // the register budget has room for it (not next to the FP64 fold totals)
-    constexpr bool PF = BF;
-    static_assert(TPF4 <= 64, "Tp block per chunk fits one wave");
+    // the register budget has room for it (not next to the 128 VGPRs of FP64
+    // fold totals that the FP32 path needs at QZL = 4)
+    constexpr bool PF = BF || QZL <= 2;
 
     __shared__ __align__(16) float4 R0[kNPT * kParts];
     __shared__ __align__(16) float4 R1[kNPT * kParts];
     // Tp words: FP32 bits, or (BF) hi | lo << 16 split-BF16 halves
-    __shared__ __align__(16) uint32_t T0[kChunk * SW];
-    __shared__ __align__(16) uint32_t T1[kChunk * SW];
+    __shared__ __align__(16) uint32_t T0[TPW];
+    __shared__ __align__(16) uint32_t T1[TPW];
     __shared__ __align__(16) float2 Wl[kNPT * kWStride];
 
     const int tid = threadIdx.x;
@@ -183,7 +185,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 
     // ---- this thread's slice: axis and offset of its 16 bytes in a table row
     const int part = tid & 15;
-    const int pt0 = tid >> 4;
     int axis, qoff;
     if (part < 2) {
         axis = 0; qoff = qx0 + 2 * part;
@@ -196,23 +197,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     // row ids of the slices of chunk c (loaded one chunk ahead of the DMA)
     int rid[NJ];
     auto load_rows = [&](int c) {
-        const int nptl = kChunk * chunk_npp[c];
-        const int* tc = reinterpret_cast<const int*>(terms + chunk_off[c]);
+        const int4 ch = chunks[c];   // (first unit, units, npp, first slot)
+        const int nptl = ch.y * kChunk * ch.z;
+        const int* tc = reinterpret_cast<const int*>(terms + ch.w);
+        // lane indices recomputed here rather than kept live across the loop
+        int t0 = threadIdx.x;
+        asm volatile("" : "+v"(t0));
+        const int p0 = t0 >> 4;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(pt0 + 16 * j, nptl - 1) + axis];
+        for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(p0 + 16 * j, nptl - 1) + axis];
     };
-    // DMA of chunk c's raw slices and Tp block into buffer (R, T)
-    // the chunk's Tp block: wave 0, one float4 per lane
-    auto issue_tp = [&](int c, uint32_t tbase) {
-        if (wave == 0 && lane < TPF4) dma_b128(16u * lane, Tp + (size_t)c * kChunk * SW, tbase);
-    };
-    auto issue_dma = [&](uint32_t rbase) {
+    // DMA of chunk c's raw slices into buffer rbase and its Tp block into tbase
+    auto issue_dma = [&](int c, uint32_t rbase, uint32_t tbase) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             // wave w of term group j covers terms 16j + 4w .. 16j + 4w + 3
             if (16 * j + 4 * wave < kNPT)
                 dma_b128(8u * (__umul24(rid[j], vstride) + qoff), V, rbase + (16 * j + 4 * wave) * kParts * 16);
         }
+        const int4 ch = chunks[c];
+        const int tpf4 = ch.y * (kChunk * SW / 4);   // float4 of Tp in this chunk
+        if (64 * wave < tpf4 && lane < tpf4 - 64 * wave)
+            dma_b128(16u * (64 * wave + lane), Tp + (size_t)ch.x * kChunk * SW, tbase + 1024 * wave);
     };
 
     floatx4 acc_r[SB][SLOTS], acc_i[SB][SLOTS];
@@ -226,18 +232,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 #pragma unroll
             for (int i = 0; i < 4; ++i) tot_r[sb][s][i] = tot_i[sb][s][i] = 0.0;
         }
-    // BF: packed split-BF16 operands of one 16-pair MFMA group.  k = 4*kk + j,
-    // j = 2*half + step: the two chunks of a main-loop iteration fill one group.
-    uint32_t bhr[SLOTS][2], blr[SLOTS][2], bhi[SLOTS][2], bli[SLOTS][2];
-    uint32_t ah[SB][2], al[SB][2];
-    auto mfma_group = [&]() {
+    // exact fold of the short FP32 MFMA block into FP64 totals (FP32 path)
+    auto fold = [&]() {
 #pragma unroll
-        for (int sb = 0; sb < SB; ++sb) {
-            const shortx4 Ah = bf16x4_of(ah[sb][0], ah[sb][1]), Al = bf16x4_of(al[sb][0], al[sb][1]);
+        for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
-                const shortx4 Bhr = bf16x4_of(bhr[s][0], bhr[s][1]), Blr = bf16x4_of(blr[s][0], blr[s][1]);
-                const shortx4 Bhi = bf16x4_of(bhi[s][0], bhi[s][1]), Bli = bf16x4_of(bli[s][0], bli[s][1]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    tot_r[sb][s][i] += (double)acc_r[sb][s][i];
+                    tot_i[sb][s][i] += (double)acc_i[sb][s][i];
+                }
+                acc_r[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+                acc_i[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+    };
+
+    // BF: packed split-BF16 operands of one 16-pair MFMA group (two units).
+    // k = 4*kk + j; j = 0, 1 come from the first unit (x0), j = 2, 3 from the
+    // second (passed in).
+    uint32_t x0hr[SLOTS], x0lr[SLOTS], x0hi[SLOTS], x0li[SLOTS], x0ah[SB], x0al[SB];
+    auto mfma_group = [&](const uint32_t (&hr)[SLOTS], const uint32_t (&lr)[SLOTS], const uint32_t (&hi)[SLOTS],
+                          const uint32_t (&li)[SLOTS], const uint32_t (&ah)[SB], const uint32_t (&al)[SB]) {
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) {
+            const shortx4 Ah = bf16x4_of(x0ah[sb], ah[sb]), Al = bf16x4_of(x0al[sb], al[sb]);
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const shortx4 Bhr = bf16x4_of(x0hr[s], hr[s]), Blr = bf16x4_of(x0lr[s], lr[s]);
+                const shortx4 Bhi = bf16x4_of(x0hi[s], hi[s]), Bli = bf16x4_of(x0li[s], li[s]);
                 // hi*lo + lo*hi first, then hi*hi, into one FP32 accumulator
                 acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Blr, acc_r[sb][s], 0, 0, 0);
                 acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Bli, acc_i[sb][s], 0, 0, 0);
@@ -248,12 +271,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             }
         }
     };
+    int units_done = 0;   // units contracted so far (fold cadence; BF group parity)
 
-    auto chunk_body = [&](int c, const float4* R, const uint32_t* T, auto half_tag) {
-        constexpr int H = decltype(half_tag)::value;
-        const int npp = chunk_npp[c];
-        // W = Vx * Vy: item = (term, qx) -> 8 lines
-        for (int i = tid; i < kChunk * npp * 4; i += 256) {
+    auto chunk_body = [&](int c, const float4* R, const uint32_t* T) {
+        const int4 ch = chunks[c];
+        const int nu = ch.y;
+        const int npp = ch.z;
+        // W = Vx * Vy: item = (term, qx) -> 8 lines.  The thread index is
+        // re-read (not kept live across the loop) to spare a register.
+        int i0 = threadIdx.x;
+        asm volatile("" : "+v"(i0));
+        for (int i = i0; i < nu * kChunk * npp * 4; i += 256) {
             const int ptl = i >> 2, xq = i & 3;
             const float2 vx = reinterpret_cast<const float2*>(R + ptl * kParts)[xq];
             const float4* yr = R + ptl * kParts + 2;
@@ -266,12 +294,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             }
         }
         barrier_lds();
-        // G of one component pair for this lane's 2 lines x QZL q_z values,
-        // G = sum_t W_t(line) Vz_t(qz).  The first term initialises G; the
-        // slices of term t+1 are read from LDS while the FMAs of term t run.
-        auto gen = [&](int pair, float (&gr)[SLOTS], float (&gi)[SLOTS]) {
-            const float2* wp = Wl + (pair * npp) * kWStride + wave * 8 + 2 * lpair;
-            const float2* zp = reinterpret_cast<const float2*>(R + (pair * npp) * kParts + 6) + zgrp * QZL;
+        // G of one component pair (index p in the chunk) for this lane's 2
+        // lines x QZL q_z values, G = sum_t W_t(line) Vz_t(qz).  The first term
+        // initialises G; in the prefetching variant the slices of term t+1 are
+        // read from LDS while the FMAs of term t run.
+        auto gen = [&](int p, float (&gr)[SLOTS], float (&gi)[SLOTS]) {
+            // 24-bit index arithmetic: keeps the compiler from forming 64-bit
+            // multiply-adds whose unused high half may name a register with a
+            // load still in flight (which would make it wait for that load)
+            const int pt = __umul24(p, npp);
+            const float2* wp = Wl + (__umul24(pt, kWStride) + wave * 8 + 2 * lpair);
+            const float2* zp = reinterpret_cast<const float2*>(R) + (__umul24(pt, 2 * kParts) + 12 + zgrp * QZL);
             auto load = [&](int t, float4& w, float4 (&zz)[QZL / 2]) {
                 w = *reinterpret_cast<const float4*>(wp + t * kWStride);
 #pragma unroll
@@ -322,90 +355,91 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
                 }
             }
         };
-        // two MFMA k-steps of 4 pairs each; lane (kk, ln) handles pair 4*step + kk
-        float gr[2][SLOTS], gi[2][SLOTS];
-        uint32_t a_op[2][SB];
+        for (int u = 0; u < nu; ++u) {
+            // two MFMA k-steps of 4 pairs each; lane (kk, ln) handles pair 4*step + kk of the unit
+            float gr[2][SLOTS], gi[2][SLOTS];
+            uint32_t a_op[2][SB];
 #pragma unroll
-        for (int step = 0; step < kChunk / 4; ++step) {
-            const int pair = step * 4 + kk;
+            for (int step = 0; step < kChunk / 4; ++step) {
+                const int p = u * kChunk + step * 4 + kk;
 #pragma unroll
-            for (int sb = 0; sb < SB; ++sb) a_op[step][sb] = T[pair * SW + sb * 16 + ln];
-            gen(pair, gr[step], gi[step]);
-            if constexpr (!BF) {
+                for (int sb = 0; sb < SB; ++sb) a_op[step][sb] = T[p * SW + sb * 16 + ln];
+                gen(p, gr[step], gi[step]);
+                if constexpr (!BF) {
 #pragma unroll
-                for (int sb = 0; sb < SB; ++sb)
+                    for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
-                    for (int s = 0; s < SLOTS; ++s) {
-                        const float a = __uint_as_float(a_op[step][sb]);
-                        acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gr[step][s], acc_r[sb][s], 0, 0, 0);
-                        acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gi[step][s], acc_i[sb][s], 0, 0, 0);
-                    }
+                        for (int s = 0; s < SLOTS; ++s) {
+                            const float a = __uint_as_float(a_op[step][sb]);
+                            acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gr[step][s], acc_r[sb][s], 0, 0, 0);
+                            acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gi[step][s], acc_i[sb][s], 0, 0, 0);
+                        }
+                }
             }
-        }
-        if constexpr (BF) {
-            // k-steps j = 2H, 2H+1 of the group: split G and pack Tp halves
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                split_bf16(gr[0][s], gr[1][s], bhr[s][H], blr[s][H]);
-                split_bf16(gi[0][s], gi[1][s], bhi[s][H], bli[s][H]);
-            }
-#pragma unroll
-            for (int sb = 0; sb < SB; ++sb) {
-                ah[sb][H] = (a_op[0][sb] & 0xffffu) | (a_op[1][sb] << 16);
-                al[sb][H] = (a_op[0][sb] >> 16) | (a_op[1][sb] & 0xffff0000u);
-            }
-        }
-        if constexpr (BF) {
-            if (H == 1) mfma_group();
-        } else if ((c + 1) % kTiles == 0 || c + 1 == n_chunks) {
-            // exact fold of the short FP32 MFMA block into FP64 totals
-#pragma unroll
-            for (int sb = 0; sb < SB; ++sb)
+            ++units_done;
+            if constexpr (BF) {
+                // split G and pack the Tp halves of this unit's two k-steps
+                uint32_t hr[SLOTS], lr[SLOTS], hi[SLOTS], li[SLOTS], ah[SB], al[SB];
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        tot_r[sb][s][i] += (double)acc_r[sb][s][i];
-                        tot_i[sb][s][i] += (double)acc_i[sb][s][i];
-                    }
-                    acc_r[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    acc_i[sb][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    split_bf16(gr[0][s], gr[1][s], hr[s], lr[s]);
+                    split_bf16(gi[0][s], gi[1][s], hi[s], li[s]);
                 }
+#pragma unroll
+                for (int sb = 0; sb < SB; ++sb) {
+                    ah[sb] = (a_op[0][sb] & 0xffffu) | (a_op[1][sb] << 16);
+                    al[sb] = (a_op[0][sb] >> 16) | (a_op[1][sb] & 0xffff0000u);
+                }
+                if (units_done & 1) {   // first unit of a group: keep it
+#pragma unroll
+                    for (int s = 0; s < SLOTS; ++s) {
+                        x0hr[s] = hr[s]; x0lr[s] = lr[s]; x0hi[s] = hi[s]; x0li[s] = li[s];
+                    }
+#pragma unroll
+                    for (int sb = 0; sb < SB; ++sb) {
+                        x0ah[sb] = ah[sb]; x0al[sb] = al[sb];
+                    }
+                } else {
+                    mfma_group(hr, lr, hi, li, ah, al);
+                }
+            } else {
+                if ((units_done & (kFoldUnits - 1)) == 0) fold();
+            }
         }
     };
 
     if (n_chunks > 0) {
         load_rows(0);
-        issue_tp(0, lds_addr(T0));
-        issue_dma(lds_addr(R0));
+        issue_dma(0, lds_addr(R0), lds_addr(T0));
         if (n_chunks > 1) load_rows(1);
     }
     // two chunks per iteration so each buffer is a distinct LDS object
     for (int c = 0; c < n_chunks; c += 2) {
         barrier_dma();                                  // chunk c landed in R0/T0; Wl and R1 are free
         if (c + 1 < n_chunks) {
-            issue_tp(c + 1, lds_addr(T1));
-            issue_dma(lds_addr(R1));
+            issue_dma(c + 1, lds_addr(R1), lds_addr(T1));
             if (c + 2 < n_chunks) load_rows(c + 2);
         }
-        chunk_body(c, R0, T0, std::integral_constant<int, 0>{});
+        chunk_body(c, R0, T0);
         if (c + 1 >= n_chunks) break;
         barrier_dma();                                  // chunk c+1 landed in R1/T1; Wl and R0 are free
         if (c + 2 < n_chunks) {
-            issue_tp(c + 2, lds_addr(T0));
-            issue_dma(lds_addr(R0));
+            issue_dma(c + 2, lds_addr(R0), lds_addr(T0));
             if (c + 3 < n_chunks) load_rows(c + 3);
         }
-        chunk_body(c + 1, R1, T1, std::integral_constant<int, 1>{});
+        chunk_body(c + 1, R1, T1);
     }
     if constexpr (BF) {
-        if (n_chunks & 1) {   // last group holds one chunk: k-steps 2, 3 are zero
+        if (units_done & 1) {   // last group holds one unit: k-steps 2, 3 are zero
+            uint32_t z[SLOTS], za[SB];
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) bhr[s][1] = blr[s][1] = bhi[s][1] = bli[s][1] = 0u;
+            for (int s = 0; s < SLOTS; ++s) z[s] = 0u;
 #pragma unroll
-            for (int sb = 0; sb < SB; ++sb) ah[sb][1] = al[sb][1] = 0u;
-            mfma_group();
+            for (int sb = 0; sb < SB; ++sb) za[sb] = 0u;
+            mfma_group(z, z, z, z, za, za);
         }
+    } else {
+        if (units_done & (kFoldUnits - 1)) fold();
     }
 
     // epilogue: lane holds states sb*16 + 4*kk + i for the q values of column ln
@@ -496,14 +530,14 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
 }
 
 template <int SB, int QZL, int WPE, bool BF>
-static hipError_t launch_grid_t(const float2* V, int vstride, const int4* terms, const int* coff,
-                                const int* cnpp, int n_chunks, const uint32_t* Tp, const int n[3],
-                                int n_states, float2* f, float* f2, hipStream_t st) {
+static hipError_t launch_grid_t(const float2* V, int vstride, const int4* terms, const int4* chunks,
+                                int n_chunks, const uint32_t* Tp, const int n[3], int n_states, float2* f,
+                                float* f2, hipStream_t st) {
     const int3 nn = make_int3(n[0], n[1], n[2]);
     const int3 nt = make_int3((n[0] + 3) / 4, (n[1] + 7) / 8, (n[2] + 4 * QZL - 1) / (4 * QZL));
     const long long blocks = (long long)nt.x * nt.y * nt.z;
     hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE, BF>), dim3((unsigned)blocks), dim3(256), 0, st, V, vstride,
-                       terms, coff, cnpp, n_chunks, Tp, nn, nt, n_states, f, f2);
+                       terms, chunks, n_chunks, Tp, nn, nt, n_states, f, f2);
     return hipGetLastError();
 }
 
@@ -516,9 +550,9 @@ int vtable_stride(const int n[3]) {
 }
 
 hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride,
-                       const int4* terms, const int* coff, const int* cnpp, int n_chunks,
-                       const float* Tp, const uint32_t* tp_bf, const int n[3], int n_states,
-                       float2* f, float* f2, hipStream_t st) {
+                       const int4* terms, const int4* chunks, int n_chunks, const float* Tp,
+                       const uint32_t* tp_bf, const int n[3], int n_states, float2* f, float* f2,
+                       hipStream_t st) {
     if (precision != 0 && precision != 1) return hipErrorInvalidValue;
     if (vstride < vtable_stride(n)) return hipErrorInvalidValue;
     static int variant = -1;
@@ -528,14 +562,13 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
     }
     const uint32_t* tp32 = reinterpret_cast<const uint32_t*>(Tp);
 #define SCFF_GRID(SB_, QZL_, WPE_, BF_) \
-    return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, terms, coff, cnpp, n_chunks, BF_ ? tp_bf : tp32, n, \
+    return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, terms, chunks, n_chunks, BF_ ? tp_bf : tp32, n, \
                                                n_states, f, f2, st)
     if (precision == 1) {
         if (state_blocks == 1) {
             if (variant == 1) SCFF_GRID(1, 2, 2, true);
             SCFF_GRID(1, 4, 2, true);
         }
-        if (variant == 1) SCFF_GRID(2, 4, 2, true);
         SCFF_GRID(2, 2, 2, true);
     }
     if (state_blocks == 1) {

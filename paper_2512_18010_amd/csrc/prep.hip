@@ -298,13 +298,15 @@ __global__ void vkeys_kernel(const int* __restrict__ nk, const int* __restrict__
     }
 }
 
-__global__ void chunk_kernel(const int* __restrict__ order, const int4* __restrict__ vinfo, int nv,
-                             int n_chunks, int* __restrict__ cnpp, int* __restrict__ csize) {
+__global__ void unit_kernel(const int* __restrict__ order, const int4* __restrict__ vinfo, int nv,
+                            int n_chunks, int* __restrict__ cnpp, int* __restrict__ csize,
+                            int* __restrict__ uhist) {
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks; c += gridDim.x * blockDim.x) {
         const int o = c * kChunk;
         const int npp = o < nv ? max(1, vinfo[order[o]].z) : 1;
         cnpp[c] = npp;
         csize[c] = kChunk * npp;
+        atomicAdd(&uhist[npp], 1);   // units per term count (units are sorted by it, longest first)
     }
 }
 
@@ -473,22 +475,55 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
         CK(alloc(w.tmp2, sort_bytes + 256));
         CK(hipcub::DeviceRadixSort::SortPairs(w.tmp2.p, sort_bytes, key_in, key_out, val_in, val_out, NV, 0, 4, st));
     }
+    // units of kChunk sorted virtual pairs, each padded to its first pair's term count
     const int n_vpairs = ((NVA + kChunk - 1) / kChunk) * kChunk;
-    const int n_chunks = n_vpairs / kChunk;
+    const int n_chunks = n_vpairs / kChunk;   // units
     CK(alloc(w.cnpp, (size_t)n_chunks * sizeof(int)));
     CK(alloc(w.csize, (size_t)n_chunks * sizeof(int)));
     CK(alloc(w.coff, (size_t)n_chunks * sizeof(int)));
-    hipLaunchKernelGGL(chunk_kernel, dim3(blocks_for(n_chunks, 256)), dim3(256), 0, st, (const int*)val_out,
-                       (const int4*)w.vinfo.p, NV, n_chunks, (int*)w.cnpp.p, (int*)w.csize.p);
+    CK(alloc(w.uhist, 16 * sizeof(int)));
+    CK(hipMemsetAsync(w.uhist.p, 0, 16 * sizeof(int), st));
+    hipLaunchKernelGGL(unit_kernel, dim3(blocks_for(n_chunks, 256)), dim3(256), 0, st, (const int*)val_out,
+                       (const int4*)w.vinfo.p, NV, n_chunks, (int*)w.cnpp.p, (int*)w.csize.p, (int*)w.uhist.p);
     CK(hipGetLastError());
     size_t tmp3 = 0;
     CK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp3, (int*)w.csize.p, (int*)w.coff.p, n_chunks, st));
     CK(alloc(w.tmp3, tmp3 + 256));
     CK(hipcub::DeviceScan::ExclusiveSum(w.tmp3.p, tmp3, (int*)w.csize.p, (int*)w.coff.p, n_chunks, st));
-    int lastc[2];
+    int lastc[2], uhist[16];
     CK(hipMemcpyAsync(&lastc[0], (int*)w.coff.p + n_chunks - 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(&lastc[1], (int*)w.csize.p + n_chunks - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(uhist, w.uhist.p, 16 * sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
+    // grid-kernel chunks: runs of consecutive units with equal npp (units come
+    // longest first), at most kMaxUnitsPerChunk units and kMaxChunkTerms terms.
+    // Entry = (first unit, units, npp, first term slot); the slot offsets of
+    // the units follow from the same counts (kChunk * npp slots per unit).
+    std::vector<int>& ch = w.chunk_host;
+    ch.clear();
+    {
+        int u0 = 0;
+        long long slot = 0;
+        for (int v = kMaxTermsPerPair; v >= 1; --v) {
+            const int cnt = uhist[v];
+            int um = kMaxChunkTerms / (kChunk * v);
+            if (um > kMaxUnitsPerChunk) um = kMaxUnitsPerChunk;
+            for (int k = 0; k < cnt; k += um) {
+                const int nu = cnt - k < um ? cnt - k : um;
+                ch.push_back(u0 + k);
+                ch.push_back(nu);
+                ch.push_back(v);
+                ch.push_back((int)slot);
+                slot += (long long)nu * kChunk * v;
+            }
+            u0 += cnt;
+        }
+        // every unit has 1 <= npp <= kMaxTermsPerPair; slots agree with the device scan
+        if (u0 != n_chunks || slot != (long long)lastc[0] + lastc[1]) return hipErrorUnknown;
+    }
+    const int n_grid_chunks = (int)(ch.size() / 4);
+    CK(alloc(w.chunks, ch.size() * sizeof(int)));
+    CK(hipMemcpyAsync(w.chunks.p, ch.data(), ch.size() * sizeof(int), hipMemcpyHostToDevice, st));
     const long long nslots = (long long)lastc[0] + lastc[1];
     CK(alloc(w.slots, (size_t)nslots * sizeof(int4)));
     CK(alloc(w.tp32, (size_t)n_vpairs * SW * sizeof(float)));
@@ -519,7 +554,8 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
                        (const int*)w.newid.p);
     CK(hipGetLastError());
     res.n_vpairs = n_vpairs;
-    res.n_chunks = n_chunks;
+    res.n_units = n_chunks;
+    res.n_chunks = n_grid_chunks;
     res.n_slots = nslots;
     res.n_rows = nrows_used + 1;
     res.state_blocks = SW / kStateBlock;

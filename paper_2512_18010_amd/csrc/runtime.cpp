@@ -17,9 +17,9 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
                          const double qmin[3], const double dq[3], float2* V, hipStream_t st);
 int vtable_stride(const int n[3]);
 hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride,
-                       const int4* terms, const int* coff, const int* cnpp, int n_chunks,
-                       const float* Tp, const uint32_t* tp_bf, const int n[3], int n_states,
-                       float2* f, float* f2, hipStream_t st);
+                       const int4* terms, const int4* chunks, int n_chunks, const float* Tp,
+                       const uint32_t* tp_bf, const int n[3], int n_states, float2* f, float* f2,
+                       hipStream_t st);
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
                          const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
                          int n_states, float2* f, float* f2, hipStream_t st);
@@ -360,6 +360,7 @@ int scff_query(scff_ctx* c, scff_info* info) {
         info->pairs_kept = c->pres.pairs_kept;
         info->prim_comp_pairs_kept = c->pres.terms_kept;
         info->work_chunks = c->pres.n_chunks;
+        info->work_units = c->pres.n_units;
     }
     info->device_bytes = c->used;
     return ok();
@@ -390,8 +391,8 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
     if ((rc = record(c, EV_GRID0, st))) return rc;
     const PrepResult& p = c->pres;
     rc = hip_check(launch_grid(p.state_blocks, precision, (const float2*)c->d_vtab.p, c->vtab_stride,
-                               (const int4*)c->prep.slots.p, (const int*)c->prep.coff.p,
-                               (const int*)c->prep.cnpp.p, p.n_chunks, (const float*)c->prep.tp32.p,
+                               (const int4*)c->prep.slots.p, (const int4*)c->prep.chunks.p, p.n_chunks,
+                               (const float*)c->prep.tp32.p,
                                (const uint32_t*)c->prep.tpbf.p, g->n, c->n_states, df, df2, st),
                    "grid kernel launch");
     if (rc) return rc;
@@ -459,7 +460,7 @@ int scff_eval_points(scff_ctx* c, int n_q, const double* q, int precision, float
     }
     const PrepResult& p = c->pres;
     rc = hip_check(launch_points(p.state_blocks, (const VRowDev*)c->prep.rows.p, (const int4*)c->prep.slots.p,
-                                 (const int*)c->prep.coff.p, (const int*)c->prep.cnpp.p, p.n_chunks,
+                                 (const int*)c->prep.coff.p, (const int*)c->prep.cnpp.p, p.n_units,
                                  (const float*)c->prep.tp32.p, (const double*)c->d_q.p, n_q, c->n_states,
                                  df, df2, st),
                    "points kernel launch");
@@ -484,7 +485,7 @@ int scff_export_vtensors(scff_ctx* c, const scff_grid* g, long long* n_terms_out
     if ((rc = build_vtables(c, g, st))) return rc;
     const int SW = kStateBlock * p.state_blocks;
     std::vector<float2> V((size_t)c->vtab_rows * c->vtab_stride);
-    std::vector<int> slots((size_t)p.n_slots * 4), coff(p.n_chunks), cnpp(p.n_chunks);
+    std::vector<int> slots((size_t)p.n_slots * 4), coff(p.n_units), cnpp(p.n_units);
     std::vector<float> tp32((size_t)p.n_vpairs * SW);
     struct Cp {
         void* dst;
@@ -500,7 +501,7 @@ int scff_export_vtensors(scff_ctx* c, const scff_grid* g, long long* n_terms_out
     if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
     long long t = 0;
     float* outs[3] = {vx, vy, vz};
-    for (int ch = 0; ch < p.n_chunks; ++ch) {
+    for (int ch = 0; ch < p.n_units; ++ch) {
         const int npp = cnpp[ch];
         for (int j = 0; j < kChunk; ++j)
             for (int k = 0; k < npp; ++k) {

@@ -6,6 +6,7 @@ in the launch configuration the benchmark times and compared on a seeded
 sample of grid points (plus the grid's |f|^2 maximum), with the tolerance
 of the precision (peak-normalised |f|^2: 1e-6 FP32, 1e-4 split-BF16).
 """
+import dataclasses
 import os
 import sys
 
@@ -108,12 +109,25 @@ def test_config3_sampled_screened(eng, oracle_mod, precision):
     sampled_parity(eng, oracle_mod, 3, precision, 48, eps=1e-9)
 
 
+def few_primitive(mol):
+    """The molecule with shells cut to 1 or 2 primitives (alternating), so
+    component pairs have 1, 2 or 4 terms."""
+    keep = [1 + (i % 2) for i in range(mol.n_shells)]
+    off = np.concatenate([[0], np.cumsum(mol.shell_nprim)])
+    idx = np.concatenate([np.arange(off[i], off[i] + k) for i, k in enumerate(keep)])
+    return dataclasses.replace(mol, shell_nprim=np.array(keep, np.int32), exps=mol.exps[idx].copy(),
+                               coefs=mol.coefs[idx].copy())
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_odd_and_even_chunk_counts(eng, oracle_mod, precision):
-    """The split-BF16 path pairs chunks into 16-pair MFMA groups; an odd
-    number of chunks leaves a half group.  Screening thresholds are swept
-    until both parities have been seen, each checked against the oracle."""
+def test_odd_and_even_unit_counts(eng, oracle_mod, precision):
+    """Packed pairs come in units of 8; the split-BF16 path pairs units into
+    16-pair MFMA groups (across chunk boundaries), so an odd unit count leaves
+    a half group, and the FP32 path folds every 4 units.  Screening thresholds
+    are swept until both parities have been seen, each checked against the
+    oracle; chunks of several units (pairs with few terms) occur in every case."""
     W = wl.make_config(0)
+    W.mol = few_primitive(W.mol)
     W.grid = wl.Grid(n=(8, 9, 17), qmin=(-5.0,) * 3, qmax=(5.0,) * 3)
     ref = oracle_mod.eval_grid(W.mol, W.T, W.grid, n_threads=NTH)
     seen = set()
@@ -121,13 +135,16 @@ def test_odd_and_even_chunk_counts(eng, oracle_mod, precision):
         eng.load_molecule(W.mol)
         eng.load_transitions(W.T)
         eng.set_options(eps, 1.0)
-        nch = eng.query()["work_chunks"]
-        if nch % 2 in seen:
+        info = eng.query()
+        nu, nch = info["work_units"], info["work_chunks"]
+        assert nch < nu, (nch, nu)   # 1-4 term pairs: some chunk holds several units
+        if nu % 2 in seen:
             continue
-        seen.add(nch % 2)
+        seen.add(nu % 2)
         f, f2 = eng.eval_grid_host(W.grid, precision)
         e = errors(f, ref)
-        log(f"[chunks={nch} eps={eps:g}] {precision}: peak-normalised |f|^2 err {e['f2_peak_norm'].max():.3e}")
+        log(f"[units={nu} chunks={nch} eps={eps:g}] {precision}: peak-normalised |f|^2 err "
+            f"{e['f2_peak_norm'].max():.3e}")
         # the screening error is part of the budget here; eps <= 1e-8 keeps it well below 1e-6
         assert e["f2_peak_norm"].max() <= TOL_F2[precision]
         if len(seen) == 2:
