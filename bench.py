@@ -34,10 +34,14 @@ PEAK_HBM = 8.0e12
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel source with comments and blank lines dropped (a
+    comment edit does not invalidate measured counters; a code edit does)."""
+    import re
     h = hashlib.sha256()
-    for name in ("kernels.hip",):
-        with open(os.path.join(ROOT, "paper_2512_18010_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+    for name in ("kernels.hip", "engine.h"):
+        with open(os.path.join(ROOT, "paper_2512_18010_amd", "csrc", name)) as fh:
+            text = re.sub(r"//[^\n]*", "", fh.read())
+        h.update("\n".join(l.rstrip() for l in text.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
 
@@ -306,10 +310,10 @@ def main():
                                              log=lambda m: print(m, file=sys.stderr, flush=True)))
 
     if args.copy_mib > 0:
-        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")   # fill: writes N MiB
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)                                                  # reads and writes N MiB
         torch.cuda.synchronize()
         del src, dst
 

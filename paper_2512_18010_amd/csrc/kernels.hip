@@ -15,15 +15,16 @@
 //    polynomial) and rounded once to FP32: the polynomial can cancel, and
 //    FP32 evaluation would leave errors proportional to its bound rather
 //    than to its value.
-//  * grid_kernel: one workgroup per q-tile of (WAVES x 8) lines (qx,qy) x
-//    (4*QZL) values of qz.  Per chunk of 8 component pairs the tile's
+//  * grid_kernel: one workgroup per q-tile of 4 x 8 lines (qx,qy) x
+//    (4*QZL) values of qz.  Per chunk of 8-32 component pairs the tile's
 //    W = Vx*Vy (per line) and Vz (per qz) slices are staged in LDS; every
 //    lane then forms G for 2 lines x QZL qz values of one component pair on
-//    the VALU and feeds it, still in registers, as the B operand of
-//    v_mfma_f32_16x16x4_f32 (A = Tp, 16 states x 4 pairs).  Accumulation is
-//    blocked: MFMA sums run over kFoldChunks chunks and are then added into
-//    a second set of FP32 accumulators, which bounds the rounding error of
-//    the long pair sum.
+//    the VALU and feeds it, still in registers, to the matrix cores.  FP32:
+//    v_mfma_f32_16x16x4_f32 (A = Tp, 16 states x 4 pairs), with the FP32
+//    MFMA sums of every 32 pairs folded into FP64 totals, which bounds the
+//    rounding error of the long, cancelling pair sum.  Split-BF16 (template
+//    flag BF): G and Tp as hi + lo BF16 halves, hi*lo + lo*hi + hi*hi on
+//    v_mfma_f32_16x16x16_bf16 with FP32 accumulation.
 //  * points_kernel: the same sum at arbitrary points (VALU only), V
 //    evaluated on the fly.
 #include <hip/hip_runtime.h>
@@ -55,7 +56,7 @@ __device__ __forceinline__ shortx4 bf16x4_of(uint32_t lo_k, uint32_t hi_k) {
     return __builtin_bit_cast(shortx4, uintx2{lo_k, hi_k});
 }
 
-constexpr int kFoldChunks = 32;   // 256 component pairs per MFMA accumulation block
+constexpr int kFoldChunks = 32;   // points kernel: units (256 pairs) per FP32 partial sum
 
 // ---------------------------------------------------------------- 1D tables
 
