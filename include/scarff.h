@@ -23,12 +23,16 @@
  *    caller pointer is retained after a call returns.
  *  - Errors: every int-returning call returns SCFF_OK (0) or a negative
  *    code; scff_last_error() then describes the failure.  A failed call
- *    leaves the context as it was and writes no output.
+ *    leaves the context as it was and writes no output, with one exception:
+ *    scff_load_molecule failing while it copies the new tables to the
+ *    device (out of memory or budget) leaves no molecule loaded.
  *  - Threading: a context is not re-entrant; use one context per thread or
  *    serialise calls.  The server (scff_server_*) is thread-safe.
  *  - Device: one context drives one HIP device.  Device output pointers
  *    must be device memory of that device (e.g. from torch.empty(...,
  *    device='cuda')); the call is then asynchronous on the given stream.
+ *    Successive calls on one context may use different streams: each call's
+ *    device work is ordered after the context's previous asynchronous work.
  */
 #ifndef SCARFF_H
 #define SCARFF_H
@@ -108,7 +112,10 @@ void scff_destroy(scff_ctx* ctx);
  *                contracted Cartesian component to unit norm; 0: primitives
  *                are unit-normalised, the d_k are used as given.
  *   nbf_out      (may be NULL) number of Cartesian basis functions.
- * Invalidates previously loaded transitions if nbf changes.
+ * Invalidates previously loaded transitions if nbf changes.  Invalid input is
+ * rejected before any device state changes (SCFF_EINVAL); if copying the
+ * tables to the device fails (SCFF_ENOMEM, SCFF_EDEVICE) the previous
+ * molecule is gone as well and the context has no molecule loaded.
  */
 int scff_load_molecule(scff_ctx* ctx, int n_atoms, const double* xyz_bohr, int n_shells,
                        const int* shell_atom, const int* shell_l, const int* shell_nprim,
@@ -126,7 +133,8 @@ int scff_load_transitions(scff_ctx* ctx, int n_states, const double* T);
  * Same as scff_load_transitions with T already in device memory of the
  * context's device: T_dev [n_states][nbf][nbf] FP64, copied on hip_stream
  * (asynchronous; the caller keeps T_dev valid until the stream reaches the
- * copy).  T_dev is not checked for non-finite entries.
+ * copy).  Later calls on this context, on any stream, are ordered after
+ * the copy.  T_dev is not checked for non-finite entries.
  */
 int scff_load_transitions_device(scff_ctx* ctx, int n_states, const double* T_dev, void* hip_stream);
 

@@ -29,6 +29,15 @@ ERROR_NAMES = {0: "SCFF_OK", -1: "SCFF_EINVAL", -2: "SCFF_ENOMEM", -3: "SCFF_EDE
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2512_18010_amd.build` "
                       "(the engine has no non-HIP fallback)")
+# PyTorch ships its own HIP and HSA runtimes under the same sonames as the
+# system ones the library links against.  Whichever is loaded first serves the
+# whole process; if the library came first, PyTorch would load a second copy
+# of each and find no GPU.  Load PyTorch's first when it is installed, so one
+# HIP runtime serves both PyTorch (device memory, streams) and this library.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 
 P = ctypes.POINTER

@@ -123,8 +123,10 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
 // ---- runtime.cpp ----
 // Thread-local message returned by scff_last_error().
 void set_error(const std::string& msg);
-// Pack and upload a context's problem for grid g; *bytes_needed receives the
+// Pack and upload a context's problem for grid g on stream st and wait for
+// it: when this returns, the precompute is complete in device memory, so an
+// evaluation on any other stream may use it.  *bytes_needed receives the
 // device bytes an evaluation on g will hold in total.
-int ctx_prepare(scff_ctx* c, const scff_grid* g, size_t* bytes_needed);
+int ctx_prepare(scff_ctx* c, const scff_grid* g, hipStream_t st, size_t* bytes_needed);
 
 }  // namespace scff

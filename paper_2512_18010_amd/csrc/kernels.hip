@@ -30,7 +30,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <cstdlib>
 #include <type_traits>
 
 #include "engine.h"
@@ -556,29 +555,17 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
                        hipStream_t st) {
     if (precision != 0 && precision != 1) return hipErrorInvalidValue;
     if (vstride < vtable_stride(n)) return hipErrorInvalidValue;
-    static int variant = -1;
-    if (variant < 0) {
-        const char* e = getenv("SCFF_GRID_VARIANT");
-        variant = e ? atoi(e) : 0;
-    }
     const uint32_t* tp32 = reinterpret_cast<const uint32_t*>(Tp);
 #define SCFF_GRID(SB_, QZL_, WPE_, BF_) \
     return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, terms, chunks, n_chunks, BF_ ? tp_bf : tp32, n, \
                                                n_states, f, f2, st)
+    // <=16 states: 4 q_z per lane (8 q values); 17..32 states: 2 q_z per lane,
+    // so the accumulators of both precisions fit 2 waves per SIMD
     if (precision == 1) {
-        if (state_blocks == 1) {
-            if (variant == 1) SCFF_GRID(1, 2, 2, true);
-            SCFF_GRID(1, 4, 2, true);
-        }
+        if (state_blocks == 1) SCFF_GRID(1, 4, 2, true);
         SCFF_GRID(2, 2, 2, true);
     }
-    if (state_blocks == 1) {
-        if (variant == 1) SCFF_GRID(1, 4, 1, false);
-        if (variant == 3) SCFF_GRID(1, 2, 3, false);
-        if (variant == 4) SCFF_GRID(1, 2, 2, false);
-        SCFF_GRID(1, 4, 2, false);
-    }
-    if (variant == 1) SCFF_GRID(2, 2, 1, false);
+    if (state_blocks == 1) SCFF_GRID(1, 4, 2, false);
     SCFF_GRID(2, 2, 2, false);
 #undef SCFF_GRID
 }

@@ -58,6 +58,10 @@ struct scff_ctx {
     bool timing = false;
     hipEvent_t ev[EV_N] = {};
     bool ev_recorded = false, ev_prep = false;
+    // stream ordering: the end of the last asynchronous work on the context
+    hipEvent_t order_ev = nullptr;
+    hipStream_t order_st = nullptr;
+    bool order_pending = false;
 };
 
 namespace {
@@ -120,6 +124,35 @@ int upload_sync(scff_ctx* c, DeviceBuffer& b, const void* src, size_t bytes) {
 }
 
 int set_device(scff_ctx* c) { return hip_check(hipSetDevice(c->device), "hipSetDevice"); }
+
+// A context may be driven from several streams in turn.  Work that depends on
+// the context's device state (precompute results, tables, T) is ordered after
+// the context's previous asynchronous work with an event, so a call on stream
+// B never overtakes a call still running on stream A.
+int order_after(scff_ctx* c, hipStream_t st) {
+    if (!c->order_pending || st == c->order_st) return SCFF_OK;
+    return hip_check(hipStreamWaitEvent(st, c->order_ev, 0), "stream ordering");
+}
+int order_mark(scff_ctx* c, hipStream_t st) {
+    int rc;
+    if (!c->order_ev &&
+        (rc = hip_check(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming), "event create")))
+        return rc;
+    if ((rc = hip_check(hipEventRecord(c->order_ev, st), "event record"))) return rc;
+    c->order_st = st;
+    c->order_pending = true;
+    return SCFF_OK;
+}
+// host-side wait for the context's asynchronous work (before the host
+// rewrites device buffers that it may still read)
+int order_drain(scff_ctx* c) {
+    if (!c->order_pending) return SCFF_OK;
+    int rc = hip_check(hipEventSynchronize(c->order_ev), "event sync");
+    if (rc == SCFF_OK) c->order_pending = false;
+    return rc;
+}
+// st has been synchronised after order_after(c, st): everything is done
+void order_done(scff_ctx* c) { c->order_pending = false; }
 
 int record(scff_ctx* c, int which, hipStream_t st) {
     if (!c->timing) return SCFF_OK;
@@ -223,11 +256,17 @@ int copy_out(const float2* df, float* f, const float* df2, float* f2, size_t nou
 
 // Precompute a context's problem and report the device bytes an evaluation
 // on g holds in total (precompute buffers, 1D tables, output staging).
-int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, size_t* bytes_needed) {
+int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, hipStream_t st, size_t* bytes_needed) {
     int rc = validate_grid(g);
     if (rc) return rc;
     if ((rc = set_device(c))) return rc;
-    if ((rc = ensure_prepared(c, nullptr))) return rc;
+    if ((rc = order_after(c, st))) return rc;
+    if ((rc = ensure_prepared(c, st))) return rc;
+    // the last precompute kernels (row compaction, slot remap) are still in
+    // flight on st: the caller evaluates on another stream, which is not
+    // ordered after this one
+    if ((rc = hip_check(hipStreamSynchronize(st), "precompute sync"))) return rc;
+    order_done(c);
     const size_t npts = (size_t)g->n[0] * g->n[1] * g->n[2];
     const int stride = vtable_stride(g->n);
     *bytes_needed = c->used + (size_t)c->pres.n_rows * stride * sizeof(float2) +
@@ -263,6 +302,7 @@ void scff_destroy(scff_ctx* c) {
     free_all(c);
     for (hipEvent_t& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->order_ev) (void)hipEventDestroy(c->order_ev);
     delete c;
 }
 
@@ -276,7 +316,15 @@ int scff_load_molecule(scff_ctx* c, int n_atoms, const double* xyz, int n_shells
     if (!err.empty()) return fail(SCFF_EINVAL, err);
     int rc;
     if ((rc = set_device(c))) return rc;
-    // upload the molecule tables (small host arrays)
+    // upload the molecule tables (small host arrays).  Once the first table
+    // is overwritten the previous molecule is gone: a failure past that point
+    // leaves the context with no molecule (and no transitions) loaded.
+    if ((rc = order_drain(c))) return rc;   // in-flight work may still read the old tables
+    const bool had_T = c->have_T;
+    const int old_nbf = c->basis.nbf;
+    c->have_mol = false;
+    c->have_T = false;
+    c->prepared = false;
     if ((rc = upload_sync(c, c->d_shells, b.shells.data(), b.shells.size() * sizeof(PrepShell)))) return rc;
     if ((rc = upload_sync(c, c->d_sp, b.sp.data(), b.sp.size() * sizeof(int)))) return rc;
     if ((rc = upload_sync(c, c->d_sp_cp, b.sp_cp.data(), b.sp_cp.size() * sizeof(int)))) return rc;
@@ -288,10 +336,9 @@ int scff_load_molecule(scff_ctx* c, int n_atoms, const double* xyz, int n_shells
     if ((rc = upload_sync(c, c->d_coefs, b.coefs.data(), b.coefs.size() * sizeof(double)))) return rc;
     if ((rc = upload_sync(c, c->d_n1d, b.n1d.data(), b.n1d.size() * sizeof(double)))) return rc;
     if ((rc = upload_sync(c, c->d_cnorm, b.cnorm.data(), b.cnorm.size() * sizeof(double)))) return rc;
-    if (c->have_T && b.nbf != c->basis.nbf) c->have_T = false;
+    c->have_T = had_T && b.nbf == old_nbf;   // T (untouched) still matches the basis size
     c->basis = std::move(b);
     c->have_mol = true;
-    c->prepared = false;
     if (nbf_out) *nbf_out = c->basis.nbf;
     return ok();
 }
@@ -306,6 +353,7 @@ int scff_load_transitions(scff_ctx* c, int n_states, const double* T) {
         if (!std::isfinite(T[i])) return fail(SCFF_EINVAL, "non-finite entry in T");
     int rc;
     if ((rc = set_device(c))) return rc;
+    if ((rc = order_drain(c))) return rc;   // in-flight work may still read the old T
     if ((rc = upload_sync(c, c->d_T, T, n * sizeof(double)))) return rc;
     c->n_states = n_states;
     c->have_T = true;
@@ -321,11 +369,13 @@ int scff_load_transitions_device(scff_ctx* c, int n_states, const double* T_dev,
     int rc;
     if ((rc = set_device(c))) return rc;
     const size_t n = (size_t)n_states * c->basis.nbf * c->basis.nbf;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((rc = order_after(c, st))) return rc;
     if ((rc = dev_reserve(c, c->d_T, n * sizeof(double)))) return rc;
-    if ((rc = hip_check(hipMemcpyAsync(c->d_T.p, T_dev, n * sizeof(double), hipMemcpyDeviceToDevice,
-                                       (hipStream_t)hip_stream),
+    if ((rc = hip_check(hipMemcpyAsync(c->d_T.p, T_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st),
                         "device copy of T")))
         return rc;
+    if ((rc = order_mark(c, st))) return rc;
     c->n_states = n_states;
     c->have_T = true;
     c->prepared = false;
@@ -356,7 +406,12 @@ int scff_query(scff_ctx* c, scff_info* info) {
     if (c->have_mol && c->have_T) {
         int rc;
         if ((rc = set_device(c))) return rc;
-        if ((rc = ensure_prepared(c, nullptr))) return rc;
+        if (!c->prepared) {
+            if ((rc = order_after(c, nullptr))) return rc;
+            if ((rc = ensure_prepared(c, nullptr))) return rc;
+            if ((rc = hip_check(hipStreamSynchronize(nullptr), "precompute sync"))) return rc;
+            order_done(c);
+        }
         info->pairs_kept = c->pres.pairs_kept;
         info->prim_comp_pairs_kept = c->pres.terms_kept;
         info->work_chunks = c->pres.n_chunks;
@@ -375,6 +430,7 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     c->ev_prep = false;
+    if ((rc = order_after(c, st))) return rc;
     if ((rc = ensure_prepared(c, st))) return rc;
     const size_t npts = (size_t)g->n[0] * g->n[1] * g->n[2];
     const size_t nout = npts * (size_t)c->n_states;
@@ -401,6 +457,9 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
     if (!out_on_device) {
         if ((rc = copy_out(df, f, df2, f2, nout, st))) return rc;
         if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
+        order_done(c);
+    } else if ((rc = order_mark(c, st))) {
+        return rc;
     }
     return ok();
 }
@@ -444,6 +503,7 @@ int scff_eval_points(scff_ctx* c, int n_q, const double* q, int precision, float
         if (!std::isfinite(q[i])) return fail(SCFF_EINVAL, "non-finite q");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
+    if ((rc = order_after(c, st))) return rc;
     if ((rc = ensure_prepared(c, st))) return rc;
     if ((rc = dev_reserve(c, c->d_q, (size_t)n_q * 3 * sizeof(double)))) return rc;
     if ((rc = hip_check(hipMemcpyAsync(c->d_q.p, q, (size_t)n_q * 3 * sizeof(double), hipMemcpyHostToDevice, st),
@@ -468,6 +528,7 @@ int scff_eval_points(scff_ctx* c, int n_q, const double* q, int precision, float
     if (!out_on_device && (rc = copy_out(df, f, df2, f2, nout, st))) return rc;
     // the host q array was copied asynchronously: finish before returning
     if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
+    order_done(c);
     return ok();
 }
 
@@ -478,10 +539,15 @@ int scff_export_vtensors(scff_ctx* c, const scff_grid* g, long long* n_terms_out
     if (rc) return rc;
     if ((rc = set_device(c))) return rc;
     hipStream_t st = nullptr;
+    if ((rc = order_after(c, st))) return rc;
     if ((rc = ensure_prepared(c, st))) return rc;
     const PrepResult& p = c->pres;
     *n_terms_out = p.terms_kept;
-    if (!vx && !vy && !vz && !tp) return ok();
+    if (!vx && !vy && !vz && !tp) {
+        if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
+        order_done(c);
+        return ok();
+    }
     if ((rc = build_vtables(c, g, st))) return rc;
     const int SW = kStateBlock * p.state_blocks;
     std::vector<float2> V((size_t)c->vtab_rows * c->vtab_stride);
@@ -499,6 +565,7 @@ int scff_export_vtensors(scff_ctx* c, const scff_grid* g, long long* n_terms_out
     for (const Cp& x : cps)
         if ((rc = hip_check(hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, st), "D2H export"))) return rc;
     if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
+    order_done(c);
     long long t = 0;
     float* outs[3] = {vx, vy, vz};
     for (int ch = 0; ch < p.n_units; ++ch) {

@@ -111,13 +111,24 @@ void finish(scff_server* s, Req* r, int status) {
 }
 
 void prep_loop(scff_server* s) {
+    // each prep thread stages its precompute on a stream of its own and waits
+    // for it, so a prepared request is complete in device memory before a run
+    // slot (another stream) evaluates it
+    hipStream_t pst = nullptr;
+    if (!s->fake) {
+        (void)hipSetDevice(s->device);
+        if (hipStreamCreateWithFlags(&pst, hipStreamNonBlocking) != hipSuccess) pst = nullptr;
+    }
     for (;;) {
         unsigned long long t;
         Req* r;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_prep.wait(lk, [&] { return s->stop || !s->prep_q.empty(); });
-            if (s->stop) return;
+            if (s->stop) {
+                if (pst) (void)hipStreamDestroy(pst);
+                return;
+            }
             t = s->prep_q.front();
             s->prep_q.pop_front();
             r = lookup(s, t);
@@ -154,7 +165,7 @@ void prep_loop(scff_server* s) {
                                         r->normalise, nullptr);
             if (rc == SCFF_OK) rc = scff_load_transitions(c, r->n_states, r->T.data());
             if (rc == SCFF_OK) rc = scff_set_options(c, r->eps, r->spin);
-            if (rc == SCFF_OK) rc = scff::ctx_prepare(c, &r->grid, &bytes);
+            if (rc == SCFF_OK) rc = scff::ctx_prepare(c, &r->grid, pst, &bytes);
         } else if (rc == SCFF_OK) {
             // scheduler test mode: footprint of the outputs only
             bytes = (size_t)r->grid.n[0] * r->grid.n[1] * r->grid.n[2] * (size_t)r->n_states * 12;
