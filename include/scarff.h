@@ -95,7 +95,12 @@ const char* scff_last_error(void);
  * SCFF_ENOMEM.  Returns SCFF_EDEVICE if no HIP device is usable. */
 int scff_create(int device, size_t hbm_budget_bytes, scff_ctx** out);
 
-/* Release every resource of the context (NULL is ignored). */
+/* Release every resource of the context (NULL is ignored).  Waits for the
+ * context's own outstanding device work (e.g. an evaluation into device
+ * outputs still running on a caller stream) before freeing its buffers;
+ * other contexts' work is not waited for.  A context may instead be kept
+ * and reused for another molecule: it keeps every device buffer that is
+ * large enough for the next problem. */
 void scff_destroy(scff_ctx* ctx);
 
 /*
@@ -241,7 +246,10 @@ typedef struct {
  * bytes of all in-flight requests fit `hbm_budget_bytes` (0 = 64 GiB) and at
  * most `max_inflight` requests run at once (1..64).  Requests that do not
  * fit wait in FIFO order.  A request larger than the whole budget fails
- * with SCFF_ENOMEM.  device = -1 selects a scheduler test mode that touches
+ * with SCFF_ENOMEM.  The server keeps up to (4 prep threads + max_inflight)
+ * idle contexts for reuse, each holding at most budget / (2 x that count)
+ * device bytes; this idle memory is not counted against the budget.
+ * device = -1 selects a scheduler test mode that touches
  * no GPU: requests are validated, admitted and completed exactly as above,
  * but nothing is computed and their outputs are left untouched. */
 int scff_server_create(int device, size_t hbm_budget_bytes, int max_inflight,

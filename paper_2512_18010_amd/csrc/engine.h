@@ -128,5 +128,7 @@ void set_error(const std::string& msg);
 // evaluation on any other stream may use it.  *bytes_needed receives the
 // device bytes an evaluation on g will hold in total.
 int ctx_prepare(scff_ctx* c, const scff_grid* g, hipStream_t st, size_t* bytes_needed);
+// Device bytes a context holds (its buffers are kept between calls).
+size_t ctx_device_bytes(const scff_ctx* c);
 
 }  // namespace scff

@@ -62,6 +62,9 @@ struct scff_ctx {
     hipEvent_t order_ev = nullptr;
     hipStream_t order_st = nullptr;
     bool order_pending = false;
+    // a call has enqueued device work that is not yet covered by order_ev
+    // or a synchronisation (an error return in the middle of a call)
+    bool async_open = false;
 };
 
 namespace {
@@ -130,6 +133,7 @@ int set_device(scff_ctx* c) { return hip_check(hipSetDevice(c->device), "hipSetD
 // the context's previous asynchronous work with an event, so a call on stream
 // B never overtakes a call still running on stream A.
 int order_after(scff_ctx* c, hipStream_t st) {
+    c->async_open = true;
     if (!c->order_pending || st == c->order_st) return SCFF_OK;
     return hip_check(hipStreamWaitEvent(st, c->order_ev, 0), "stream ordering");
 }
@@ -141,6 +145,7 @@ int order_mark(scff_ctx* c, hipStream_t st) {
     if ((rc = hip_check(hipEventRecord(c->order_ev, st), "event record"))) return rc;
     c->order_st = st;
     c->order_pending = true;
+    c->async_open = false;
     return SCFF_OK;
 }
 // host-side wait for the context's asynchronous work (before the host
@@ -152,7 +157,10 @@ int order_drain(scff_ctx* c) {
     return rc;
 }
 // st has been synchronised after order_after(c, st): everything is done
-void order_done(scff_ctx* c) { c->order_pending = false; }
+void order_done(scff_ctx* c) {
+    c->order_pending = false;
+    c->async_open = false;
+}
 
 int record(scff_ctx* c, int which, hipStream_t st) {
     if (!c->timing) return SCFF_OK;
@@ -269,10 +277,17 @@ int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, hipStream_t st, size_t* b
     order_done(c);
     const size_t npts = (size_t)g->n[0] * g->n[1] * g->n[2];
     const int stride = vtable_stride(g->n);
-    *bytes_needed = c->used + (size_t)c->pres.n_rows * stride * sizeof(float2) +
-                    npts * (size_t)c->n_states * (sizeof(float2) + sizeof(float));
+    // the 1D tables and output staging reuse buffers the context already
+    // holds when those are large enough (a reused context)
+    const size_t vt = (size_t)c->pres.n_rows * stride * sizeof(float2);
+    const size_t of = npts * (size_t)c->n_states * sizeof(float2), of2 = npts * (size_t)c->n_states * sizeof(float);
+    const size_t held = c->d_vtab.bytes + c->d_f.bytes + c->d_f2.bytes;
+    *bytes_needed = c->used - held + std::max(c->d_vtab.bytes, vt) + std::max(c->d_f.bytes, of) +
+                    std::max(c->d_f2.bytes, of2);
     return ok();
 }
+
+size_t scff::ctx_device_bytes(const scff_ctx* c) { return c ? c->used : 0; }
 
 extern "C" {
 
@@ -298,7 +313,9 @@ int scff_create(int device, size_t hbm_budget_bytes, scff_ctx** out) {
 void scff_destroy(scff_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    (void)hipDeviceSynchronize();
+    // wait for this context's own device work only (other contexts keep
+    // running); after a call that failed half-way, for the whole device
+    if (c->async_open || order_drain(c) != SCFF_OK) (void)hipDeviceSynchronize();
     free_all(c);
     for (hipEvent_t& e : c->ev)
         if (e) (void)hipEventDestroy(e);

@@ -14,6 +14,11 @@
 //             the device
 //   complete  release the footprint, record latency, wake waiters
 // A failing request records its own status and never affects others.
+// Contexts are pooled: a finished request hands its context back and the next
+// prep reuses it (a context keeps every device buffer that is large enough),
+// so in steady state a request allocates and frees no device memory and no
+// thread ever waits for the whole device (freeing memory and destroying a
+// context would).
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -76,6 +81,10 @@ struct scff_server {
     long long n_submitted = 0, n_completed = 0, n_failed = 0, n_cancelled = 0;
     bool stop = false;
     std::vector<std::thread> threads;
+    std::vector<scff_ctx*> ctx_pool;   // idle contexts, device buffers kept
+    std::vector<scff_ctx*> to_free;    // contexts to destroy outside the lock
+    size_t pool_cap = 0;               // idle contexts kept at most
+    size_t pool_ctx_max = 0;           // largest context (device bytes) kept idle
 };
 
 namespace {
@@ -96,6 +105,36 @@ void unref(scff_server* s, unsigned long long t) {
 Req* lookup(scff_server* s, unsigned long long t) {
     auto it = s->reqs.find(t);
     return it == s->reqs.end() ? nullptr : it->second.get();
+}
+
+// caller holds s->mu
+scff_ctx* take_ctx(scff_server* s) {
+    if (s->ctx_pool.empty()) return nullptr;
+    scff_ctx* c = s->ctx_pool.back();
+    s->ctx_pool.pop_back();
+    return c;
+}
+
+// caller holds s->mu: return a context to the pool, or, when the pool is
+// full or the context holds more device memory than an idle context may
+// (idle contexts are not counted against the budget), queue it for
+// destruction outside the lock (destroying waits for the device)
+void give_ctx(scff_server* s, scff_ctx* c) {
+    if (!c) return;
+    if (s->ctx_pool.size() < s->pool_cap && scff::ctx_device_bytes(c) <= s->pool_ctx_max)
+        s->ctx_pool.push_back(c);
+    else
+        s->to_free.push_back(c);
+}
+
+// destroy the queued contexts; caller does not hold s->mu
+void drain_to_free(scff_server* s) {
+    std::vector<scff_ctx*> v;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        v.swap(s->to_free);
+    }
+    for (scff_ctx* c : v) scff_destroy(c);
 }
 
 void finish(scff_server* s, Req* r, int status) {
@@ -158,7 +197,11 @@ void prep_loop(scff_server* s) {
             }
         }
         if (rc == SCFF_OK && !s->fake) {
-            rc = scff_create(s->device, 0, &c);
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                c = take_ctx(s);
+            }
+            if (!c) rc = scff_create(s->device, 0, &c);
             if (rc == SCFF_OK)
                 rc = scff_load_molecule(c, r->n_atoms, r->xyz.data(), r->n_shells, r->sh_atom.data(),
                                         r->sh_l.data(), r->sh_nprim.data(), r->exps.data(), r->coefs.data(),
@@ -171,9 +214,9 @@ void prep_loop(scff_server* s) {
             bytes = (size_t)r->grid.n[0] * r->grid.n[1] * r->grid.n[2] * (size_t)r->n_states * 12;
         }
         if (rc != SCFF_OK) err = scff_last_error();
-        std::lock_guard<std::mutex> lk(s->mu);
+        std::unique_lock<std::mutex> lk(s->mu);
         if (rc != SCFF_OK) {
-            if (c) scff_destroy(c);
+            give_ctx(s, c);
             scff::set_error(err);
             // remove from the admission queue and fail alone
             for (auto it = s->admit_q.begin(); it != s->admit_q.end(); ++it)
@@ -184,7 +227,7 @@ void prep_loop(scff_server* s) {
                 }
             if (r->state != St::Cancelled) finish(s, r, rc);
         } else if (r->state == St::Cancelled) {
-            if (c) scff_destroy(c);
+            give_ctx(s, c);
         } else {
             r->ctx = c;
             r->bytes = bytes;
@@ -193,6 +236,8 @@ void prep_loop(scff_server* s) {
         unref(s, t);   // the prep reference
         unref(s, t);   // the prep_q entry
         s->cv_sched.notify_all();
+        lk.unlock();
+        drain_to_free(s);
     }
 }
 
@@ -214,7 +259,7 @@ void sched_loop(scff_server* s) {
             if (r->bytes > s->budget) {                       // can never fit
                 s->admit_q.pop_front();
                 unref(s, t);
-                if (r->ctx) scff_destroy(r->ctx);
+                give_ctx(s, r->ctx);
                 r->ctx = nullptr;
                 scff::set_error("request footprint exceeds the server's HBM budget");
                 finish(s, r, SCFF_ENOMEM);
@@ -256,19 +301,22 @@ void run_loop(scff_server* s) {
         int rc = SCFF_OK;
         std::string err;
         if (!s->fake) {
+            // host outputs: when this returns, the context's work is complete
             rc = scff_eval_grid(r->ctx, &r->grid, r->precision, r->f, r->f2, 0, st);
             if (rc != SCFF_OK) err = scff_last_error();
-            scff_destroy(r->ctx);
-            r->ctx = nullptr;
         } else {
             std::this_thread::sleep_for(std::chrono::milliseconds(2));
         }
-        std::lock_guard<std::mutex> lk(s->mu);
+        std::unique_lock<std::mutex> lk(s->mu);
+        give_ctx(s, r->ctx);
+        r->ctx = nullptr;
         s->admitted -= r->bytes;
         --s->inflight;
         if (rc != SCFF_OK) scff::set_error(err);
         finish(s, r, rc);
         s->cv_sched.notify_all();
+        lk.unlock();
+        drain_to_free(s);
     }
     if (st) (void)hipStreamDestroy(st);
 }
@@ -298,6 +346,10 @@ int scff_server_create(int device, size_t hbm_budget_bytes, int max_inflight, sc
     s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)64 << 30;
     s->max_inflight = max_inflight;
     const int n_prep = 4;
+    // every thread can hold one context; prepared requests waiting for
+    // admission hold theirs until they run
+    s->pool_cap = (size_t)(n_prep + max_inflight);
+    s->pool_ctx_max = s->budget / (2 * s->pool_cap);
     for (int i = 0; i < n_prep; ++i) s->threads.emplace_back(prep_loop, s);
     s->threads.emplace_back(sched_loop, s);
     for (int i = 0; i < max_inflight; ++i) s->threads.emplace_back(run_loop, s);
@@ -381,10 +433,8 @@ int scff_server_cancel(scff_server* s, unsigned long long ticket) {
     if (r->state == St::Running || r->state == St::Done) return sfail(SCFF_EBUSY, "request already running or finished");
     r->state = St::Cancelled;
     r->t_done = Clock::now();
-    if (r->ctx) {
-        scff_destroy(r->ctx);
-        r->ctx = nullptr;
-    }
+    give_ctx(s, r->ctx);
+    r->ctx = nullptr;
     ++s->n_cancelled;
     s->cv_done.notify_all();
     s->cv_sched.notify_all();
@@ -413,13 +463,8 @@ void scff_server_destroy(scff_server* s) {
         std::unique_lock<std::mutex> lk(s->mu);
         // cancel everything not yet running, let running requests finish
         for (auto& kv : s->reqs)
-            if (kv.second->state == St::Queued || kv.second->state == St::Ready) {
-                kv.second->state = St::Cancelled;
-                if (kv.second->ctx) {
-                    scff_destroy(kv.second->ctx);
-                    kv.second->ctx = nullptr;
-                }
-            }
+            if (kv.second->state == St::Queued || kv.second->state == St::Ready)
+                kv.second->state = St::Cancelled;   // contexts are freed below
         s->admit_q.clear();
         s->cv_done.wait(lk, [&] { return s->inflight == 0 && s->run_q.empty(); });
         s->stop = true;
@@ -431,6 +476,8 @@ void scff_server_destroy(scff_server* s) {
     for (auto& t : s->threads) t.join();
     for (auto& kv : s->reqs)
         if (kv.second->ctx) scff_destroy(kv.second->ctx);
+    for (scff_ctx* c : s->ctx_pool) scff_destroy(c);
+    for (scff_ctx* c : s->to_free) scff_destroy(c);
     delete s;
 }
 
