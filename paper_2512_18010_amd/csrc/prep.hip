@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "engine.h"
@@ -222,6 +223,12 @@ __global__ void pairmax_kernel(const double* __restrict__ tp64, const double* __
 __global__ void weight_kernel(const int4* __restrict__ trow, const double* __restrict__ tbound,
                               const double* __restrict__ mk, long long nterms, double* __restrict__ w,
                               unsigned int* __restrict__ hist) {
+    // the workgroup counts its terms' exponents in LDS (most terms share a
+    // few bins, so global atomics per term would serialise) and adds its
+    // non-empty bins to the global histogram once
+    __shared__ unsigned int lh[kHistBins];
+    for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) lh[b] = 0u;
+    __syncthreads();
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nterms;
          t += (long long)gridDim.x * blockDim.x) {
         const double x = mk[trow[t].w] * tbound[t];
@@ -230,17 +237,25 @@ __global__ void weight_kernel(const int4* __restrict__ trow, const double* __res
             int e;
             frexp(x, &e);    // x in [2^(e-1), 2^e)
             e = min(max(e + kHistBias, 0), kHistBins - 1);
-            atomicAdd(&hist[e], 1u);
+            atomicAdd(&lh[e], 1u);
         }
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kHistBins; b += blockDim.x)
+        if (lh[b]) atomicAdd(&hist[b], lh[b]);
 }
 
 __global__ void thresh_kernel(const unsigned int* __restrict__ hist, double eps, double* __restrict__ thr) {
     // one wave: per-bin upper bounds, an inclusive prefix sum in fixed order,
-    // then the last bin whose prefix stays <= eps
+    // then the last bin whose prefix stays <= eps (counts and bounds staged in
+    // LDS first: the serial scan then makes no global reads)
     __shared__ double pre[kHistBins];
+    __shared__ unsigned int cnt[kHistBins];
     const int lane = threadIdx.x;
-    for (int b = lane; b < kHistBins; b += blockDim.x) pre[b] = (double)hist[b] * ldexp(1.0, b - kHistBias);
+    for (int b = lane; b < kHistBins; b += blockDim.x) {
+        cnt[b] = hist[b];
+        pre[b] = (double)cnt[b] * ldexp(1.0, b - kHistBias);
+    }
     __syncthreads();
     if (lane == 0) {
         if (!(eps > 0.0)) {
@@ -250,7 +265,7 @@ __global__ void thresh_kernel(const unsigned int* __restrict__ hist, double eps,
         double sum = 0.0;
         int best = -1;   // drop terms whose exponent bin is <= best
         for (int b = 0; b < kHistBins; ++b) {
-            if (hist[b] == 0) continue;
+            if (cnt[b] == 0) continue;
             if (sum + pre[b] > eps) break;
             sum += pre[b];
             best = b;
@@ -434,7 +449,7 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
     hipLaunchKernelGGL(pairmax_kernel, dim3(blocks_for(NCP, 256)), dim3(256), 0, st, (const double*)w.tp64.p,
                        (const double*)tot, ns, NCP, (double*)w.bsum.p);
     CK(hipGetLastError());
-    hipLaunchKernelGGL(weight_kernel, dim3(blocks_for(NT, 256)), dim3(256), 0, st, (const int4*)w.trow.p,
+    hipLaunchKernelGGL(weight_kernel, dim3(std::min(blocks_for(NT, 256), 512)), dim3(256), 0, st, (const int4*)w.trow.p,
                        (const double*)w.tbound.p, (const double*)w.bsum.p, NT, (double*)w.wt.p, hist);
     CK(hipGetLastError());
     hipLaunchKernelGGL(thresh_kernel, dim3(1), dim3(64), 0, st, (const unsigned*)hist, in.eps, thr);
