@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -46,8 +47,13 @@ struct scff_ctx {
     bool have_T = false;
     double eps = 0.0, spin = 1.0;
     // molecule tables on the device
-    DeviceBuffer d_shells, d_sp, d_sp_cp, d_bf0, d_cp_first, d_cp_nterms, d_xyz, d_exps, d_coefs,
-        d_n1d, d_cnorm, d_T;
+    // molecule tables, uploaded together in one buffer: shells, shell pairs,
+    // first component pair per shell pair, first basis function per shell,
+    // first term / term count per component pair, positions, exponents,
+    // coefficients, 1D primitive norms, contracted norms (byte offsets)
+    DeviceBuffer d_mol, d_T;
+    size_t mol_off[11] = {};
+    std::vector<unsigned char> mol_stage;   // host staging of the upload
     // precompute results and evaluation buffers
     PrepWork prep;
     PrepResult pres;
@@ -173,17 +179,18 @@ int ensure_prepared(scff_ctx* c, hipStream_t st) {
     if (c->prepared) return SCFF_OK;
     const Basis& b = c->basis;
     PrepInputs in{};
-    in.shells = (const PrepShell*)c->d_shells.p;
-    in.sp = (const int4*)c->d_sp.p;
-    in.sp_cp = (const int*)c->d_sp_cp.p;
-    in.bf0 = (const int*)c->d_bf0.p;
-    in.cp_first = (const int*)c->d_cp_first.p;
-    in.cp_nterms = (const int*)c->d_cp_nterms.p;
-    in.xyz = (const double*)c->d_xyz.p;
-    in.exps = (const double*)c->d_exps.p;
-    in.coefs = (const double*)c->d_coefs.p;
-    in.n1d = (const double*)c->d_n1d.p;
-    in.cnorm = (const double*)c->d_cnorm.p;
+    const unsigned char* m = (const unsigned char*)c->d_mol.p;
+    in.shells = (const PrepShell*)(m + c->mol_off[0]);
+    in.sp = (const int4*)(m + c->mol_off[1]);
+    in.sp_cp = (const int*)(m + c->mol_off[2]);
+    in.bf0 = (const int*)(m + c->mol_off[3]);
+    in.cp_first = (const int*)(m + c->mol_off[4]);
+    in.cp_nterms = (const int*)(m + c->mol_off[5]);
+    in.xyz = (const double*)(m + c->mol_off[6]);
+    in.exps = (const double*)(m + c->mol_off[7]);
+    in.coefs = (const double*)(m + c->mol_off[8]);
+    in.n1d = (const double*)(m + c->mol_off[9]);
+    in.cnorm = (const double*)(m + c->mol_off[10]);
     in.T = (const double*)c->d_T.p;
     in.nbf = b.nbf;
     in.n_states = c->n_states;
@@ -239,8 +246,7 @@ int check_precision(int precision) {
 }
 
 void free_all(scff_ctx* c) {
-    for (DeviceBuffer* b : {&c->d_shells, &c->d_sp, &c->d_sp_cp, &c->d_bf0, &c->d_cp_first, &c->d_cp_nterms,
-                            &c->d_xyz, &c->d_exps, &c->d_coefs, &c->d_n1d, &c->d_cnorm, &c->d_T, &c->d_vtab,
+    for (DeviceBuffer* b : {&c->d_mol, &c->d_T, &c->d_vtab,
                             &c->d_f, &c->d_f2, &c->d_q})
         dev_free(c, *b);
     PrepWork& w = c->prep;
@@ -342,17 +348,25 @@ int scff_load_molecule(scff_ctx* c, int n_atoms, const double* xyz, int n_shells
     c->have_mol = false;
     c->have_T = false;
     c->prepared = false;
-    if ((rc = upload_sync(c, c->d_shells, b.shells.data(), b.shells.size() * sizeof(PrepShell)))) return rc;
-    if ((rc = upload_sync(c, c->d_sp, b.sp.data(), b.sp.size() * sizeof(int)))) return rc;
-    if ((rc = upload_sync(c, c->d_sp_cp, b.sp_cp.data(), b.sp_cp.size() * sizeof(int)))) return rc;
-    if ((rc = upload_sync(c, c->d_bf0, b.sh_bf0.data(), b.sh_bf0.size() * sizeof(int)))) return rc;
-    if ((rc = upload_sync(c, c->d_cp_first, b.cp_first.data(), b.cp_first.size() * sizeof(int)))) return rc;
-    if ((rc = upload_sync(c, c->d_cp_nterms, b.cp_nterms.data(), b.cp_nterms.size() * sizeof(int)))) return rc;
-    if ((rc = upload_sync(c, c->d_xyz, b.xyz.data(), b.xyz.size() * sizeof(double)))) return rc;
-    if ((rc = upload_sync(c, c->d_exps, b.exps.data(), b.exps.size() * sizeof(double)))) return rc;
-    if ((rc = upload_sync(c, c->d_coefs, b.coefs.data(), b.coefs.size() * sizeof(double)))) return rc;
-    if ((rc = upload_sync(c, c->d_n1d, b.n1d.data(), b.n1d.size() * sizeof(double)))) return rc;
-    if ((rc = upload_sync(c, c->d_cnorm, b.cnorm.data(), b.cnorm.size() * sizeof(double)))) return rc;
+    {
+        // one host staging buffer, one copy (each table at a 256-byte aligned offset)
+        const std::pair<const void*, size_t> tabs[11] = {
+            {b.shells.data(), b.shells.size() * sizeof(PrepShell)}, {b.sp.data(), b.sp.size() * sizeof(int)},
+            {b.sp_cp.data(), b.sp_cp.size() * sizeof(int)},         {b.sh_bf0.data(), b.sh_bf0.size() * sizeof(int)},
+            {b.cp_first.data(), b.cp_first.size() * sizeof(int)},   {b.cp_nterms.data(), b.cp_nterms.size() * sizeof(int)},
+            {b.xyz.data(), b.xyz.size() * sizeof(double)},          {b.exps.data(), b.exps.size() * sizeof(double)},
+            {b.coefs.data(), b.coefs.size() * sizeof(double)},      {b.n1d.data(), b.n1d.size() * sizeof(double)},
+            {b.cnorm.data(), b.cnorm.size() * sizeof(double)}};
+        size_t total = 0;
+        for (int i = 0; i < 11; ++i) {
+            c->mol_off[i] = total;
+            total += (tabs[i].second + 255) & ~(size_t)255;
+        }
+        c->mol_stage.assign(total, 0);
+        for (int i = 0; i < 11; ++i)
+            if (tabs[i].second) std::memcpy(c->mol_stage.data() + c->mol_off[i], tabs[i].first, tabs[i].second);
+        if ((rc = upload_sync(c, c->d_mol, c->mol_stage.data(), total))) return rc;
+    }
     c->have_T = had_T && b.nbf == old_nbf;   // T (untouched) still matches the basis size
     c->basis = std::move(b);
     c->have_mol = true;
