@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--check-points", type=int, default=48, help="oracle-checked grid points (0 = skip)")
     ap.add_argument("--no-bf16", action="store_true", help="skip the split-BF16 comparison run")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--no-symmetric", action="store_true",
+                    help="skip the symmetric-grid measurement (f(-q) = f(q)*, half the planes evaluated)")
     ap.add_argument("--serve-pool", type=int, default=24, help="distinct requests in the serving pool")
     ap.add_argument("--serve-sat", type=int, default=48, help="requests of the closed-loop saturation run")
     ap.add_argument("--serve-requests", type=int, default=96, help="requests per Poisson arrival rate")
@@ -306,6 +308,22 @@ def main():
         o["t_additive_ms"] = (t_valu + t_mfma(oprec)) * 1e3
         other = o
 
+    # the same workload in the symmetric-grid mode: the grid is symmetric about
+    # q = 0 and T is real, so the planes ix >= ceil(nx/2) are written as
+    # f(-q) = f(q)* of evaluated ones (not part of the headline value)
+    symmetric = None
+    sym_grid = all(W.grid.qmin[a] == -W.grid.qmax[a] for a in range(3))
+    if not args.no_symmetric and sym_grid:
+        ctx.set_symmetry(True)
+        o = timed(args.precision, max(3, args.steps // 2), 1)
+        o["errors_vs_oracle"] = check_errors()
+        ctx.set_symmetry(False)
+        o["precision"] = args.precision
+        o["value"] = ns * nq / (o["ms_per_step"] * 1e-3)
+        o["kernel_only_value"] = ns * nq / (o["grid_kernel_ms"] * 1e-3)
+        o["planes_evaluated"] = (n[0] + 1) // 2
+        symmetric = o
+
     serving = None
     if not args.no_serving:
         serving = []
@@ -350,6 +368,7 @@ def main():
         "cpu_baseline": cpu,
         "errors_vs_oracle": errors,
         "other_precision": other,
+        "symmetric_grid": symmetric,
         "serving": serving,
     }
     print(json.dumps(out))

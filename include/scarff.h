@@ -171,6 +171,17 @@ int scff_eval_grid(scff_ctx* ctx, const scff_grid* grid, int precision, float* f
                    int out_on_device, void* hip_stream);
 
 /*
+ * Symmetric-grid mode (off by default).  The transition densities are real,
+ * so f(-q) = f(q)* (Sec. 4: e^{iq.r} is the only complex factor of the
+ * integrand).  With enable = 1, scff_eval_grid on a grid with
+ * qmin[a] == -qmax[a] on every axis evaluates the planes ix < ceil(nx/2)
+ * and writes every other point as the conjugate of its mirror point
+ * (nx-1-ix, ny-1-iy, nz-1-iz); |f|^2 is copied.  Other grids are evaluated
+ * in full.  enable must be 0 or 1 (else SCFF_EINVAL).
+ */
+int scff_set_symmetry(scff_ctx* ctx, int enable);
+
+/*
  * Evaluate at arbitrary points q [n_q][3] (host array, a.u.).  Same outputs
  * as scff_eval_grid with the grid axes replaced by the point index:
  * f [n_states][n_q][2], f2 [n_states][n_q].  1 <= n_q <= 2^24.

@@ -96,6 +96,7 @@ scff_eval_points = _fn("scff_eval_points", c_int,
                        [c_void_p, c_int, P(c_double), c_int, c_void_p, c_void_p, c_int, c_void_p])
 scff_query = _fn("scff_query", c_int, [c_void_p, P(scff_info)])
 scff_set_timing = _fn("scff_set_timing", c_int, [c_void_p, c_int])
+scff_set_symmetry = _fn("scff_set_symmetry", c_int, [c_void_p, c_int])
 scff_last_timing = _fn("scff_last_timing", c_int, [c_void_p, P(c_float), P(c_float), P(c_float)])
 scff_export_vtensors = _fn("scff_export_vtensors", c_int,
                            [c_void_p, P(scff_grid), P(c_longlong), c_void_p, c_void_p, c_void_p,
@@ -208,6 +209,10 @@ class Context:
 
     def set_timing(self, enable: bool = True):
         check(scff_set_timing(self._h, int(bool(enable))))
+
+    def set_symmetry(self, enable: bool = True):
+        """Evaluate half of a grid symmetric about q = 0 and mirror f(-q) = f(q)*."""
+        check(scff_set_symmetry(self._h, int(bool(enable))))
 
     def last_timing(self):
         """(prep_ms, vtable_ms, grid_ms) of the last timed evaluation (HIP events on its stream)."""

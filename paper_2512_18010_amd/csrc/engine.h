@@ -25,6 +25,14 @@ constexpr int kChunk = 8;
 // count npp: at most kMaxUnitsPerChunk units and kMaxChunkTerms terms.
 constexpr int kMaxUnitsPerChunk = 4;
 constexpr int kMaxChunkTerms = kChunk * kMaxTermsPerPair;   // 72
+// The grid kernel may split a grid's chunk list into up to kMaxSplit ranges
+// (one workgroup per tile and range, FP64 partial sums reduced afterwards)
+// when the grid has too few tiles to fill the device.
+constexpr int kMaxSplit = 8;
+struct ChunkSplit {
+    int n;                   // number of ranges (1 = no split)
+    int lo[kMaxSplit + 1];   // range j is chunks [lo[j], lo[j+1]); lo[0] = 0, lo[n] = n_chunks
+};
 // States per MFMA row block.
 constexpr int kStateBlock = 16;
 constexpr int kMaxStates = 32;

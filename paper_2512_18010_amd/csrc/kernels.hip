@@ -145,8 +145,9 @@ __device__ __forceinline__ void barrier_dma() {
 template <int SB, int QZL, int WPE, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
     const float2* __restrict__ V, int vstride, const int4* __restrict__ terms,
-    const int4* __restrict__ chunks, int n_chunks, const uint32_t* __restrict__ Tp, int3 n, int3 ntiles,
-    int n_states, float2* __restrict__ f, float* __restrict__ f2) {
+    const int4* __restrict__ chunks, ChunkSplit sp, const uint32_t* __restrict__ Tp, int3 n, int3 ntiles,
+    int nx_eval, int n_states, float2* __restrict__ f, float* __restrict__ f2, double2* __restrict__ partial,
+    long long part_stride) {
     constexpr int TZ = 4 * QZL;
     constexpr int ZPARTS = TZ / 2;     // float4 slices of a Z row
     constexpr int SLOTS = 2 * QZL;     // q values per lane
@@ -176,7 +177,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const int lpair = ln >> 2;         // lines 2*lpair, 2*lpair+1 of the wave
     const int zgrp = ln & 3;           // qz values zgrp*QZL .. zgrp*QZL+QZL-1
 
+    // block = (split of the chunk list, tile); a split sums chunks [c_lo, c_hi)
     int b = blockIdx.x;
+    const int split = b / (ntiles.x * ntiles.y * ntiles.z);
+    b -= split * (ntiles.x * ntiles.y * ntiles.z);
+    const int c_lo = sp.lo[split], c_hi = sp.lo[split + 1];
     const int tz = b % ntiles.z;
     b /= ntiles.z;
     const int ty = b % ntiles.y;
@@ -408,24 +413,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         }
     };
 
-    if (n_chunks > 0) {
-        load_rows(0);
-        issue_dma(0, lds_addr(R0), lds_addr(T0));
-        if (n_chunks > 1) load_rows(1);
+    if (c_hi > c_lo) {
+        load_rows(c_lo);
+        issue_dma(c_lo, lds_addr(R0), lds_addr(T0));
+        if (c_lo + 1 < c_hi) load_rows(c_lo + 1);
     }
     // two chunks per iteration so each buffer is a distinct LDS object
-    for (int c = 0; c < n_chunks; c += 2) {
+    for (int c = c_lo; c < c_hi; c += 2) {
         barrier_dma();                                  // chunk c landed in R0/T0; Wl and R1 are free
-        if (c + 1 < n_chunks) {
+        if (c + 1 < c_hi) {
             issue_dma(c + 1, lds_addr(R1), lds_addr(T1));
-            if (c + 2 < n_chunks) load_rows(c + 2);
+            if (c + 2 < c_hi) load_rows(c + 2);
         }
         chunk_body(c, R0, T0);
-        if (c + 1 >= n_chunks) break;
+        if (c + 1 >= c_hi) break;
         barrier_dma();                                  // chunk c+1 landed in R1/T1; Wl and R0 are free
-        if (c + 2 < n_chunks) {
+        if (c + 2 < c_hi) {
             issue_dma(c + 2, lds_addr(R0), lds_addr(T0));
-            if (c + 3 < n_chunks) load_rows(c + 3);
+            if (c + 3 < c_hi) load_rows(c + 3);
         }
         chunk_body(c + 1, R1, T1);
     }
@@ -451,7 +456,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             const int a = s / QZL, j = s % QZL;
             const int qy = qy0 + 2 * lpair + a;
             const int qz = qz0 + zgrp * QZL + j;
-            if (qx >= n.x || qy >= n.y || qz >= n.z) continue;
+            if (qx >= nx_eval || qy >= n.y || qz >= n.z) continue;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int st = sb * 16 + 4 * kk + i;
@@ -459,10 +464,74 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
                 const double vr = BF ? (double)acc_r[sb][s][i] : tot_r[sb][s][i];
                 const double vi = BF ? (double)acc_i[sb][s][i] : tot_i[sb][s][i];
                 const size_t o = (((size_t)st * n.x + qx) * n.y + qy) * n.z + qz;
-                if (f) f[o] = make_float2((float)vr, (float)vi);
-                if (f2) f2[o] = (float)(vr * vr + vi * vi);
+                if (partial) {   // split pair sum: FP64 partial, summed by reduce_kernel
+                    partial[(size_t)split * part_stride + o] = make_double2(vr, vi);
+                } else {
+                    if (f) f[o] = make_float2((float)vr, (float)vi);
+                    if (f2) f2[o] = (float)(vr * vr + vi * vi);
+                }
             }
         }
+}
+
+// ---------------------------------------------------------------- split reduction
+//
+// Sum of the FP64 partial results of the chunk-list splits (fixed order) for
+// the evaluated planes ix < nx_eval, then f and |f|^2 as from the grid kernel.
+
+__global__ void reduce_kernel(const double2* __restrict__ part, int n_split, long long stride, int3 n,
+                              int nx_eval, int n_states, float2* __restrict__ f, float* __restrict__ f2) {
+    const long long per_s = (long long)nx_eval * n.y * n.z;
+    const long long tot = per_s * n_states;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(i / per_s);
+        long long r = i - (long long)s * per_s;
+        const int iz = (int)(r % n.z);
+        r /= n.z;
+        const int iy = (int)(r % n.y);
+        const int ix = (int)(r / n.y);
+        const size_t o = (((size_t)s * n.x + ix) * n.y + iy) * n.z + iz;
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < n_split; ++j) {
+            const double2 v = part[(size_t)j * stride + o];
+            re += v.x;
+            im += v.y;
+        }
+        if (f) f[o] = make_float2((float)re, (float)im);
+        if (f2) f2[o] = (float)(re * re + im * im);
+    }
+}
+
+// ---------------------------------------------------------------- mirror kernel
+//
+// For a real transition density the form factor obeys f(-q) = f(q)* (the
+// integrand's phase e^{iq.r} is conjugated by q -> -q, everything else is
+// real).  On a grid symmetric about q = 0 (q_min = -q_max on every axis) the
+// point with indices (nx-1-ix, ny-1-iy, nz-1-iz) is -q of (ix, iy, iz), so
+// the grid kernel evaluates the planes ix < nx_eval = ceil(nx/2) and this
+// kernel writes the others as conjugates: f[s][ix][iy][iz] =
+// conj(f[s][nx-1-ix][ny-1-iy][nz-1-iz]), |f|^2 copied.
+
+__global__ void mirror_kernel(int3 n, int nx_eval, int n_states, float2* __restrict__ f, float* __restrict__ f2) {
+    const long long per_s = (long long)(n.x - nx_eval) * n.y * n.z;
+    const long long tot = per_s * n_states;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(i / per_s);
+        long long r = i - (long long)s * per_s;
+        const int iz = (int)(r % n.z);
+        r /= n.z;
+        const int iy = (int)(r % n.y);
+        const int ix = nx_eval + (int)(r / n.y);
+        const size_t o = (((size_t)s * n.x + ix) * n.y + iy) * n.z + iz;
+        const size_t m = (((size_t)s * n.x + (n.x - 1 - ix)) * n.y + (n.y - 1 - iy)) * n.z + (n.z - 1 - iz);
+        if (f) {
+            const float2 v = f[m];
+            f[o] = make_float2(v.x, -v.y);
+        }
+        if (f2) f2[o] = f2[m];
+    }
 }
 
 // ---------------------------------------------------------------- points kernel
@@ -531,14 +600,24 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
 
 template <int SB, int QZL, int WPE, bool BF>
 static hipError_t launch_grid_t(const float2* V, int vstride, const int4* terms, const int4* chunks,
-                                int n_chunks, const uint32_t* Tp, const int n[3], int n_states, float2* f,
-                                float* f2, hipStream_t st) {
+                                const ChunkSplit& sp, const uint32_t* Tp, const int n[3], int nx_eval,
+                                int n_states, float2* f, float* f2, double2* part, hipStream_t st) {
     const int3 nn = make_int3(n[0], n[1], n[2]);
-    const int3 nt = make_int3((n[0] + 3) / 4, (n[1] + 7) / 8, (n[2] + 4 * QZL - 1) / (4 * QZL));
-    const long long blocks = (long long)nt.x * nt.y * nt.z;
+    const int3 nt = make_int3((nx_eval + 3) / 4, (n[1] + 7) / 8, (n[2] + 4 * QZL - 1) / (4 * QZL));
+    const long long blocks = (long long)nt.x * nt.y * nt.z * sp.n;
+    const long long stride = (long long)n_states * n[0] * n[1] * n[2];
     hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE, BF>), dim3((unsigned)blocks), dim3(256), 0, st, V, vstride,
-                       terms, chunks, n_chunks, Tp, nn, nt, n_states, f, f2);
+                       terms, chunks, sp, Tp, nn, nt, nx_eval, n_states, f, f2, sp.n > 1 ? part : nullptr,
+                       stride);
     return hipGetLastError();
+}
+
+// q_z values per tile: 4 per lane (16) for <= 16 states, 2 per lane (8) above
+static int tile_qz(int state_blocks) { return state_blocks == 1 ? 16 : 8; }
+
+long long grid_tiles(int state_blocks, const int n[3], int nx_eval) {
+    const int tz = tile_qz(state_blocks);
+    return (long long)((nx_eval + 3) / 4) * ((n[1] + 7) / 8) * ((n[2] + tz - 1) / tz);
 }
 
 // Row stride of the 1D tables: every tile may read up to 16 values past the
@@ -550,15 +629,20 @@ int vtable_stride(const int n[3]) {
 }
 
 hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride,
-                       const int4* terms, const int4* chunks, int n_chunks, const float* Tp,
-                       const uint32_t* tp_bf, const int n[3], int n_states, float2* f, float* f2,
-                       hipStream_t st) {
+                       const int4* terms, const int4* chunks, const ChunkSplit& sp, const float* Tp,
+                       const uint32_t* tp_bf, const int n[3], int nx_eval, int n_states, float2* f, float* f2,
+                       double2* part, hipStream_t st) {
     if (precision != 0 && precision != 1) return hipErrorInvalidValue;
     if (vstride < vtable_stride(n)) return hipErrorInvalidValue;
+    if (nx_eval < 1 || nx_eval > n[0]) return hipErrorInvalidValue;
+    if (sp.n < 1 || sp.n > kMaxSplit || sp.lo[0] != 0) return hipErrorInvalidValue;
+    for (int j = 0; j < sp.n; ++j)
+        if (sp.lo[j + 1] < sp.lo[j]) return hipErrorInvalidValue;
+    if (sp.n > 1 && !part) return hipErrorInvalidValue;
     const uint32_t* tp32 = reinterpret_cast<const uint32_t*>(Tp);
 #define SCFF_GRID(SB_, QZL_, WPE_, BF_) \
-    return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, terms, chunks, n_chunks, BF_ ? tp_bf : tp32, n, \
-                                               n_states, f, f2, st)
+    return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, terms, chunks, sp, BF_ ? tp_bf : tp32, n, nx_eval, \
+                                               n_states, f, f2, part, st)
     // <=16 states: 4 q_z per lane (8 q values); 17..32 states: 2 q_z per lane,
     // so the accumulators of both precisions fit 2 waves per SIMD
     if (precision == 1) {
@@ -568,6 +652,30 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
     if (state_blocks == 1) SCFF_GRID(1, 4, 2, false);
     SCFF_GRID(2, 2, 2, false);
 #undef SCFF_GRID
+}
+
+hipError_t launch_reduce(const double2* part, int n_split, const int n[3], int nx_eval, int n_states, float2* f,
+                         float* f2, hipStream_t st) {
+    if (n_split < 1 || nx_eval < 1 || nx_eval > n[0]) return hipErrorInvalidValue;
+    const long long tot = (long long)nx_eval * n[1] * n[2] * n_states;
+    int blocks = (int)((tot + 255) / 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(256), 0, st, part, n_split,
+                       (long long)n_states * n[0] * n[1] * n[2], make_int3(n[0], n[1], n[2]), nx_eval, n_states, f,
+                       f2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror(const int n[3], int nx_eval, int n_states, float2* f, float* f2, hipStream_t st) {
+    // planes ix >= nx_eval mirror planes nx-1-ix < nx - nx_eval <= nx_eval (computed)
+    if (nx_eval < (n[0] + 1) / 2 || nx_eval > n[0]) return hipErrorInvalidValue;
+    if (nx_eval == n[0]) return hipSuccess;
+    const long long tot = (long long)(n[0] - nx_eval) * n[1] * n[2] * n_states;
+    int blocks = (int)((tot + 255) / 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(mirror_kernel, dim3(blocks), dim3(256), 0, st, make_int3(n[0], n[1], n[2]), nx_eval,
+                       n_states, f, f2);
+    return hipGetLastError();
 }
 
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,

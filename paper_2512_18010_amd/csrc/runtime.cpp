@@ -18,9 +18,13 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
                          const double qmin[3], const double dq[3], float2* V, hipStream_t st);
 int vtable_stride(const int n[3]);
 hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride,
-                       const int4* terms, const int4* chunks, int n_chunks, const float* Tp,
-                       const uint32_t* tp_bf, const int n[3], int n_states, float2* f, float* f2,
-                       hipStream_t st);
+                       const int4* terms, const int4* chunks, const ChunkSplit& sp, const float* Tp,
+                       const uint32_t* tp_bf, const int n[3], int nx_eval, int n_states, float2* f, float* f2,
+                       double2* part, hipStream_t st);
+hipError_t launch_reduce(const double2* part, int n_split, const int n[3], int nx_eval, int n_states, float2* f,
+                         float* f2, hipStream_t st);
+hipError_t launch_mirror(const int n[3], int nx_eval, int n_states, float2* f, float* f2, hipStream_t st);
+long long grid_tiles(int state_blocks, const int n[3], int nx_eval);
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
                          const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
                          int n_states, float2* f, float* f2, hipStream_t st);
@@ -71,6 +75,9 @@ struct scff_ctx {
     // a call has enqueued device work that is not yet covered by order_ev
     // or a synchronisation (an error return in the middle of a call)
     bool async_open = false;
+    int symmetry = 0;   // evaluate half of a grid symmetric about q = 0 (scff_set_symmetry)
+    int n_cu = 256;     // compute units of the device
+    DeviceBuffer d_part;   // FP64 partial results of a split chunk list
 };
 
 namespace {
@@ -240,13 +247,55 @@ int build_vtables(scff_ctx* c, const scff_grid* g, hipStream_t st) {
                      "vtable kernel launch");
 }
 
+// every axis runs from -q_max to +q_max, so index i and n-1-i are q and -q
+bool grid_symmetric(const scff_grid* g) {
+    for (int a = 0; a < 3; ++a)
+        if (g->qmin[a] != -g->qmax[a]) return false;
+    return true;
+}
+
+// How scff_eval_grid evaluates grid g: the planes it computes (ix < nx_eval;
+// the rest are mirrored in the symmetric mode) and the split of the chunk
+// list.  A grid with fewer tiles than two workgroups per CU (the grid kernel's
+// occupancy) would leave the device partly idle, so its chunk list is cut
+// into up to kMaxSplit ranges of about equal work (a chunk costs
+// units * (npp + 2): generator terms plus the contraction), one workgroup per
+// tile and range, and the FP64 partial sums are reduced afterwards.
+struct EvalPlan {
+    int nx_eval;
+    ChunkSplit sp;
+};
+
+EvalPlan plan_eval(const scff_ctx* c, const scff_grid* g) {
+    EvalPlan e{};
+    e.nx_eval = (c->symmetry && grid_symmetric(g)) ? (g->n[0] + 1) / 2 : g->n[0];
+    const int nch = c->pres.n_chunks;
+    const long long tiles = grid_tiles(c->pres.state_blocks, g->n, e.nx_eval);
+    const long long target = 2LL * c->n_cu;
+    long long S = tiles < target ? (target + tiles - 1) / tiles : 1;
+    S = std::min<long long>(std::min<long long>(S, kMaxSplit), nch);
+    e.sp.n = (int)std::max<long long>(S, 1);
+    const std::vector<int>& ch = c->prep.chunk_host;   // (first unit, units, npp, first slot) per chunk
+    std::vector<double> pre(nch + 1, 0.0);
+    for (int k = 0; k < nch; ++k) pre[k + 1] = pre[k] + (double)ch[4 * k + 1] * (ch[4 * k + 2] + 2.0);
+    e.sp.lo[0] = 0;
+    int k = 0;
+    for (int j = 1; j < e.sp.n; ++j) {
+        const double w = pre[nch] * j / e.sp.n;
+        while (k < nch && pre[k] < w) ++k;
+        e.sp.lo[j] = k;
+    }
+    e.sp.lo[e.sp.n] = nch;
+    return e;
+}
+
 int check_precision(int precision) {
     if (precision != SCFF_FP32 && precision != SCFF_BF16X3) return fail(SCFF_EINVAL, "unknown precision");
     return SCFF_OK;
 }
 
 void free_all(scff_ctx* c) {
-    for (DeviceBuffer* b : {&c->d_mol, &c->d_T, &c->d_vtab,
+    for (DeviceBuffer* b : {&c->d_mol, &c->d_T, &c->d_vtab, &c->d_part,
                             &c->d_f, &c->d_f2, &c->d_q})
         dev_free(c, *b);
     PrepWork& w = c->prep;
@@ -287,9 +336,11 @@ int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, hipStream_t st, size_t* b
     // holds when those are large enough (a reused context)
     const size_t vt = (size_t)c->pres.n_rows * stride * sizeof(float2);
     const size_t of = npts * (size_t)c->n_states * sizeof(float2), of2 = npts * (size_t)c->n_states * sizeof(float);
-    const size_t held = c->d_vtab.bytes + c->d_f.bytes + c->d_f2.bytes;
+    const EvalPlan pl = plan_eval(c, g);
+    const size_t op = pl.sp.n > 1 ? (size_t)pl.sp.n * npts * (size_t)c->n_states * sizeof(double2) : 0;
+    const size_t held = c->d_vtab.bytes + c->d_f.bytes + c->d_f2.bytes + c->d_part.bytes;
     *bytes_needed = c->used - held + std::max(c->d_vtab.bytes, vt) + std::max(c->d_f.bytes, of) +
-                    std::max(c->d_f2.bytes, of2);
+                    std::max(c->d_f2.bytes, of2) + std::max(c->d_part.bytes, op);
     return ok();
 }
 
@@ -311,6 +362,9 @@ int scff_create(int device, size_t hbm_budget_bytes, scff_ctx** out) {
     if (hipSetDevice(device) != hipSuccess) return fail(SCFF_EDEVICE, "hipSetDevice failed");
     scff_ctx* c = new scff_ctx();
     c->device = device;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        c->n_cu = ncu;
     c->budget = hbm_budget_bytes;
     *out = c;
     return ok();
@@ -473,16 +527,30 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
         df = f ? (float2*)c->d_f.p : nullptr;
         df2 = f2 ? (float*)c->d_f2.p : nullptr;
     }
+    const EvalPlan pl = plan_eval(c, g);
+    double2* part = nullptr;
+    if (pl.sp.n > 1) {
+        if ((rc = dev_reserve(c, c->d_part, (size_t)pl.sp.n * nout * sizeof(double2)))) return rc;
+        part = (double2*)c->d_part.p;
+    }
     if ((rc = record(c, EV_VT0, st))) return rc;
     if ((rc = build_vtables(c, g, st))) return rc;
     if ((rc = record(c, EV_GRID0, st))) return rc;
     const PrepResult& p = c->pres;
+    // f(-q) = f(q)* for real T: on a grid symmetric about q = 0 the planes
+    // ix >= ceil(nx/2) are the conjugates of computed ones (symmetric mode)
     rc = hip_check(launch_grid(p.state_blocks, precision, (const float2*)c->d_vtab.p, c->vtab_stride,
-                               (const int4*)c->prep.slots.p, (const int4*)c->prep.chunks.p, p.n_chunks,
-                               (const float*)c->prep.tp32.p,
-                               (const uint32_t*)c->prep.tpbf.p, g->n, c->n_states, df, df2, st),
+                               (const int4*)c->prep.slots.p, (const int4*)c->prep.chunks.p, pl.sp,
+                               (const float*)c->prep.tp32.p, (const uint32_t*)c->prep.tpbf.p, g->n, pl.nx_eval,
+                               c->n_states, df, df2, part, st),
                    "grid kernel launch");
     if (rc) return rc;
+    if (pl.sp.n > 1 &&
+        (rc = hip_check(launch_reduce(part, pl.sp.n, g->n, pl.nx_eval, c->n_states, df, df2, st), "reduce launch")))
+        return rc;
+    if (pl.nx_eval < g->n[0] &&
+        (rc = hip_check(launch_mirror(g->n, pl.nx_eval, c->n_states, df, df2, st), "mirror kernel launch")))
+        return rc;
     if ((rc = record(c, EV_GRID1, st))) return rc;
     c->ev_recorded = c->timing;
     if (!out_on_device) {
@@ -492,6 +560,13 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
     } else if ((rc = order_mark(c, st))) {
         return rc;
     }
+    return ok();
+}
+
+int scff_set_symmetry(scff_ctx* c, int enable) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (enable != 0 && enable != 1) return fail(SCFF_EINVAL, "enable must be 0 or 1");
+    c->symmetry = enable;
     return ok();
 }
 

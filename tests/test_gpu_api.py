@@ -151,3 +151,34 @@ def test_points_match_grid(binding):
     fg = fg.reshape(fg.shape[0], -1)
     scale = np.abs(fg).max()
     assert np.abs(fp - fg).max() <= 2e-6 * scale
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("nx", [13, 12])
+def test_symmetric_grid_mode(binding, oracle_mod, precision, nx):
+    """Symmetric-grid mode: on a grid symmetric about q = 0 the planes
+    ix < ceil(nx/2) are the full evaluation's values bit for bit, every other
+    plane is exactly the conjugate of its mirror (f(-q) = f(q)* for real T),
+    and the whole grid matches the oracle; a grid that is not symmetric is
+    evaluated in full, bit for bit as without the mode."""
+    W = wl.make_config(0)
+    sym = wl.Grid(n=(nx, 10, 37), qmin=(-5.0, -4.5, -6.0), qmax=(5.0, 4.5, 6.0))
+    asym = small_case().grid
+    with binding.Context(0) as ctx:
+        ctx.load_molecule(W.mol)
+        ctx.load_transitions(W.T)
+        ctx.set_options(0.0, 1.0)
+        f_full, _ = ctx.eval_grid_host(sym, precision)
+        fa_full, fa2_full = ctx.eval_grid_host(asym, precision)
+        ctx.set_symmetry(True)
+        f_sym, f2_sym = ctx.eval_grid_host(sym, precision)
+        fa_sym, fa2_sym = ctx.eval_grid_host(asym, precision)
+    h = (nx + 1) // 2
+    assert np.array_equal(f_sym[:, :h], f_full[:, :h])
+    mirror = f_sym[:, nx - h - 1::-1, ::-1, ::-1] if nx - h > 0 else f_sym[:, :0]
+    assert np.array_equal(f_sym[:, h:], np.conj(mirror))
+    assert np.array_equal(f2_sym[:, h:], f2_sym[:, nx - h - 1::-1, ::-1, ::-1])
+    assert np.array_equal(fa_sym, fa_full) and np.array_equal(fa2_sym, fa2_full)
+    e = errors(f_sym, oracle_mod.eval_grid(W.mol, W.T, sym, n_threads=NTH))
+    log(f"[symmetric nx={nx}] {precision}: peak-normalised |f|^2 err {e['f2_peak_norm'].max():.3e}")
+    assert e["f2_peak_norm"].max() <= TOL_F2[precision]
