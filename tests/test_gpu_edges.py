@@ -134,3 +134,27 @@ def test_zero_transition_density(eng, precision, eps):
     if eps > 0:
         assert info["pairs_kept"] == 0 and info["prim_comp_pairs_kept"] == 0
     assert np.all(f == 0) and np.all(f2 == 0)
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_cases(eng, oracle_mod, case):
+    """Seeded random problems: 1-4 heavy atoms (+ H), 1-32 transitions, grid
+    sizes 1-21 per axis with asymmetric bounds, screening off or on, both
+    precisions; every grid point against the oracle (screened cases keep the
+    oracle unscreened: the screening bound is part of the error budget)."""
+    rng = np.random.Generator(np.random.PCG64(7000 + case))
+    n_heavy = int(rng.integers(1, 5))
+    mol = wl.make_molecule(rng, n_heavy, int(rng.integers(0, n_heavy + 1)), layout="box", box_A=3.0,
+                           with_d=bool(rng.integers(0, 2)))
+    ns = int(rng.integers(1, 33))
+    T = wl.make_transitions(rng, mol.nbf, min(wl.n_occupied(mol.Z), mol.nbf - 1), ns)
+    n = tuple(int(v) for v in rng.integers(1, 22, size=3))
+    lo = rng.uniform(-7.0, -1.0, size=3)
+    hi = rng.uniform(1.0, 7.0, size=3)
+    grid = wl.Grid(n=n, qmin=tuple(lo), qmax=tuple(hi))
+    precision = "bf16x3" if case % 2 else "fp32"
+    eps = 0.0 if case % 3 == 0 else 1e-10
+    log(f"case random {case}: heavy {n_heavy}, nbf {mol.nbf}, states {ns}, grid {n}, {precision}, eps {eps:g}")
+    f, f2 = run(eng, mol, T, grid, precision, eps=eps)
+    assert f.shape == (ns,) + n
+    check(f"random {case}", f, f2, oracle_mod.eval_grid(mol, T, grid, n_threads=NTH), precision)
