@@ -260,6 +260,11 @@ typedef struct {
  * with SCFF_ENOMEM.  The server keeps up to (4 prep threads + max_inflight)
  * idle contexts for reuse, each holding at most budget / (2 x that count)
  * device bytes; this idle memory is not counted against the budget.
+ * Results are copied from the device into pinned host staging buffers of
+ * the server (kept for reuse until scff_server_destroy) and from there, by
+ * copy threads, into the request's f / f2; a request completes when its
+ * results are in the caller's buffers.  At most 2 x max_inflight requests
+ * are running or waiting for that host copy at once.
  * device = -1 selects a scheduler test mode that touches
  * no GPU: requests are validated, admitted and completed exactly as above,
  * but nothing is computed and their outputs are left untouched. */

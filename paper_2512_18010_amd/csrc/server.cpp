@@ -8,11 +8,14 @@
 //             when its footprint fits the HBM budget next to everything in
 //             flight and a run slot is free; requests arriving meanwhile
 //             queue behind it, so no request starves
-//   run       (run slot, one HIP stream each) upload, 1D tables, fused
-//             generator + MFMA kernel, copy to the caller's host buffers;
-//             several requests run at once and their kernels overlap on
-//             the device
-//   complete  release the footprint, record latency, wake waiters
+//   run       (run slot, one HIP stream each) 1D tables, fused generator +
+//             MFMA kernel, copy of the results into a pinned staging
+//             buffer of the server (a DMA at full link speed); several
+//             requests run at once and their kernels overlap on the device
+//   copy      (copy threads) staging buffer -> the caller's host buffers;
+//             the run slot and the device memory are released before this,
+//             so the next request's kernels do not wait for host copies
+//   complete  record latency (results in the caller's memory), wake waiters
 // A failing request records its own status and never affects others.
 // Contexts are pooled: a finished request hands its context back and the next
 // prep reuses it (a context keeps every device buffer that is large enough),
@@ -81,6 +84,12 @@ struct scff_server {
     long long n_submitted = 0, n_completed = 0, n_failed = 0, n_cancelled = 0;
     bool stop = false;
     std::vector<std::thread> threads;
+    std::condition_variable cv_copy;
+    std::deque<std::pair<unsigned long long, void*>> copy_q;   // (ticket, staging buffer) to copy out
+    int copying = 0;                   // requests between the end of their run and completion
+    std::multimap<size_t, void*> stage_free;   // pinned staging buffers by size
+    std::map<void*, size_t> stage_size;        // size of every staging buffer
+    std::vector<void*> stage_all;              // every staging buffer (freed at shutdown)
     std::vector<scff_ctx*> ctx_pool;   // idle contexts, device buffers kept
     std::vector<scff_ctx*> to_free;    // contexts to destroy outside the lock
     size_t pool_cap = 0;               // idle contexts kept at most
@@ -125,6 +134,31 @@ void give_ctx(scff_server* s, scff_ctx* c) {
         s->ctx_pool.push_back(c);
     else
         s->to_free.push_back(c);
+}
+
+// output bytes of a request: f (complex64) and |f|^2 (float32), both staged
+size_t out_points(const Req* r) {
+    return (size_t)r->grid.n[0] * r->grid.n[1] * r->grid.n[2] * (size_t)r->n_states;
+}
+
+// a pinned staging buffer of at least `bytes` (reused, else allocated); caller
+// does not hold s->mu
+void* take_stage(scff_server* s, size_t bytes) {
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->stage_free.lower_bound(bytes);
+        if (it != s->stage_free.end()) {
+            void* p = it->second;
+            s->stage_free.erase(it);
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stage_all.push_back(p);
+    s->stage_size[p] = bytes;
+    return p;
 }
 
 // destroy the queued contexts; caller does not hold s->mu
@@ -266,7 +300,11 @@ void sched_loop(scff_server* s) {
                 progressed = true;
                 continue;
             }
-            if (s->inflight >= s->max_inflight || s->admitted + r->bytes > s->budget) break;
+            // staged results waiting for their host copy hold pinned buffers:
+            // bound them (and so the pinned memory) by the run slots
+            if (s->inflight >= s->max_inflight || s->inflight + s->copying >= 2 * s->max_inflight ||
+                s->admitted + r->bytes > s->budget)
+                break;
             s->admit_q.pop_front();
             unref(s, t);
             r->state = St::Running;
@@ -300,10 +338,21 @@ void run_loop(scff_server* s) {
         }
         int rc = SCFF_OK;
         std::string err;
+        void* stage = nullptr;
         if (!s->fake) {
-            // host outputs: when this returns, the context's work is complete
-            rc = scff_eval_grid(r->ctx, &r->grid, r->precision, r->f, r->f2, 0, st);
-            if (rc != SCFF_OK) err = scff_last_error();
+            // outputs into a pinned staging buffer (f, then |f|^2); when the
+            // call returns, the context's work and the copy are complete
+            const size_t np = out_points(r);
+            stage = take_stage(s, np * (sizeof(float) * 2 + sizeof(float)));
+            if (!stage) {
+                rc = SCFF_ENOMEM;
+                err = "pinned staging buffer allocation failed";
+            } else {
+                float* sf = r->f ? (float*)stage : nullptr;
+                float* sf2 = r->f2 ? (float*)stage + 2 * np : nullptr;
+                rc = scff_eval_grid(r->ctx, &r->grid, r->precision, sf, sf2, 0, st);
+                if (rc != SCFF_OK) err = scff_last_error();
+            }
         } else {
             std::this_thread::sleep_for(std::chrono::milliseconds(2));
         }
@@ -312,13 +361,47 @@ void run_loop(scff_server* s) {
         r->ctx = nullptr;
         s->admitted -= r->bytes;
         --s->inflight;
-        if (rc != SCFF_OK) scff::set_error(err);
-        finish(s, r, rc);
+        if (rc == SCFF_OK && stage) {
+            // results are staged: the copy threads finish the request
+            ++s->copying;
+            s->copy_q.emplace_back(r->ticket, stage);
+            s->cv_copy.notify_one();
+        } else {
+            if (stage) s->stage_free.emplace(s->stage_size[stage], stage);
+            if (rc != SCFF_OK) scff::set_error(err);
+            finish(s, r, rc);
+        }
         s->cv_sched.notify_all();
         lk.unlock();
         drain_to_free(s);
     }
     if (st) (void)hipStreamDestroy(st);
+}
+
+void copy_loop(scff_server* s) {
+    for (;;) {
+        unsigned long long t;
+        void* stage;
+        Req* r;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_copy.wait(lk, [&] { return s->stop || !s->copy_q.empty(); });
+            if (s->copy_q.empty()) return;   // stop, nothing left
+            t = s->copy_q.front().first;
+            stage = s->copy_q.front().second;
+            s->copy_q.pop_front();
+            r = lookup(s, t);
+        }
+        // the request stays in the map while it is not Done (no waiter can take it)
+        const size_t np = out_points(r);
+        if (r->f) std::memcpy(r->f, stage, np * 2 * sizeof(float));
+        if (r->f2) std::memcpy(r->f2, (const float*)stage + 2 * np, np * sizeof(float));
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stage_free.emplace(s->stage_size[stage], stage);
+        --s->copying;
+        finish(s, r, SCFF_OK);
+        s->cv_sched.notify_all();
+    }
 }
 
 template <class T>
@@ -353,6 +436,7 @@ int scff_server_create(int device, size_t hbm_budget_bytes, int max_inflight, sc
     for (int i = 0; i < n_prep; ++i) s->threads.emplace_back(prep_loop, s);
     s->threads.emplace_back(sched_loop, s);
     for (int i = 0; i < max_inflight; ++i) s->threads.emplace_back(run_loop, s);
+    for (int i = 0; i < 2; ++i) s->threads.emplace_back(copy_loop, s);
     *out = s;
     return SCFF_OK;
 }
@@ -466,18 +550,20 @@ void scff_server_destroy(scff_server* s) {
             if (kv.second->state == St::Queued || kv.second->state == St::Ready)
                 kv.second->state = St::Cancelled;   // contexts are freed below
         s->admit_q.clear();
-        s->cv_done.wait(lk, [&] { return s->inflight == 0 && s->run_q.empty(); });
+        s->cv_done.wait(lk, [&] { return s->inflight == 0 && s->run_q.empty() && s->copying == 0; });
         s->stop = true;
     }
     s->cv_prep.notify_all();
     s->cv_sched.notify_all();
     s->cv_run.notify_all();
     s->cv_done.notify_all();
+    s->cv_copy.notify_all();
     for (auto& t : s->threads) t.join();
     for (auto& kv : s->reqs)
         if (kv.second->ctx) scff_destroy(kv.second->ctx);
     for (scff_ctx* c : s->ctx_pool) scff_destroy(c);
     for (scff_ctx* c : s->to_free) scff_destroy(c);
+    for (void* p : s->stage_all) (void)hipHostFree(p);
     delete s;
 }
 
