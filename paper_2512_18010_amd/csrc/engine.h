@@ -112,7 +112,14 @@ struct PrepWork {
         tmp, key, val, vinfo, tmp2, cnpp, csize, coff, tmp3, slots, tp32, tpbf, row_used, newid, tmp4,
         rows, uhist, chunks;
     std::vector<int> chunk_host;   // staging of the chunk table (kept until the next prep)
+    // pinned host memory of the context (kPinnedBytes, or NULL if it could
+    // not be allocated): small readbacks and the chunk table travel through
+    // it by DMA; every use is complete before run_prep returns
+    void* pinned = nullptr;
 };
+
+constexpr size_t kPinnedBytes = (size_t)4 << 20;
+constexpr size_t kPinnedTables = 4096;   // byte offset of the chunk table / molecule upload
 
 struct PrepResult {
     int n_vpairs = 0, n_units = 0, n_chunks = 0, n_rows = 0, state_blocks = 1;

@@ -29,6 +29,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cstring>
 #include <cstdint>
 
 #include "engine.h"
@@ -474,9 +475,16 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
     CK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, (int*)w.nv.p, (int*)w.vbase.p, NCP, st));
     CK(alloc(w.tmp, tmp_bytes + 256));
     CK(hipcub::DeviceScan::ExclusiveSum(w.tmp.p, tmp_bytes, (int*)w.nv.p, (int*)w.vbase.p, NCP, st));
+    // readbacks of sizes land in the context's pinned host memory when it has
+    // some (a DMA; pageable destinations are staged by the runtime)
+    alignas(16) unsigned char local_rb[256];
+    unsigned char* rb = w.pinned ? (unsigned char*)w.pinned : local_rb;
+    int* last = (int*)rb;                                  // [2]
+    unsigned long long* kr = (unsigned long long*)(rb + 16);   // [2]
+    int* lastc = (int*)(rb + 32);                          // [2]
+    int* uhist = (int*)(rb + 64);                          // [16]
+    int* lastr = (int*)(rb + 128);                         // [2]
     // total virtual pairs, K and R
-    int last[2];
-    unsigned long long kr[2];
     CK(hipMemcpyAsync(&last[0], (int*)w.vbase.p + NCP - 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(&last[1], (int*)w.nv.p + NCP - 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(kr, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
@@ -516,7 +524,6 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
     CK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp3, (int*)w.csize.p, (int*)w.coff.p, n_chunks, st));
     CK(alloc(w.tmp3, tmp3 + 256));
     CK(hipcub::DeviceScan::ExclusiveSum(w.tmp3.p, tmp3, (int*)w.csize.p, (int*)w.coff.p, n_chunks, st));
-    int lastc[2], uhist[16];
     CK(hipMemcpyAsync(&lastc[0], (int*)w.coff.p + n_chunks - 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(&lastc[1], (int*)w.csize.p + n_chunks - 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(uhist, w.uhist.p, 16 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -549,7 +556,17 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
     }
     const int n_grid_chunks = (int)(ch.size() / 4);
     CK(alloc(w.chunks, ch.size() * sizeof(int)));
-    CK(hipMemcpyAsync(w.chunks.p, ch.data(), ch.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    {
+        // through pinned memory when it fits; the copy is complete at the
+        // synchronisation below, before the buffer can be written again
+        const size_t cb = ch.size() * sizeof(int);
+        const void* src = ch.data();
+        if (w.pinned && cb <= kPinnedBytes - kPinnedTables) {
+            std::memcpy((unsigned char*)w.pinned + kPinnedTables, ch.data(), cb);
+            src = (unsigned char*)w.pinned + kPinnedTables;
+        }
+        CK(hipMemcpyAsync(w.chunks.p, src, cb, hipMemcpyHostToDevice, st));
+    }
     const long long nslots = (long long)lastc[0] + lastc[1];
     CK(alloc(w.slots, (size_t)nslots * sizeof(int4)));
     CK(alloc(w.tp32, (size_t)n_vpairs * SW * sizeof(float)));
@@ -567,7 +584,6 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
     CK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp4, (int*)w.row_used.p, (int*)w.newid.p, (int)NR, st));
     CK(alloc(w.tmp4, tmp4 + 256));
     CK(hipcub::DeviceScan::ExclusiveSum(w.tmp4.p, tmp4, (int*)w.row_used.p, (int*)w.newid.p, (int)NR, st));
-    int lastr[2];
     CK(hipMemcpyAsync(&lastr[0], (int*)w.newid.p + NR - 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(&lastr[1], (int*)w.row_used.p + NR - 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));

@@ -365,6 +365,9 @@ int scff_create(int device, size_t hbm_budget_bytes, scff_ctx** out) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->n_cu = ncu;
+    // pinned staging of small readbacks and uploads; without it (allocation
+    // refused) the same copies go through pageable memory
+    if (hipHostMalloc(&c->prep.pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) c->prep.pinned = nullptr;
     c->budget = hbm_budget_bytes;
     *out = c;
     return ok();
@@ -380,6 +383,7 @@ void scff_destroy(scff_ctx* c) {
     for (hipEvent_t& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+    if (c->prep.pinned) (void)hipHostFree(c->prep.pinned);
     delete c;
 }
 
@@ -416,10 +420,19 @@ int scff_load_molecule(scff_ctx* c, int n_atoms, const double* xyz, int n_shells
             c->mol_off[i] = total;
             total += (tabs[i].second + 255) & ~(size_t)255;
         }
-        c->mol_stage.assign(total, 0);
+        // pinned when it fits (the upload is synchronous, so the memory is free
+        // again when it returns), else a pageable staging vector
+        unsigned char* stage;
+        if (c->prep.pinned && total <= kPinnedBytes - kPinnedTables) {
+            stage = (unsigned char*)c->prep.pinned + kPinnedTables;
+        } else {
+            c->mol_stage.resize(total);
+            stage = c->mol_stage.data();
+        }
+        std::memset(stage, 0, total);
         for (int i = 0; i < 11; ++i)
-            if (tabs[i].second) std::memcpy(c->mol_stage.data() + c->mol_off[i], tabs[i].first, tabs[i].second);
-        if ((rc = upload_sync(c, c->d_mol, c->mol_stage.data(), total))) return rc;
+            if (tabs[i].second) std::memcpy(stage + c->mol_off[i], tabs[i].first, tabs[i].second);
+        if ((rc = upload_sync(c, c->d_mol, stage, total))) return rc;
     }
     c->have_T = had_T && b.nbf == old_nbf;   // T (untouched) still matches the basis size
     c->basis = std::move(b);
