@@ -256,24 +256,45 @@ bool grid_symmetric(const scff_grid* g) {
 
 // How scff_eval_grid evaluates grid g: the planes it computes (ix < nx_eval;
 // the rest are mirrored in the symmetric mode) and the split of the chunk
-// list.  A grid with fewer tiles than two workgroups per CU (the grid kernel's
-// occupancy) would leave the device partly idle, so its chunk list is cut
-// into up to kMaxSplit ranges of about equal work (a chunk costs
-// units * (npp + 2): generator terms plus the contraction), one workgroup per
-// tile and range, and the FP64 partial sums are reduced afterwards.
+// list.  Every tile costs the same (it runs the whole chunk list), and the
+// device holds two workgroups per CU at once (the grid kernel's occupancy),
+// so a launch of `tiles` workgroups takes ceil(tiles / slots) rounds: 64 or
+// 1728 tiles on 512 slots leave most of one round idle.  Cutting the chunk
+// list into S ranges of about equal work (a chunk costs units * (npp + 2):
+// generator terms plus the contraction), one workgroup per tile and range,
+// takes ceil(tiles * S / slots) rounds of 1/S the work; the FP64 partial sums
+// are reduced afterwards (a pass over S x 16 bytes per output value, small
+// next to the kernel).  S is the smallest value within 2 % of the best; a split
+// must save at least 5 %, and its partial buffer is kept under
+// kMaxPartBytes.  allow_split = false gives the unsplit plan.
+constexpr size_t kMaxPartBytes = (size_t)1 << 30;
+
 struct EvalPlan {
     int nx_eval;
     ChunkSplit sp;
 };
 
-EvalPlan plan_eval(const scff_ctx* c, const scff_grid* g) {
+EvalPlan plan_eval(const scff_ctx* c, const scff_grid* g, bool allow_split = true) {
     EvalPlan e{};
     e.nx_eval = (c->symmetry && grid_symmetric(g)) ? (g->n[0] + 1) / 2 : g->n[0];
     const int nch = c->pres.n_chunks;
     const long long tiles = grid_tiles(c->pres.state_blocks, g->n, e.nx_eval);
-    const long long target = 2LL * c->n_cu;
-    long long S = tiles < target ? (target + tiles - 1) / tiles : 1;
-    S = std::min<long long>(std::min<long long>(S, kMaxSplit), nch);
+    const long long slots = 2LL * c->n_cu;
+    const size_t part1 = (size_t)g->n[0] * g->n[1] * g->n[2] * (size_t)c->n_states * sizeof(double2);
+    long long smax = std::min<long long>(kMaxSplit, nch);
+    smax = std::min<long long>(smax, part1 ? (long long)(kMaxPartBytes / part1) : kMaxSplit);
+    if (!allow_split) smax = 1;
+    auto rounds_per_work = [&](long long S) { return (double)((tiles * S + slots - 1) / slots) / (double)S; };
+    long long S = 1;
+    double best = rounds_per_work(1);
+    for (long long s2 = 2; s2 <= smax; ++s2) {
+        const double r = rounds_per_work(s2);
+        if (r < 0.98 * best) {
+            best = r;
+            S = s2;
+        }
+    }
+    if (best > 0.95 * rounds_per_work(1)) S = 1;
     e.sp.n = (int)std::max<long long>(S, 1);
     const std::vector<int>& ch = c->prep.chunk_host;   // (first unit, units, npp, first slot) per chunk
     std::vector<double> pre(nch + 1, 0.0);
@@ -540,11 +561,15 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
         df = f ? (float2*)c->d_f.p : nullptr;
         df2 = f2 ? (float*)c->d_f2.p : nullptr;
     }
-    const EvalPlan pl = plan_eval(c, g);
+    EvalPlan pl = plan_eval(c, g);
     double2* part = nullptr;
     if (pl.sp.n > 1) {
-        if ((rc = dev_reserve(c, c->d_part, (size_t)pl.sp.n * nout * sizeof(double2)))) return rc;
-        part = (double2*)c->d_part.p;
+        // a split that the context's HBM budget cannot hold falls back to the
+        // unsplit evaluation (same values up to the order of the FP64 sums)
+        if (dev_reserve(c, c->d_part, (size_t)pl.sp.n * nout * sizeof(double2)) == SCFF_OK)
+            part = (double2*)c->d_part.p;
+        else
+            pl = plan_eval(c, g, false);
     }
     if ((rc = record(c, EV_VT0, st))) return rc;
     if ((rc = build_vtables(c, g, st))) return rc;
