@@ -561,18 +561,19 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
         df = f ? (float2*)c->d_f.p : nullptr;
         df2 = f2 ? (float*)c->d_f2.p : nullptr;
     }
+    if ((rc = record(c, EV_VT0, st))) return rc;
+    if ((rc = build_vtables(c, g, st))) return rc;
+    // the partial buffer is the last reservation: a split that the context's
+    // HBM budget cannot hold falls back to the unsplit evaluation (the same
+    // values up to the order of the FP64 sums)
     EvalPlan pl = plan_eval(c, g);
     double2* part = nullptr;
     if (pl.sp.n > 1) {
-        // a split that the context's HBM budget cannot hold falls back to the
-        // unsplit evaluation (same values up to the order of the FP64 sums)
         if (dev_reserve(c, c->d_part, (size_t)pl.sp.n * nout * sizeof(double2)) == SCFF_OK)
             part = (double2*)c->d_part.p;
         else
             pl = plan_eval(c, g, false);
     }
-    if ((rc = record(c, EV_VT0, st))) return rc;
-    if ((rc = build_vtables(c, g, st))) return rc;
     if ((rc = record(c, EV_GRID0, st))) return rc;
     const PrepResult& p = c->pres;
     // f(-q) = f(q)* for real T: on a grid symmetric about q = 0 the planes

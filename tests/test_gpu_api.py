@@ -138,6 +138,37 @@ def test_error_paths_on_device(binding):
         assert ei.value.code == binding.SCFF_ENOMEM
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_split_falls_back_under_budget(binding, oracle_mod, precision):
+    """A grid of few tiles splits its pair sums over several workgroups per
+    tile (an FP64 partial buffer, reserved last).  A context whose HBM budget
+    is one byte short of that evaluation's footprint evaluates the grid
+    unsplit instead: no error, the same values up to the order of the FP64
+    sums, and both within the tolerance of the oracle."""
+    W = small_case()
+    with binding.Context(0) as ctx:
+        ctx.load_molecule(W.mol)
+        ctx.load_transitions(W.T)
+        ctx.set_options(0.0, 1.0)
+        f_split, f2_split = ctx.eval_grid_host(W.grid, precision)
+        full = ctx.query()["device_bytes"]
+    with binding.Context(0, hbm_budget_bytes=full - 1) as ctx:
+        ctx.load_molecule(W.mol)
+        ctx.load_transitions(W.T)
+        ctx.set_options(0.0, 1.0)
+        f_one, f2_one = ctx.eval_grid_host(W.grid, precision)
+        held = ctx.query()["device_bytes"]
+    log(f"[split fallback] {precision}: footprint split {full} B, unsplit {held} B")
+    assert held < full
+    ref = oracle_mod.eval_grid(W.mol, W.T, W.grid, n_threads=NTH)
+    for f, f2 in ((f_split, f2_split), (f_one, f2_one)):
+        e = errors(f, ref)
+        assert e["f2_peak_norm"].max() <= TOL_F2[precision], e["f2_peak_norm"]
+        np.testing.assert_allclose(f2, np.abs(f) ** 2, rtol=2e-6, atol=1e-12 * np.abs(f).max() ** 2)
+    scale = np.abs(f_split).max()
+    assert np.abs(f_one - f_split).max() <= 1e-5 * scale
+
+
 def test_points_match_grid(binding):
     """eval_points at the grid's own points equals eval_grid (same sums,
     evaluated point-wise with on-the-fly V-tensors)."""
