@@ -23,8 +23,8 @@
 //    v_mfma_f32_16x16x4_f32 (A = Tp, 16 states x 4 pairs), with the FP32
 //    MFMA sums of every 32 pairs folded into FP64 totals, which bounds the
 //    rounding error of the long, cancelling pair sum.  Split-BF16 (template
-//    flag BF): G and Tp as hi + lo BF16 halves, hi*lo + lo*hi + hi*hi on
-//    v_mfma_f32_16x16x16_bf16 with FP32 accumulation.
+//    flag BF): G and Tp as hi + lo BF16 halves, lo*hi + hi*hi + hi*lo of one
+//    unit (8 pairs) in one v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
 //  * points_kernel: the same sum at arbitrary points (VALU only), V
 //    evaluated on the fly.
 #include <hip/hip_runtime.h>
@@ -38,9 +38,9 @@ namespace scff {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
-typedef short shortx4 __attribute__((ext_vector_type(4)));
-typedef unsigned int uintx2 __attribute__((ext_vector_type(2)));
+typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Two FP32 values -> two round-to-nearest-even BF16 in one dword (a in the low half).
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
@@ -51,8 +51,9 @@ __device__ __forceinline__ void split_bf16(float g0, float g1, uint32_t& hi, uin
     hi = pack_bf16(g0, g1);
     lo = pack_bf16(g0 - __uint_as_float(hi << 16), g1 - __uint_as_float(hi & 0xffff0000u));
 }
-__device__ __forceinline__ shortx4 bf16x4_of(uint32_t lo_k, uint32_t hi_k) {
-    return __builtin_bit_cast(shortx4, uintx2{lo_k, hi_k});
+// Eight BF16 k-items of a 16x16x32 operand, two per dword (low half first).
+__device__ __forceinline__ bf16x8 bf16x8_of(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {
+    return __builtin_bit_cast(bf16x8, uintx4{a0, a1, b0, b1});
 }
 
 constexpr int kFoldChunks = 32;   // points kernel: units (256 pairs) per FP32 partial sum
@@ -253,30 +254,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             }
     };
 
-    // BF: packed split-BF16 operands of one 16-pair MFMA group (two units).
-    // k = 4*kk + j; j = 0, 1 come from the first unit (x0), j = 2, 3 from the
-    // second (passed in).
-    uint32_t x0hr[SLOTS], x0lr[SLOTS], x0hi[SLOTS], x0li[SLOTS], x0ah[SB], x0al[SB];
-    auto mfma_group = [&](const uint32_t (&hr)[SLOTS], const uint32_t (&lr)[SLOTS], const uint32_t (&hi)[SLOTS],
-                          const uint32_t (&li)[SLOTS], const uint32_t (&ah)[SB], const uint32_t (&al)[SB]) {
-#pragma unroll
-        for (int sb = 0; sb < SB; ++sb) {
-            const shortx4 Ah = bf16x4_of(x0ah[sb], ah[sb]), Al = bf16x4_of(x0al[sb], al[sb]);
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                const shortx4 Bhr = bf16x4_of(x0hr[s], hr[s]), Blr = bf16x4_of(x0lr[s], lr[s]);
-                const shortx4 Bhi = bf16x4_of(x0hi[s], hi[s]), Bli = bf16x4_of(x0li[s], li[s]);
-                // hi*lo + lo*hi first, then hi*hi, into one FP32 accumulator
-                acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Blr, acc_r[sb][s], 0, 0, 0);
-                acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Bli, acc_i[sb][s], 0, 0, 0);
-                acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Al, Bhr, acc_r[sb][s], 0, 0, 0);
-                acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Al, Bhi, acc_i[sb][s], 0, 0, 0);
-                acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Bhr, acc_r[sb][s], 0, 0, 0);
-                acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah, Bhi, acc_i[sb][s], 0, 0, 0);
-            }
-        }
-    };
-    int units_done = 0;   // units contracted so far (fold cadence; BF group parity)
+    int units_done = 0;   // units contracted so far (fold cadence of the FP32 path)
 
     auto chunk_body = [&](int c, const float4* R, const uint32_t* T) {
         const int4 ch = chunks[c];
@@ -383,8 +361,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             }
             ++units_done;
             if constexpr (BF) {
-                // split G and pack the Tp halves of this unit's two k-steps
-                uint32_t hr[SLOTS], lr[SLOTS], hi[SLOTS], li[SLOTS], ah[SB], al[SB];
+                // Split-BF16 contraction of this unit in one 16x16x32 MFMA per
+                // output block.  A lane's eight k-items are its two k-steps
+                // (pairs kk and 4 + kk of the unit) four times over:
+                //   A = (Tp lo | 0 | Tp hi | Tp hi),  B = (G hi | G lo | G hi | G lo)
+                // so the items give lo*hi, 0, hi*hi, hi*lo.  A and B map lane and
+                // item to k alike, so this item order is a valid k order.  One
+                // unit per MFMA, so no state is carried between units (pairing
+                // units for a 16-pair group made the compiler copy the
+                // accumulators on every unit).
+                uint32_t hr[SLOTS], lr[SLOTS], hi[SLOTS], li[SLOTS];
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
                     split_bf16(gr[0][s], gr[1][s], hr[s], lr[s]);
@@ -392,20 +378,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
                 }
 #pragma unroll
                 for (int sb = 0; sb < SB; ++sb) {
-                    ah[sb] = (a_op[0][sb] & 0xffffu) | (a_op[1][sb] << 16);
-                    al[sb] = (a_op[0][sb] >> 16) | (a_op[1][sb] & 0xffff0000u);
-                }
-                if (units_done & 1) {   // first unit of a group: keep it
+                    const uint32_t ah = (a_op[0][sb] & 0xffffu) | (a_op[1][sb] << 16);
+                    const uint32_t al = (a_op[0][sb] >> 16) | (a_op[1][sb] & 0xffff0000u);
+                    const bf16x8 A = bf16x8_of(al, 0u, ah, ah);
 #pragma unroll
                     for (int s = 0; s < SLOTS; ++s) {
-                        x0hr[s] = hr[s]; x0lr[s] = lr[s]; x0hi[s] = hi[s]; x0li[s] = li[s];
+                        const bf16x8 Br = bf16x8_of(hr[s], lr[s], hr[s], lr[s]);
+                        const bf16x8 Bi = bf16x8_of(hi[s], li[s], hi[s], li[s]);
+                        acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Br, acc_r[sb][s], 0, 0, 0);
+                        acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bi, acc_i[sb][s], 0, 0, 0);
                     }
-#pragma unroll
-                    for (int sb = 0; sb < SB; ++sb) {
-                        x0ah[sb] = ah[sb]; x0al[sb] = al[sb];
-                    }
-                } else {
-                    mfma_group(hr, lr, hi, li, ah, al);
                 }
             } else {
                 if ((units_done & (kFoldUnits - 1)) == 0) fold();
@@ -434,16 +416,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         }
         chunk_body(c + 1, R1, T1);
     }
-    if constexpr (BF) {
-        if (units_done & 1) {   // last group holds one unit: k-steps 2, 3 are zero
-            uint32_t z[SLOTS], za[SB];
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) z[s] = 0u;
-#pragma unroll
-            for (int sb = 0; sb < SB; ++sb) za[sb] = 0u;
-            mfma_group(z, z, z, z, za, za);
-        }
-    } else {
+    if constexpr (!BF) {
         if (units_done & (kFoldUnits - 1)) fold();
     }
 
