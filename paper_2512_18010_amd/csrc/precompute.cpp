@@ -81,32 +81,55 @@ std::string build_basis(Basis& b, int n_atoms, const double* xyz, int n_shells,
         if (!(exps[k] > 0.0) || !std::isfinite(exps[k])) return "exponents must be positive and finite";
         if (!std::isfinite(coefs[k])) return "non-finite contraction coefficient";
     }
+    // 1D normalisation factors per primitive for powers 0..2
+    nb.n1d.resize(nb.exps.size() * 3);
+    for (size_t k = 0; k < nb.exps.size(); ++k)
+        for (int i = 0; i < 3; ++i) nb.n1d[3 * k + i] = norm1d(nb.exps[k], i);
     nb.cnorm.assign(bf, 1.0);
     if (nb.normalise) {
+        // <chi_k|chi_l> of two normalised primitives of one shell, per axis
+        // n_k(i) n_l(i) (2i-1)!! / (2p)^i sqrt(pi/p) with p = a_k + a_l; the
+        // primitive factors come from n1d, (2i-1)!! = 1, 1, 3 for i = 0, 1, 2
+        const double df[3] = {1.0, 1.0, 3.0};
         for (int mu = 0; mu < bf; ++mu) {
-            int s = bf_shell[mu];
+            const int s = bf_shell[mu];
             const int* pw = &bf_pw[3 * mu];
+            const int o = nb.sh_off[s], np = nb.sh_nprim[s];
             double sum = 0.0;
-            for (int k = 0; k < nb.sh_nprim[s]; ++k)
-                for (int l = 0; l < nb.sh_nprim[s]; ++l) {
-                    double a = nb.exps[nb.sh_off[s] + k], c = nb.exps[nb.sh_off[s] + l];
-                    double p = a + c, t = 1.0;
-                    for (int ax = 0; ax < 3; ++ax)
-                        t *= norm1d(a, pw[ax]) * norm1d(c, pw[ax]) * dfact(2 * pw[ax] - 1) /
-                             std::pow(2.0 * p, pw[ax]) * std::sqrt(M_PI / p);
-                    sum += nb.coefs[nb.sh_off[s] + k] * nb.coefs[nb.sh_off[s] + l] * t;
+            for (int k = 0; k < np; ++k)
+                for (int l = 0; l < np; ++l) {
+                    const double p = nb.exps[o + k] + nb.exps[o + l];
+                    const double sq = std::sqrt(M_PI / p), tp = 2.0 * p;
+                    double t = sq * sq * sq;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int i = pw[ax];
+                        t *= nb.n1d[3 * (o + k) + i] * nb.n1d[3 * (o + l) + i] * df[i] /
+                             (i == 0 ? 1.0 : i == 1 ? tp : tp * tp);
+                    }
+                    sum += nb.coefs[o + k] * nb.coefs[o + l] * t;
                 }
             if (!(sum > 0.0)) return "contracted function with zero norm";
             nb.cnorm[mu] = 1.0 / std::sqrt(sum);
         }
     }
-    // 1D normalisation factors per primitive for powers 0..2
-    nb.n1d.resize(nb.exps.size() * 3);
-    for (size_t k = 0; k < nb.exps.size(); ++k)
-        for (int i = 0; i < 3; ++i) nb.n1d[3 * k + i] = norm1d(nb.exps[k], i);
     // layout of rows (primitive pair x axis x power pair), component pairs
     // (mu <= nu) and terms (component pair x primitive pair), per shell pair
     for (int s = 0; s < n_shells; ++s) nb.shells.push_back(PrepShell{nb.sh_atom[s], nb.sh_l[s], nb.sh_nprim[s], nb.sh_off[s]});
+    {
+        // sizes first, so the tables are filled without reallocation
+        long long ncp_all = 0;
+        for (int sA = 0; sA < n_shells; ++sA)
+            for (int sB = sA; sB < n_shells; ++sB) {
+                const int lA = nb.sh_l[sA], lB = nb.sh_l[sB];
+                ncp_all += sA == sB ? ncart(lA) * (ncart(lA) + 1) / 2 : ncart(lA) * ncart(lB);
+            }
+        const size_t nsp = (size_t)n_shells * (n_shells + 1) / 2;
+        if (ncp_all > INT32_MAX / 2) return "molecule too large for 32-bit term indexing";
+        nb.sp.reserve(4 * nsp);
+        nb.sp_cp.reserve(nsp);
+        nb.cp_first.reserve((size_t)ncp_all);
+        nb.cp_nterms.reserve((size_t)ncp_all);
+    }
     long long rows = 0, terms = 0;
     long long cps = 0;
     for (int sA = 0; sA < n_shells; ++sA)
