@@ -166,6 +166,11 @@ int scff_set_options(scff_ctx* ctx, double screen_eps, double spin_factor);
  *   hip_stream     a hipStream_t of the context's device, or NULL.
  * Requires a loaded molecule and transitions (else SCFF_ESTATE).
  * Grid sizes: 1 <= n[a] <= 4096.
+ * Device memory: the context keeps its 1D tables, host-output staging and,
+ * for grids whose tile count would leave launch rounds partly idle, an FP64
+ * buffer of split pair sums (at most 1 GiB) between calls.  A split that the
+ * context's HBM budget cannot hold is not taken (the grid is evaluated
+ * unsplit, equal up to the order of the FP64 sums).
  */
 int scff_eval_grid(scff_ctx* ctx, const scff_grid* grid, int precision, float* f, float* f2,
                    int out_on_device, void* hip_stream);
