@@ -171,7 +171,8 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
             r = res["rates"][-1]
             log(f"serving {precision}: lambda {frac:.2f} mu -> p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms, "
                 f"{r['throughput_req_per_s']:.2f} req/s")
-    res["server_stats"] = {k: v for k, v in srv.stats().items() if k.startswith("peak") or k in ("completed", "failed")}
+    res["server_stats"] = {k: v for k, v in srv.stats().items()
+                           if k.startswith("peak") or k in ("completed", "failed", "mol_cache_hits")}
     srv.close()
     return res
 

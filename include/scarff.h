@@ -256,6 +256,9 @@ typedef struct {
     long long queued, inflight;
     size_t admitted_bytes, budget_bytes, peak_admitted_bytes;
     long long peak_inflight;
+    /* requests whose molecule was already loaded on the idle context that
+     * served them (its load was skipped) */
+    long long mol_cache_hits;
 } scff_server_stats;
 
 /* Create a server on `device`.  Requests are admitted while the device
@@ -265,6 +268,10 @@ typedef struct {
  * with SCFF_ENOMEM.  The server keeps up to (4 prep threads + max_inflight)
  * idle contexts for reuse, each holding at most budget / (2 x that count)
  * device bytes; this idle memory is not counted against the budget.
+ * An idle context keeps the molecule of its last request in device memory:
+ * a request on the same molecule (equal geometry, shells, exponents,
+ * coefficients and normalise flag) is given that context and skips the
+ * molecule load (host basis build and upload).
  * Results are copied from the device into pinned host staging buffers of
  * the server (kept for reuse until scff_server_destroy) and from there, by
  * copy threads, into the request's f / f2; a request completes when its

@@ -70,7 +70,8 @@ class scff_server_stats(ctypes.Structure):
     _fields_ = [("submitted", c_longlong), ("completed", c_longlong), ("failed", c_longlong),
                 ("cancelled", c_longlong), ("queued", c_longlong), ("inflight", c_longlong),
                 ("admitted_bytes", c_size_t), ("budget_bytes", c_size_t),
-                ("peak_admitted_bytes", c_size_t), ("peak_inflight", c_longlong)]
+                ("peak_admitted_bytes", c_size_t), ("peak_inflight", c_longlong),
+                ("mol_cache_hits", c_longlong)]
 
 
 def _fn(name, res, args):

@@ -18,7 +18,9 @@
 //   complete  record latency (results in the caller's memory), wake waiters
 // A failing request records its own status and never affects others.
 // Contexts are pooled: a finished request hands its context back and the next
-// prep reuses it (a context keeps every device buffer that is large enough),
+// prep reuses it (a context keeps every device buffer that is large enough,
+// and its molecule: a request on the same molecule is given that context and
+// skips the molecule load, a device-resident molecule cache),
 // so in steady state a request allocates and frees no device memory and no
 // thread ever waits for the whole device (freeing memory and destroying a
 // context would).
@@ -45,18 +47,41 @@ using Clock = std::chrono::steady_clock;
 
 enum class St { Queued, Ready, Running, Done, Cancelled };
 
+// The molecule of a request (owned copies of its inputs).  Equal keys load
+// equal device tables, so an idle context that holds one serves the next
+// request on the same molecule without loading it again.
+struct MolKey {
+    std::vector<double> xyz, exps, coefs;
+    std::vector<int> sh_atom, sh_l, sh_nprim;
+    int normalise = 1;
+    bool operator==(const MolKey& o) const {
+        return normalise == o.normalise && sh_l == o.sh_l && sh_nprim == o.sh_nprim && sh_atom == o.sh_atom &&
+               xyz == o.xyz && exps == o.exps && coefs == o.coefs;
+    }
+};
+using MolPtr = std::shared_ptr<const MolKey>;
+
+bool same_mol(const MolPtr& a, const MolPtr& b) { return a && b && (a == b || *a == *b); }
+
+// an idle context and the molecule loaded on it (NULL: unknown)
+struct Idle {
+    scff_ctx* c = nullptr;
+    MolPtr mol;
+};
+
 struct Req {
     unsigned long long ticket = 0;
     // owned copies of the inputs
-    std::vector<double> xyz, exps, coefs, T;
-    std::vector<int> sh_atom, sh_l, sh_nprim;
-    int n_atoms = 0, n_shells = 0, normalise = 1, n_states = 0, precision = 0;
+    MolPtr mol;
+    std::vector<double> T;
+    int n_atoms = 0, n_shells = 0, n_states = 0, precision = 0;
     scff_grid grid{};
     double eps = 0.0, spin = 1.0;
     float* f = nullptr;
     float* f2 = nullptr;
     // execution state
     scff_ctx* ctx = nullptr;
+    MolPtr ctx_mol;   // the molecule loaded on ctx
     size_t bytes = 0;
     St state = St::Queued;
     int status = SCFF_OK;
@@ -90,7 +115,8 @@ struct scff_server {
     std::multimap<size_t, void*> stage_free;   // pinned staging buffers by size
     std::map<void*, size_t> stage_size;        // size of every staging buffer
     std::vector<void*> stage_all;              // every staging buffer (freed at shutdown)
-    std::vector<scff_ctx*> ctx_pool;   // idle contexts, device buffers kept
+    std::vector<Idle> ctx_pool;        // idle contexts, device buffers and molecule kept
+    long long n_mol_hits = 0;          // requests served by a context that held their molecule
     std::vector<scff_ctx*> to_free;    // contexts to destroy outside the lock
     size_t pool_cap = 0;               // idle contexts kept at most
     size_t pool_ctx_max = 0;           // largest context (device bytes) kept idle
@@ -116,22 +142,30 @@ Req* lookup(scff_server* s, unsigned long long t) {
     return it == s->reqs.end() ? nullptr : it->second.get();
 }
 
-// caller holds s->mu
-scff_ctx* take_ctx(scff_server* s) {
-    if (s->ctx_pool.empty()) return nullptr;
-    scff_ctx* c = s->ctx_pool.back();
-    s->ctx_pool.pop_back();
-    return c;
+// caller holds s->mu: an idle context, preferably one that holds molecule m
+// (the most recently returned such context), else the most recently
+// returned one; {NULL, NULL} when the pool is empty
+Idle take_ctx(scff_server* s, const MolPtr& m) {
+    if (s->ctx_pool.empty()) return Idle{};
+    size_t k = s->ctx_pool.size() - 1;
+    for (size_t i = s->ctx_pool.size(); i-- > 0;)
+        if (same_mol(s->ctx_pool[i].mol, m)) {
+            k = i;
+            break;
+        }
+    Idle e = s->ctx_pool[k];
+    s->ctx_pool.erase(s->ctx_pool.begin() + (long)k);
+    return e;
 }
 
 // caller holds s->mu: return a context to the pool, or, when the pool is
 // full or the context holds more device memory than an idle context may
 // (idle contexts are not counted against the budget), queue it for
 // destruction outside the lock (destroying waits for the device)
-void give_ctx(scff_server* s, scff_ctx* c) {
+void give_ctx(scff_server* s, scff_ctx* c, MolPtr mol) {
     if (!c) return;
     if (s->ctx_pool.size() < s->pool_cap && scff::ctx_device_bytes(c) <= s->pool_ctx_max)
-        s->ctx_pool.push_back(c);
+        s->ctx_pool.push_back(Idle{c, std::move(mol)});
     else
         s->to_free.push_back(c);
 }
@@ -215,13 +249,18 @@ void prep_loop(scff_server* s) {
         int rc = SCFF_OK;
         size_t bytes = 0;
         scff_ctx* c = nullptr;
+        MolPtr loaded;   // the molecule c holds
         std::string err;
-        // validation common to both modes (host only)
+        const MolKey& m = *r->mol;
+        // validation common to both modes (host only); on a device the
+        // molecule is validated by its load (or was, if a context holds it)
         {
-            scff::Basis bchk;
-            std::string e2 = scff::build_basis(bchk, r->n_atoms, r->xyz.data(), r->n_shells, r->sh_atom.data(),
-                                               r->sh_l.data(), r->sh_nprim.data(), r->exps.data(),
-                                               r->coefs.data(), r->normalise);
+            std::string e2;
+            if (s->fake) {
+                scff::Basis bchk;
+                e2 = scff::build_basis(bchk, r->n_atoms, m.xyz.data(), r->n_shells, m.sh_atom.data(), m.sh_l.data(),
+                                       m.sh_nprim.data(), m.exps.data(), m.coefs.data(), m.normalise);
+            }
             if (e2.empty() && r->precision != SCFF_FP32 && r->precision != SCFF_BF16X3) e2 = "unknown precision";
             for (int a = 0; e2.empty() && a < 3; ++a)
                 if (r->grid.n[a] < 1 || r->grid.n[a] > 4096) e2 = "grid n must be in 1..4096";
@@ -231,15 +270,19 @@ void prep_loop(scff_server* s) {
             }
         }
         if (rc == SCFF_OK && !s->fake) {
+            bool hit = false;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
-                c = take_ctx(s);
+                Idle e = take_ctx(s, r->mol);
+                c = e.c;
+                hit = c && same_mol(e.mol, r->mol);
+                if (hit) ++s->n_mol_hits;
             }
             if (!c) rc = scff_create(s->device, 0, &c);
-            if (rc == SCFF_OK)
-                rc = scff_load_molecule(c, r->n_atoms, r->xyz.data(), r->n_shells, r->sh_atom.data(),
-                                        r->sh_l.data(), r->sh_nprim.data(), r->exps.data(), r->coefs.data(),
-                                        r->normalise, nullptr);
+            if (rc == SCFF_OK && !hit)
+                rc = scff_load_molecule(c, r->n_atoms, m.xyz.data(), r->n_shells, m.sh_atom.data(), m.sh_l.data(),
+                                        m.sh_nprim.data(), m.exps.data(), m.coefs.data(), m.normalise, nullptr);
+            if (rc == SCFF_OK) loaded = r->mol;
             if (rc == SCFF_OK) rc = scff_load_transitions(c, r->n_states, r->T.data());
             if (rc == SCFF_OK) rc = scff_set_options(c, r->eps, r->spin);
             if (rc == SCFF_OK) rc = scff::ctx_prepare(c, &r->grid, pst, &bytes);
@@ -250,7 +293,7 @@ void prep_loop(scff_server* s) {
         if (rc != SCFF_OK) err = scff_last_error();
         std::unique_lock<std::mutex> lk(s->mu);
         if (rc != SCFF_OK) {
-            give_ctx(s, c);
+            give_ctx(s, c, loaded);
             scff::set_error(err);
             // remove from the admission queue and fail alone
             for (auto it = s->admit_q.begin(); it != s->admit_q.end(); ++it)
@@ -261,9 +304,10 @@ void prep_loop(scff_server* s) {
                 }
             if (r->state != St::Cancelled) finish(s, r, rc);
         } else if (r->state == St::Cancelled) {
-            give_ctx(s, c);
+            give_ctx(s, c, loaded);
         } else {
             r->ctx = c;
+            r->ctx_mol = loaded;
             r->bytes = bytes;
             r->state = St::Ready;
         }
@@ -293,7 +337,7 @@ void sched_loop(scff_server* s) {
             if (r->bytes > s->budget) {                       // can never fit
                 s->admit_q.pop_front();
                 unref(s, t);
-                give_ctx(s, r->ctx);
+                give_ctx(s, r->ctx, r->ctx_mol);
                 r->ctx = nullptr;
                 scff::set_error("request footprint exceeds the server's HBM budget");
                 finish(s, r, SCFF_ENOMEM);
@@ -357,7 +401,7 @@ void run_loop(scff_server* s) {
             std::this_thread::sleep_for(std::chrono::milliseconds(2));
         }
         std::unique_lock<std::mutex> lk(s->mu);
-        give_ctx(s, r->ctx);
+        give_ctx(s, r->ctx, r->ctx_mol);
         r->ctx = nullptr;
         s->admitted -= r->bytes;
         --s->inflight;
@@ -456,16 +500,20 @@ int scff_server_submit(scff_server* s, const scff_request* q, unsigned long long
         nbf += (q->shell_l[i] + 1) * (q->shell_l[i] + 2) / 2;
     }
     auto r = std::make_unique<Req>();
-    copy_in(r->xyz, q->xyz_bohr, (size_t)3 * q->n_atoms);
-    copy_in(r->sh_atom, q->shell_atom, q->n_shells);
-    copy_in(r->sh_l, q->shell_l, q->n_shells);
-    copy_in(r->sh_nprim, q->shell_nprim, q->n_shells);
-    copy_in(r->exps, q->exps, nprim);
-    copy_in(r->coefs, q->coefs, nprim);
+    {
+        auto m = std::make_shared<MolKey>();
+        copy_in(m->xyz, q->xyz_bohr, (size_t)3 * q->n_atoms);
+        copy_in(m->sh_atom, q->shell_atom, q->n_shells);
+        copy_in(m->sh_l, q->shell_l, q->n_shells);
+        copy_in(m->sh_nprim, q->shell_nprim, q->n_shells);
+        copy_in(m->exps, q->exps, nprim);
+        copy_in(m->coefs, q->coefs, nprim);
+        m->normalise = q->normalise;
+        r->mol = std::move(m);
+    }
     copy_in(r->T, q->T, (size_t)q->n_states * nbf * nbf);
     r->n_atoms = q->n_atoms;
     r->n_shells = q->n_shells;
-    r->normalise = q->normalise;
     r->n_states = q->n_states;
     r->precision = q->precision;
     r->grid = q->grid;
@@ -517,7 +565,7 @@ int scff_server_cancel(scff_server* s, unsigned long long ticket) {
     if (r->state == St::Running || r->state == St::Done) return sfail(SCFF_EBUSY, "request already running or finished");
     r->state = St::Cancelled;
     r->t_done = Clock::now();
-    give_ctx(s, r->ctx);
+    give_ctx(s, r->ctx, r->ctx_mol);
     r->ctx = nullptr;
     ++s->n_cancelled;
     s->cv_done.notify_all();
@@ -538,6 +586,7 @@ int scff_server_stats_get(scff_server* s, scff_server_stats* o) {
     o->budget_bytes = s->budget;
     o->peak_admitted_bytes = s->peak_admitted;
     o->peak_inflight = s->peak_inflight;
+    o->mol_cache_hits = s->n_mol_hits;
     return SCFF_OK;
 }
 
@@ -561,7 +610,7 @@ void scff_server_destroy(scff_server* s) {
     for (auto& t : s->threads) t.join();
     for (auto& kv : s->reqs)
         if (kv.second->ctx) scff_destroy(kv.second->ctx);
-    for (scff_ctx* c : s->ctx_pool) scff_destroy(c);
+    for (Idle& e : s->ctx_pool) scff_destroy(e.c);
     for (scff_ctx* c : s->to_free) scff_destroy(c);
     for (void* p : s->stage_all) (void)hipHostFree(p);
     delete s;

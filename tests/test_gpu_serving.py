@@ -63,3 +63,29 @@ def test_alone_vs_mix_identical_and_correct(oracle_mod):
         e = errors(f, ref)
         log(f"request {k}: peak-normalised |f|^2 error {e['f2_peak_norm'].max():.3e}")
         assert e["f2_peak_norm"].max() <= TOL_F2["fp32"]
+
+
+def test_molecule_cache_reuses_loaded_molecule():
+    """A request on a molecule that an idle context already holds is given
+    that context and skips the molecule load; with new transitions and a new
+    grid its result equals a fresh context's bit for bit."""
+    import torch  # noqa: F401
+    from paper_2512_18010_amd import binding
+    (mol, T1, g1), (_, _, g2) = requests(77, 2)
+    rng = np.random.Generator(np.random.PCG64(78))
+    T2 = wl.make_transitions(rng, mol.nbf, wl.n_occupied(mol.Z), 3)
+    with binding.Server(0, 0, max_inflight=2) as srv:
+        status, _, _, _ = srv.wait(srv.submit(mol, T1, g1, screen_eps=1e-9))
+        assert status == binding.SCFF_OK
+        hits0 = srv.stats()["mol_cache_hits"]
+        status, _, f, f2 = srv.wait(srv.submit(mol, T2, g2, screen_eps=1e-9))
+        assert status == binding.SCFF_OK
+        st = srv.stats()
+    log("stats", st)
+    assert hits0 == 0 and st["mol_cache_hits"] == 1
+    with binding.Context(0) as ctx:
+        ctx.load_molecule(mol)
+        ctx.load_transitions(T2)
+        ctx.set_options(1e-9, 1.0)
+        fr, f2r = ctx.eval_grid_host(g2, "fp32")
+    assert np.array_equal(f, fr) and np.array_equal(f2, f2r)
