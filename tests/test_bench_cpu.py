@@ -1,0 +1,31 @@
+"""The benchmark's command-line contract on the CPU: more than one GPU is
+refused with a message before anything touches a device, and the kernel
+source hash that keys the stored HBM-traffic figures ignores comments."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    csrc = tmp_path / "paper_2512_18010_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "kernels.hip").write_text("int a; // one\n\nint b;\n")
+    (csrc / "engine.h").write_text("int c;\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    (csrc / "kernels.hip").write_text("int a; // a different comment\n// and a new one\nint b;   \n")
+    assert bench.kernel_source_hash() == h0
+    (csrc / "kernels.hip").write_text("int a;\nint b2;\n")
+    assert bench.kernel_source_hash() != h0
