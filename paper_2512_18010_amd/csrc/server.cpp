@@ -26,11 +26,13 @@
 // context would).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -175,23 +177,38 @@ size_t out_points(const Req* r) {
     return (size_t)r->grid.n[0] * r->grid.n[1] * r->grid.n[2] * (size_t)r->n_states;
 }
 
-// a pinned staging buffer of at least `bytes` (reused, else allocated); caller
-// does not hold s->mu
+// a pinned staging buffer of at least `bytes`; caller does not hold s->mu.
+// Sizes are rounded up to powers of two (at least 1 MiB) so buffers are
+// reused across requests of similar size; when no idle buffer is large
+// enough, the largest idle one is freed and a larger one allocated, so the
+// server never holds more buffers than it has used at once (at most the
+// requests running or waiting for their host copy, 2 x max_inflight).
 void* take_stage(scff_server* s, size_t bytes) {
+    size_t cls = (size_t)1 << 20;
+    while (cls < bytes) cls <<= 1;
+    void* drop = nullptr;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        auto it = s->stage_free.lower_bound(bytes);
+        auto it = s->stage_free.lower_bound(cls);
         if (it != s->stage_free.end()) {
             void* p = it->second;
             s->stage_free.erase(it);
             return p;
         }
+        if (!s->stage_free.empty()) {
+            auto last = std::prev(s->stage_free.end());
+            drop = last->second;
+            s->stage_free.erase(last);
+            s->stage_size.erase(drop);
+            s->stage_all.erase(std::find(s->stage_all.begin(), s->stage_all.end(), drop));
+        }
     }
+    if (drop) (void)hipHostFree(drop);   // idle: no copy uses it
     void* p = nullptr;
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(s->mu);
     s->stage_all.push_back(p);
-    s->stage_size[p] = bytes;
+    s->stage_size[p] = cls;
     return p;
 }
 
