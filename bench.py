@@ -88,14 +88,35 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
     1. saturated rate mu: closed loop, 2 * max_inflight requests outstanding;
     2. open-loop Poisson arrivals at 0.5, 0.8 and 0.95 mu.
     Latency = result in host memory - submission (the server's steady clock);
-    each arrival draws a request from the pool."""
+    each arrival draws a request from the pool.  The device time of each pool
+    request evaluated alone (precompute + 1D tables + grid kernel, HIP events)
+    gives the rate the device could sustain without overlap, 1 / mean."""
     import threading
+    import torch
     import workload as wl
     from paper_2512_18010_amd import binding
 
     rng = np.random.Generator(np.random.PCG64(5000))
     pool = [wl.make_serving_request(rng) for _ in range(n_pool)]
     qt = [w.T.shape[0] * w.grid.n_points for w in pool]
+
+    def device_ms_alone(w):
+        with binding.Context(0) as ctx:
+            ctx.set_timing(True)
+            ctx.load_molecule(w.mol)
+            ctx.set_options(screen_eps, 1.0)
+            shape = (w.T.shape[0],) + tuple(w.grid.n)
+            f = torch.empty(shape + (2,), dtype=torch.float32, device="cuda")
+            f2 = torch.empty(shape, dtype=torch.float32, device="cuda")
+            ms = 0.0
+            for _ in range(2):   # the first call allocates; the second is timed
+                ctx.load_transitions(w.T)   # the precompute runs again
+                ctx.eval_grid_device(w.grid, f, f2, precision=precision)
+                torch.cuda.synchronize()
+                ms = sum(ctx.last_timing())
+            return ms
+
+    alone = [device_ms_alone(w) for w in pool]
     srv = binding.Server(0, int(budget_gb * (1 << 30)), max_inflight)
 
     def submit(i):
@@ -125,11 +146,14 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
     mu = n_sat / dt
     res = {"precision": precision, "screen_eps": screen_eps, "pool": n_pool, "max_inflight": max_inflight,
            "budget_gb": budget_gb,
+           "device_ms_alone": {"mean": float(np.mean(alone)), "min": float(np.min(alone)),
+                               "max": float(np.max(alone)), "bound_req_per_s": 1000.0 / float(np.mean(alone))},
            "saturated": {"requests": n_sat, "req_per_s": mu, "q_t_per_s": sum(qt[i] for i in done) / dt,
                          "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))},
            "rates": []}
     if log:
-        log(f"serving {precision}: saturated {mu:.2f} req/s")
+        log(f"serving {precision}: saturated {mu:.2f} req/s (device time alone {np.mean(alone):.2f} ms "
+            f"per request on average -> {1000.0 / np.mean(alone):.1f} req/s without overlap)")
     for ri, frac in enumerate((0.5, 0.8, 0.95)):
         lam = frac * mu
         g = np.random.Generator(np.random.PCG64(5000 + ri + 1))
