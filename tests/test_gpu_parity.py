@@ -109,6 +109,26 @@ def test_config3_sampled_screened(eng, oracle_mod, precision):
     sampled_parity(eng, oracle_mod, 3, precision, 48, eps=1e-9)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n", [72, 96])
+def test_split_pair_sums_at_scale_sampled(eng, oracle_mod, precision, n):
+    """The benchmark molecule and transitions on n^3 grids whose tile counts
+    (810 and 1728 workgroups) leave a launch round partly idle, so the pair
+    sums are split over several workgroups per tile and reduced in FP64;
+    a seeded sample plus every transition's grid maximum against the oracle."""
+    W = wl.make_config(1)
+    W.grid = wl.Grid(n=(n, n, n), qmin=(-6.0,) * 3, qmax=(6.0,) * 3)
+    log(f"case split n={n} {precision}")
+    f, f2 = run_grid(eng, W, precision, eps=1e-9)
+    nout = f2.size
+    log(f"  device bytes {eng.query()['device_bytes']} (outputs {nout} values)")
+    idx = wl.sample_grid_indices(W.grid, 40, seed=4321 + n)
+    flat2 = f2.reshape(f2.shape[0], -1)
+    idx = np.unique(np.concatenate([idx, flat2.argmax(axis=1)]))
+    ref = oracle_mod.eval_points(W.mol, W.T, W.grid.points()[idx], n_threads=NTH)
+    check(f"split {n}^3 sampled {len(idx)}", f.reshape(f.shape[0], -1)[:, idx], flat2[:, idx], ref, precision)
+
+
 def few_primitive(mol):
     """The molecule with shells cut to 1 or 2 primitives (alternating), so
     component pairs have 1, 2 or 4 terms."""
