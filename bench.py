@@ -141,7 +141,15 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
         dt = time.perf_counter() - t0
         return dt, lat, out
 
+    names = ("wait_prep", "prep", "wait_run", "run", "copy")
+
+    def stage_means(a, b):
+        """mean time per request in each server stage between two stats snapshots (ms)"""
+        n = max(b["completed"] - a["completed"], 1)
+        return {k: (b["ns_stage"][i] - a["ns_stage"][i]) * 1e-6 / n for i, k in enumerate(names)}
+
     run_closed(n_warm, 4999)
+    st_sat = srv.stats()
     dt, lat, done = run_closed(n_sat, 5100)
     mu = n_sat / dt
     res = {"precision": precision, "screen_eps": screen_eps, "pool": n_pool, "max_inflight": max_inflight,
@@ -149,12 +157,14 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
            "device_ms_alone": {"mean": float(np.mean(alone)), "min": float(np.min(alone)),
                                "max": float(np.max(alone)), "bound_req_per_s": 1000.0 / float(np.mean(alone))},
            "saturated": {"requests": n_sat, "req_per_s": mu, "q_t_per_s": sum(qt[i] for i in done) / dt,
-                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))},
+                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                         "stage_ms_mean": stage_means(st_sat, srv.stats())},
            "rates": []}
     if log:
         log(f"serving {precision}: saturated {mu:.2f} req/s (device time alone {np.mean(alone):.2f} ms "
             f"per request on average -> {1000.0 / np.mean(alone):.1f} req/s without overlap)")
     for ri, frac in enumerate((0.5, 0.8, 0.95)):
+        st0 = srv.stats()
         lam = frac * mu
         g = np.random.Generator(np.random.PCG64(5000 + ri + 1))
         arrivals = np.cumsum(g.exponential(1.0 / lam, size=n_per_rate))
@@ -190,12 +200,14 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
                              "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                              "throughput_req_per_s": n_per_rate / dt,
                              "q_t_per_s": sum(qt[i] for i in pick) / dt,
-                             "max_submit_lag_ms": float(late[0] * 1e3)})
+                             "max_submit_lag_ms": float(late[0] * 1e3),
+                             "stage_ms_mean": stage_means(st0, srv.stats())})
         if log:
             r = res["rates"][-1]
             log(f"serving {precision}: lambda {frac:.2f} mu -> p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms, "
                 f"{r['throughput_req_per_s']:.2f} req/s")
-    res["server_stats"] = {k: v for k, v in srv.stats().items()
+    st = srv.stats()
+    res["server_stats"] = {k: v for k, v in st.items()
                            if k.startswith("peak") or k in ("completed", "failed", "mol_cache_hits")}
     srv.close()
     return res

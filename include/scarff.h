@@ -259,13 +259,18 @@ typedef struct {
     /* requests whose molecule was already loaded on the idle context that
      * served them (its load was skipped) */
     long long mol_cache_hits;
+    /* time spent in each stage, summed over completed requests (ns):
+     * [0] waiting for a prep thread, [1] prep (molecule, T, precompute),
+     * [2] waiting for admission and a run slot, [3] run (tables, grid
+     * kernel, copy into pinned staging), [4] copy to the caller's buffers */
+    long long ns_stage[5];
 } scff_server_stats;
 
 /* Create a server on `device`.  Requests are admitted while the device
  * bytes of all in-flight requests fit `hbm_budget_bytes` (0 = 64 GiB) and at
  * most `max_inflight` requests run at once (1..64).  Requests that do not
  * fit wait in FIFO order.  A request larger than the whole budget fails
- * with SCFF_ENOMEM.  The server keeps up to (4 prep threads + max_inflight)
+ * with SCFF_ENOMEM.  The server keeps up to (8 prep threads + max_inflight)
  * idle contexts for reuse, each holding at most budget / (2 x that count)
  * device bytes; this idle memory is not counted against the budget.
  * An idle context keeps the molecule of its last request in device memory:

@@ -71,7 +71,7 @@ class scff_server_stats(ctypes.Structure):
                 ("cancelled", c_longlong), ("queued", c_longlong), ("inflight", c_longlong),
                 ("admitted_bytes", c_size_t), ("budget_bytes", c_size_t),
                 ("peak_admitted_bytes", c_size_t), ("peak_inflight", c_longlong),
-                ("mol_cache_hits", c_longlong)]
+                ("mol_cache_hits", c_longlong), ("ns_stage", c_longlong * 5)]
 
 
 def _fn(name, res, args):
@@ -324,7 +324,9 @@ class Server:
     def stats(self) -> dict:
         st = scff_server_stats()
         check(scff_server_stats_get(self._h, ctypes.byref(st)))
-        return {k: getattr(st, k) for k, _ in scff_server_stats._fields_}
+        d = {k: getattr(st, k) for k, _ in scff_server_stats._fields_}
+        d["ns_stage"] = list(d["ns_stage"])
+        return d
 
     def close(self):
         if getattr(self, "_h", None):

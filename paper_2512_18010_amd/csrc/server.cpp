@@ -90,6 +90,8 @@ struct Req {
     bool waited = false;
     int queue_refs = 0;   // prep_q / admit_q entries still naming this ticket
     Clock::time_point t_submit, t_done;
+    // stage times: prep start/end, run start/end (device results staged)
+    Clock::time_point t_prep0, t_prep1, t_run0, t_run1;
 };
 
 }  // namespace
@@ -119,6 +121,9 @@ struct scff_server {
     std::vector<void*> stage_all;              // every staging buffer (freed at shutdown)
     std::vector<Idle> ctx_pool;        // idle contexts, device buffers and molecule kept
     long long n_mol_hits = 0;          // requests served by a context that held their molecule
+    // stage times summed over completed requests (ns): waiting for a prep
+    // thread, prep, waiting for admission and a run slot, run, host copy
+    long long ns_stage[5] = {};
     std::vector<scff_ctx*> to_free;    // contexts to destroy outside the lock
     size_t pool_cap = 0;               // idle contexts kept at most
     size_t pool_ctx_max = 0;           // largest context (device bytes) kept idle
@@ -227,10 +232,19 @@ void finish(scff_server* s, Req* r, int status) {
     r->status = status;
     r->state = St::Done;
     r->t_done = Clock::now();
-    if (status == SCFF_OK)
+    if (status == SCFF_OK) {
         ++s->n_completed;
-    else
+        auto ns = [](Clock::time_point a, Clock::time_point b) {
+            return (long long)std::chrono::duration_cast<std::chrono::nanoseconds>(b - a).count();
+        };
+        s->ns_stage[0] += ns(r->t_submit, r->t_prep0);
+        s->ns_stage[1] += ns(r->t_prep0, r->t_prep1);
+        s->ns_stage[2] += ns(r->t_prep1, r->t_run0);
+        s->ns_stage[3] += ns(r->t_run0, r->t_run1);
+        s->ns_stage[4] += ns(r->t_run1, r->t_done);
+    } else {
         ++s->n_failed;
+    }
     s->cv_done.notify_all();
 }
 
@@ -262,6 +276,7 @@ void prep_loop(scff_server* s) {
                 continue;
             }
             ++r->queue_refs;   // held while prep runs unlocked
+            r->t_prep0 = Clock::now();
         }
         int rc = SCFF_OK;
         size_t bytes = 0;
@@ -326,6 +341,7 @@ void prep_loop(scff_server* s) {
             r->ctx = c;
             r->ctx_mol = loaded;
             r->bytes = bytes;
+            r->t_prep1 = Clock::now();
             r->state = St::Ready;
         }
         unref(s, t);   // the prep reference
@@ -396,6 +412,7 @@ void run_loop(scff_server* s) {
             r = lookup(s, s->run_q.front());
             s->run_q.pop_front();
             if (!r) continue;
+            r->t_run0 = Clock::now();
         }
         int rc = SCFF_OK;
         std::string err;
@@ -418,6 +435,7 @@ void run_loop(scff_server* s) {
             std::this_thread::sleep_for(std::chrono::milliseconds(2));
         }
         std::unique_lock<std::mutex> lk(s->mu);
+        r->t_run1 = Clock::now();
         give_ctx(s, r->ctx, r->ctx_mol);
         r->ctx = nullptr;
         s->admitted -= r->bytes;
@@ -489,7 +507,7 @@ int scff_server_create(int device, size_t hbm_budget_bytes, int max_inflight, sc
     s->fake = fake;
     s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)64 << 30;
     s->max_inflight = max_inflight;
-    const int n_prep = 4;
+    const int n_prep = 8;
     // every thread can hold one context; prepared requests waiting for
     // admission hold theirs until they run
     s->pool_cap = (size_t)(n_prep + max_inflight);
@@ -604,6 +622,7 @@ int scff_server_stats_get(scff_server* s, scff_server_stats* o) {
     o->peak_admitted_bytes = s->peak_admitted;
     o->peak_inflight = s->peak_inflight;
     o->mol_cache_hits = s->n_mol_hits;
+    for (int i = 0; i < 5; ++i) o->ns_stage[i] = s->ns_stage[i];
     return SCFF_OK;
 }
 

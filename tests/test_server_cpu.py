@@ -93,3 +93,22 @@ def test_submit_validation():
         bad = np.zeros((33,) + T.shape[1:])
         with pytest.raises(binding.ScffError):
             srv.submit(mol, bad, g)
+
+
+def test_stage_times_add_up_to_latency():
+    """The per-stage times the server reports (waiting for prep, prep,
+    waiting for a run slot, run, host copy) are non-negative, include the
+    test mode's 2 ms of run per request, and sum to the requests' latencies."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    with binding.Server(-1, 0, max_inflight=2) as srv:
+        tickets = [srv.submit(*small_request(rng)) for _ in range(10)]
+        lat_ns = 0
+        for t in tickets:
+            status, lat, _, _ = srv.wait(t)
+            assert status == binding.SCFF_OK
+            lat_ns += lat
+        st = srv.stats()
+    ns = st["ns_stage"]
+    assert all(v >= 0 for v in ns)
+    assert ns[3] >= 10 * 2_000_000
+    assert abs(sum(ns) - lat_ns) <= 1000 * 10   # rounding to whole nanoseconds per stage
