@@ -89,3 +89,35 @@ def test_molecule_cache_reuses_loaded_molecule():
         ctx.set_options(1e-9, 1.0)
         fr, f2r = ctx.eval_grid_host(g2, "fp32")
     assert np.array_equal(f, fr) and np.array_equal(f2, f2r)
+
+
+def test_failing_requests_fail_alone_on_the_device():
+    """On a real device the molecule is validated by its load in prep: a
+    request with a negative exponent and one with an unknown precision fail
+    with SCFF_EINVAL, the requests around them complete and match a fresh
+    context, and a context whose load failed is not reused as if it held
+    the bad molecule."""
+    import dataclasses
+    import torch  # noqa: F401
+    from paper_2512_18010_amd import binding
+    (mol, T, g), (mol2, T2, g2) = requests(99, 2)
+    bad_exps = mol.exps.copy()
+    bad_exps[0] = -1.0
+    bad = dataclasses.replace(mol, exps=bad_exps)
+    with binding.Server(0, 0, max_inflight=2) as srv:
+        t_ok1 = srv.submit(mol, T, g, screen_eps=1e-9)
+        t_bad = srv.submit(bad, T, g, screen_eps=1e-9)
+        t_prec = srv.submit(mol2, T2, g2, precision_code=7)
+        t_ok2 = srv.submit(mol2, T2, g2, screen_eps=1e-9)
+        r1, rb, rp, r2 = (srv.wait(t) for t in (t_ok1, t_bad, t_prec, t_ok2))
+        st = srv.stats()
+    assert rb[0] == binding.SCFF_EINVAL and rp[0] == binding.SCFF_EINVAL
+    assert r1[0] == binding.SCFF_OK and r2[0] == binding.SCFF_OK
+    assert st["failed"] == 2 and st["completed"] == 2
+    for (m, TT, gg), res in (((mol, T, g), r1), ((mol2, T2, g2), r2)):
+        with binding.Context(0) as ctx:
+            ctx.load_molecule(m)
+            ctx.load_transitions(TT)
+            ctx.set_options(1e-9, 1.0)
+            f, f2 = ctx.eval_grid_host(gg, "fp32")
+        assert np.array_equal(res[2], f) and np.array_equal(res[3], f2)
