@@ -301,9 +301,15 @@ int scff_server_wait(scff_server* srv, unsigned long long ticket, long long time
 /* Cancel a queued (not yet admitted) request. SCFF_EBUSY if already running. */
 int scff_server_cancel(scff_server* srv, unsigned long long ticket);
 
+/* Counters of the server since its creation, copied into *out (caller-owned).
+ * queued / inflight / admitted_bytes are the current values; the peaks,
+ * totals and summed stage times cover its whole life.  SCFF_EINVAL on a
+ * NULL argument.  Thread-safe. */
 int scff_server_stats_get(scff_server* srv, scff_server_stats* out);
 
-/* Drain nothing: pending requests are cancelled, running ones finish first. */
+/* Destroy the server: requests not yet running are cancelled, running ones
+ * (and their host copies) finish first; then every context, stream and
+ * staging buffer is released.  srv is invalid afterwards. */
 void scff_server_destroy(scff_server* srv);
 
 #ifdef __cplusplus
