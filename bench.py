@@ -213,18 +213,65 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
     return res
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def grid_roofline(K, R, ns, nq, precision, grid_ms):
+    """Algorithmic bounds of the fused grid kernel on one launch: generator
+    flops (8 R per q-point) on the FP32 vector units, contraction flops
+    (4 K per q-point and transition; three products for split-BF16) on the
+    matrix cores.  The binding pipe is the one with the larger time bound."""
+    gen_flops = 8.0 * R * nq
+    con_flops = 4.0 * K * ns * nq
+    bf = precision == "bf16x3"
+    con_issued = con_flops * (3 if bf else 1)
+    mfma_peak = PEAK_BF16_MFMA if bf else PEAK_FP32_MFMA
+    t_valu = gen_flops / PEAK_FP32_VECTOR
+    t_mfma = con_issued / mfma_peak
+    grid_s = grid_ms * 1e-3
+    if t_mfma > t_valu:
+        bound, achieved, peak = "mfma", con_issued / grid_s, mfma_peak
+    else:
+        bound, achieved, peak = "alu", gen_flops / grid_s, PEAK_FP32_VECTOR
+    return {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "algorithmic": {"generator_flops": gen_flops, "contraction_flops": con_flops,
+                            "contraction_flops_issued": con_issued,
+                            "t_valu_ms": t_valu * 1e3, "t_mfma_ms": t_mfma * 1e3,
+                            "t_star_ms": max(t_valu, t_mfma) * 1e3,
+                            "frac_of_t_star": max(t_valu, t_mfma) / grid_s,
+                            "t_additive_ms": (t_valu + t_mfma) * 1e3,
+                            "frac_of_additive": (t_valu + t_mfma) / grid_s,
+                            "valu_achieved_tflops": gen_flops / grid_s / 1e12,
+                            "mfma_achieved_tflops": con_issued / grid_s / 1e12}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1, help="workload: 1 (64^3), 2 (128^3), 3 (96^3, 570 bf)")
+    ap.add_argument("--config", type=int, default=3,
+                    help="headline workload: 3 (570 bf, 24 transitions, 96^3; default), 1 (190 bf, 64^3), "
+                         "2 (190 bf, 128^3)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--screen-eps", type=float, default=1e-9)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds-1core", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-points", type=int, default=48, help="oracle-checked grid points (0 = skip)")
-    ap.add_argument("--no-bf16", action="store_true", help="skip the split-BF16 comparison run")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the other-precision run of the headline workload")
+    ap.add_argument("--no-config2", action="store_true",
+                    help="skip the 128^3 leg (190 bf, 12 transitions: split-BF16 vs FP32, error per transition)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
     ap.add_argument("--no-symmetric", action="store_true",
                     help="skip the symmetric-grid measurement (f(-q) = f(q)*, half the planes evaluated)")
@@ -249,101 +296,114 @@ def main():
     import workload as wl
     from paper_2512_18010_amd import binding
 
-    W = wl.make_config(args.config)
-    ns = W.T.shape[0]
-    n = tuple(W.grid.n)
-    nq = n[0] * n[1] * n[2]
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
     ctx = binding.Context(0)
     ctx.set_timing(True)
-    T_dev = torch.from_numpy(np.ascontiguousarray(W.T)).cuda()
-    f = torch.empty((ns,) + n + (2,), dtype=torch.float32, device="cuda")
-    f2 = torch.empty((ns,) + n, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def timed(precision, steps, warmup):
-        """Whole-path steps with inputs resident in HBM; HIP events per stage."""
-        def step():
-            ctx.load_molecule(W.mol)
-            ctx.load_transitions_device(T_dev, stream)
+    class Case:
+        """One workload resident in HBM: T on the device, output tensors."""
+
+        def __init__(self, cfg):
+            self.cfg = cfg
+            self.W = wl.make_config(cfg)
+            self.ns = self.W.T.shape[0]
+            self.n = tuple(self.W.grid.n)
+            self.nq = self.n[0] * self.n[1] * self.n[2]
+            self.T_dev = torch.from_numpy(np.ascontiguousarray(self.W.T)).cuda()
+            self.f = torch.empty((self.ns,) + self.n + (2,), dtype=torch.float32, device="cuda")
+            self.f2 = torch.empty((self.ns,) + self.n, dtype=torch.float32, device="cuda")
+
+        def release(self):
+            del self.T_dev, self.f, self.f2
+
+        def step(self, precision):
+            ctx.load_molecule(self.W.mol)
+            ctx.load_transitions_device(self.T_dev, stream)
             ctx.set_options(args.screen_eps, 1.0)
-            ctx.eval_grid_device(W.grid, f, f2, precision=precision, stream=stream)
+            ctx.eval_grid_device(self.W.grid, self.f, self.f2, precision=precision, stream=stream)
 
-        for _ in range(warmup):
-            step()
-        torch.cuda.synchronize()
-        stages = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
-            stages.append(ctx.last_timing())   # HIP events of this step's kernels, on `stream`
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        st = np.array(stages)
-        prep_ms, vt_ms, grid_ms = (float(np.mean(st[:, i])) for i in range(3))
-        return {"ms_per_step": wall / steps * 1e3, "precompute_ms": prep_ms, "vtables_ms": vt_ms,
-                "grid_kernel_ms": grid_ms}
+        def timed(self, precision, steps, warmup):
+            """Whole-path steps with inputs resident in HBM; HIP events per stage."""
+            for _ in range(warmup):
+                self.step(precision)
+            torch.cuda.synchronize()
+            stages = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                self.step(precision)
+                stages.append(ctx.last_timing())   # HIP events of this step's kernels, on `stream`
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = np.array(stages)
+            prep_ms, vt_ms, grid_ms = (float(np.mean(st[:, i])) for i in range(3))
+            info = ctx.query()
+            K, R = info["pairs_kept"], info["prim_comp_pairs_kept"]
+            ms = wall / steps * 1e3
+            return {"precision": precision, "steps": steps, "ms_per_step": ms,
+                    "value": self.ns * self.nq / (ms * 1e-3),
+                    "kernel_only_value": self.ns * self.nq / (grid_ms * 1e-3),
+                    "stages_ms": {"precompute": prep_ms, "vtables": vt_ms, "grid_kernel": grid_ms},
+                    "pairs_kept_K": K, "terms_kept_R": R,
+                    "roofline": grid_roofline(K, R, self.ns, self.nq, precision, grid_ms)}
 
-    def check_errors():
-        """Accuracy of the last step on a seeded sample against the FP64 oracle."""
-        if args.check_points <= 0:
-            return None
-        import oracle
-        from tests.metrics import errors as err_fn
-        idx = wl.sample_grid_indices(W.grid, args.check_points, seed=4242)
-        f2h = f2.reshape(ns, -1).cpu().numpy()
-        idx = np.unique(np.concatenate([idx, f2h.argmax(axis=1)]))
-        fh = f.reshape(ns, -1, 2).cpu().numpy()
-        fs = fh[:, idx, 0] + 1j * fh[:, idx, 1]
-        ref = oracle.eval_points(W.mol, W.T, W.grid.points()[idx], n_threads=min(16, os.cpu_count() or 1))
-        e = err_fn(fs, ref)
-        return {"points": int(len(idx)), "max_f2_peak_normalised": float(e["f2_peak_norm"].max()),
-                "max_complex": float(e["complex"].max())}
+        def errors(self, n_points, seed=4242):
+            """Accuracy of the last step on a seeded sample plus every
+            transition's |f|^2 maximum, against the FP64 oracle, per transition."""
+            if n_points <= 0:
+                return None
+            import oracle
+            from tests.metrics import errors as err_fn
+            idx = wl.sample_grid_indices(self.W.grid, n_points, seed=seed)
+            f2h = self.f2.reshape(self.ns, -1).cpu().numpy()
+            idx = np.unique(np.concatenate([idx, f2h.argmax(axis=1)]))
+            fh = self.f.reshape(self.ns, -1, 2).cpu().numpy()
+            fs = fh[:, idx, 0] + 1j * fh[:, idx, 1]
+            ref = oracle.eval_points(self.W.mol, self.W.T, self.W.grid.points()[idx],
+                                     n_threads=min(16, os.cpu_count() or 1))
+            e = err_fn(fs, ref)
+            return {"points": int(len(idx)), "max_f2_peak_normalised": float(e["f2_peak_norm"].max()),
+                    "max_complex": float(e["complex"].max()),
+                    "f2_peak_normalised_per_transition": [float(x) for x in e["f2_peak_norm"]]}
 
-    main_run = timed(args.precision, args.steps, args.warmup)
-    ms_per_step, grid_ms = main_run["ms_per_step"], main_run["grid_kernel_ms"]
-    prep_ms, vt_ms = main_run["precompute_ms"], main_run["vtables_ms"]
-    errors = check_errors()
+    def run_both(case, first, steps, warmup, check_points, other=True):
+        res = case.timed(first, steps, warmup)
+        res["errors_vs_oracle"] = case.errors(check_points)
+        out = {first: res}
+        if other:
+            op = "bf16x3" if first == "fp32" else "fp32"
+            o = case.timed(op, max(3, steps // 2), 1)
+            o["errors_vs_oracle"] = case.errors(check_points)
+            out[op] = o
+        for p, r in out.items():
+            e = r["errors_vs_oracle"]
+            log(f"config {case.cfg} {p}: {r['ms_per_step']:.2f} ms/step, grid kernel "
+                f"{r['stages_ms']['grid_kernel']:.2f} ms, {r['roofline']['algorithmic']['frac_of_t_star']:.3f} "
+                f"of t*" + (f", max |f|^2 error {e['max_f2_peak_normalised']:.2e}" if e else ""))
+        return out
+
+    # ---- headline workload: the requested precision, then the other one
+    main_case = Case(args.config)
+    W = main_case.W
+    ns, n, nq = main_case.ns, main_case.n, main_case.nq
+    legs = run_both(main_case, args.precision, args.steps, args.warmup, args.check_points, not args.no_bf16)
+    head = legs[args.precision]
+    other = legs.get("bf16x3" if args.precision == "fp32" else "fp32")
+    ms_per_step = head["ms_per_step"]
+    grid_ms = head["stages_ms"]["grid_kernel"]
+    K, R = head["pairs_kept_K"], head["terms_kept_R"]
     info = ctx.query()
-    K, R = info["pairs_kept"], info["prim_comp_pairs_kept"]
 
-    # roofline of the fused grid kernel
-    gen_flops = 8.0 * R * nq                    # one complex MAC per (pair, prim pair, q)
-    con_flops = 4.0 * K * ns * nq               # real Tp x complex G per (pair, q, transition)
-    t_valu = gen_flops / PEAK_FP32_VECTOR
-
-    def t_mfma(precision):
-        return con_flops * (3 if precision == "bf16x3" else 1) / (
-            PEAK_BF16_MFMA if precision == "bf16x3" else PEAK_FP32_MFMA)
-
-    grid_s = grid_ms * 1e-3
-    achieved = gen_flops / grid_s
+    roof = dict(head["roofline"])
     wkey = f"cfg{args.config}/eps{args.screen_eps:g}"
-    traffic = measured_traffic(wkey, args.precision)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
-            "kernel": "grid_kernel", "kernel_ms": grid_ms,
-            "algorithmic": {"generator_flops": gen_flops, "contraction_flops": con_flops,
-                            "t_valu_ms": t_valu * 1e3, "t_mfma_ms": t_mfma(args.precision) * 1e3,
-                            "t_star_ms": max(t_valu, t_mfma(args.precision)) * 1e3,
-                            "frac_of_t_star": max(t_valu, t_mfma(args.precision)) / grid_s,
-                            # a SIMD does not execute VALU and MFMA work at the same time, so
-                            # the attainable time is the sum of the two pipes' times
-                            "t_additive_ms": (t_valu + t_mfma(args.precision)) * 1e3,
-                            "frac_of_additive": (t_valu + t_mfma(args.precision)) / grid_s,
-                            "mfma_achieved_tflops": con_flops / grid_s / 1e12}}
-
-    # the other contraction precision on the same workload (FP32 vs split-BF16)
-    other = None
-    if not args.no_bf16:
-        oprec = "bf16x3" if args.precision == "fp32" else "fp32"
-        o = timed(oprec, max(3, args.steps // 2), 1)
-        o["errors_vs_oracle"] = check_errors()
-        o["precision"] = oprec
-        o["value"] = ns * nq / (o["ms_per_step"] * 1e-3)
-        o["kernel_only_value"] = ns * nq / (o["grid_kernel_ms"] * 1e-3)
-        o["t_star_ms"] = max(t_valu, t_mfma(oprec)) * 1e3
-        o["t_additive_ms"] = (t_valu + t_mfma(oprec)) * 1e3
-        other = o
+    roof["traffic"] = measured_traffic(wkey, args.precision)
+    roof["kernel"] = "grid_kernel"
+    roof["kernel_ms"] = grid_ms
+    roof["units"] = {"K": K, "R": R, "n_states": ns, "q_points": nq,
+                     "per_unit": "8 flops per (term, q-point) on the vector units; 4 flops per "
+                                 "(pair, q-point, transition) on the matrix cores (x3 for split-BF16)"}
 
     # the same workload in the symmetric-grid mode: the grid is symmetric about
     # q = 0 and T is real, so the planes ix >= ceil(nx/2) are written as
@@ -352,14 +412,21 @@ def main():
     sym_grid = all(W.grid.qmin[a] == -W.grid.qmax[a] for a in range(3))
     if not args.no_symmetric and sym_grid:
         ctx.set_symmetry(True)
-        o = timed(args.precision, max(3, args.steps // 2), 1)
-        o["errors_vs_oracle"] = check_errors()
+        o = main_case.timed(args.precision, max(3, args.steps // 2), 1)
+        o["errors_vs_oracle"] = main_case.errors(args.check_points)
         ctx.set_symmetry(False)
-        o["precision"] = args.precision
-        o["value"] = ns * nq / (o["ms_per_step"] * 1e-3)
-        o["kernel_only_value"] = ns * nq / (o["grid_kernel_ms"] * 1e-3)
         o["planes_evaluated"] = (n[0] + 1) // 2
+        del o["roofline"]
         symmetric = o
+    main_case.release()
+
+    # ---- 128^3 leg: split-BF16 against plain FP32, error per transition
+    config2 = None
+    if not args.no_config2 and args.config != 2:
+        c2 = Case(2)
+        legs2 = run_both(c2, "fp32", max(5, args.steps // 2), 2, max(args.check_points, 64))
+        c2.release()
+        config2 = {"workload": c2.W.name, "grid": list(c2.n), "n_states": c2.ns, "legs": legs2}
 
     serving = None
     if not args.no_serving:
@@ -367,7 +434,7 @@ def main():
         for prec in [p for p in args.serve_precisions.split(",") if p]:
             serving.append(serving_benchmark(prec, args.serve_pool, args.serve_sat, args.serve_requests,
                                              args.serve_warmup, args.serve_inflight, 64.0, args.screen_eps,
-                                             log=lambda m: print(m, file=sys.stderr, flush=True)))
+                                             log=log))
 
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")   # fill: writes N MiB
@@ -381,6 +448,11 @@ def main():
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
         cpu = cpu_baseline(W, args.cpu_seconds, threads)
+        one = cpu_baseline(W, args.cpu_seconds_1core, 1)
+        cpu["cpu_model"] = cpu_model()
+        cpu["host_threads_available"] = os.cpu_count()
+        cpu["value_1core"] = one["value"]
+        cpu["sample_1core"] = one["sample"]
 
     out = {
         "metric": "q-points x transitions / s (Cartesian form factor, full grid)",
@@ -399,12 +471,13 @@ def main():
                    "grid": list(n), "qmax": W.grid.qmax[0], "precision": args.precision,
                    "screen_eps": args.screen_eps, "pairs_kept_K": K, "terms_kept_R": R,
                    "pairs_total": info["pairs_total"], "terms_total": info["prim_pairs_total"]},
-        "stages_ms": {"precompute": prep_ms, "vtables": vt_ms, "grid_kernel": grid_ms},
-        "kernel_only_value": ns * nq / grid_s,
+        "stages_ms": head["stages_ms"],
+        "kernel_only_value": head["kernel_only_value"],
         "roofline": roof,
         "cpu_baseline": cpu,
-        "errors_vs_oracle": errors,
+        "errors_vs_oracle": head["errors_vs_oracle"],
         "other_precision": other,
+        "config2": config2,
         "symmetric_grid": symmetric,
         "serving": serving,
     }

@@ -178,8 +178,9 @@ int scff_eval_grid(scff_ctx* ctx, const scff_grid* grid, int precision, float* f
 /*
  * Symmetric-grid mode (off by default).  The transition densities are real,
  * so f(-q) = f(q)* (Sec. 4: e^{iq.r} is the only complex factor of the
- * integrand).  With enable = 1, scff_eval_grid on a grid with
- * qmin[a] == -qmax[a] on every axis evaluates the planes ix < ceil(nx/2)
+ * integrand).  With enable = 1, scff_eval_grid on a grid symmetric about
+ * q = 0 (qmin[a] == -qmax[a] on every axis of n[a] > 1 points, and
+ * qmin[a] == 0 on every one-point axis) evaluates the planes ix < ceil(nx/2)
  * and writes every other point as the conjugate of its mirror point
  * (nx-1-ix, ny-1-iy, nz-1-iz); |f|^2 is copied.  Other grids are evaluated
  * in full.  enable must be 0 or 1 (else SCFF_EINVAL).
@@ -187,9 +188,14 @@ int scff_eval_grid(scff_ctx* ctx, const scff_grid* grid, int precision, float* f
 int scff_set_symmetry(scff_ctx* ctx, int enable);
 
 /*
- * Evaluate at arbitrary points q [n_q][3] (host array, a.u.).  Same outputs
- * as scff_eval_grid with the grid axes replaced by the point index:
- * f [n_states][n_q][2], f2 [n_states][n_q].  1 <= n_q <= 2^24.
+ * Evaluate at arbitrary points q [n_q][3] (host array, a.u.; paper Sec. 5.3:
+ * individual points from the V-tensors).  Same outputs as scff_eval_grid
+ * with the grid axes replaced by the point index: f [n_states][n_q][2],
+ * f2 [n_states][n_q].  1 <= n_q <= 2^24.  precision must be SCFF_FP32 (the
+ * points kernel runs on the FP32 vector units, with the same FP32 block
+ * sums folded into FP64 every 32 pairs as the grid kernel's FP32 path);
+ * SCFF_BF16X3 is rejected with SCFF_EINVAL.  The call waits for its
+ * stream: it returns with the outputs written (host or device pointers).
  */
 int scff_eval_points(scff_ctx* ctx, int n_q, const double* q, int precision, float* f,
                      float* f2, int out_on_device, void* hip_stream);

@@ -131,6 +131,48 @@ def _i(a):
     return a.ctypes.data_as(P(c_int))
 
 
+def _molecule_arrays(mol):
+    """Contiguous copies of a molecule's arrays, with their lengths checked
+    against each other (the C side trusts the lengths it is given); returns
+    (arrays, nbf)."""
+    arrs = [np.ascontiguousarray(mol.xyz, np.float64), np.ascontiguousarray(mol.shell_atom, np.int32),
+            np.ascontiguousarray(mol.shell_l, np.int32), np.ascontiguousarray(mol.shell_nprim, np.int32),
+            np.ascontiguousarray(mol.exps, np.float64), np.ascontiguousarray(mol.coefs, np.float64)]
+    xyz, sa, sl, sn, ex, co = arrs
+    if xyz.ndim != 2 or xyz.shape[1] != 3:
+        raise ValueError(f"xyz must be [n_atoms, 3], got {xyz.shape}")
+    if not (sa.ndim == sl.ndim == sn.ndim == 1 and sa.shape == sl.shape == sn.shape):
+        raise ValueError("shell_atom, shell_l and shell_nprim must be 1D arrays of one length")
+    if np.any(sn < 0) or np.any((sl < 0) | (sl > 2)):
+        raise ValueError("shell_nprim must be >= 0 and shell_l in 0..2")
+    nprim = int(sn.sum())
+    if ex.shape != (nprim,) or co.shape != (nprim,):
+        raise ValueError(f"exps and coefs must hold sum(shell_nprim) = {nprim} values each")
+    nbf = int(sum((l + 1) * (l + 2) // 2 for l in sl.tolist()))
+    return arrs, nbf
+
+
+def _check_T(T, nbf):
+    if T.ndim != 3 or T.shape[1:] != (nbf, nbf):
+        raise ValueError(f"T must be [n_states, {nbf}, {nbf}], got {T.shape}")
+
+
+def _check_device_tensor(t, name, dtype, shape, device):
+    """A torch tensor the C side will write or read through a raw pointer:
+    exact dtype and shape, contiguous, on the context's GPU."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device.type != "cuda" or (t.device.index if t.device.index is not None else 0) != device:
+        raise ValueError(f"{name} must be on cuda:{device}, got {t.device}")
+
+
 def make_grid(n, qmin, qmax) -> scff_grid:
     g = scff_grid()
     for a in range(3):
@@ -179,12 +221,7 @@ class Context:
 
     # ---- loads
     def load_molecule(self, mol, normalise: bool = True) -> int:
-        self._mol_keep = [np.ascontiguousarray(mol.xyz, np.float64),
-                          np.ascontiguousarray(mol.shell_atom, np.int32),
-                          np.ascontiguousarray(mol.shell_l, np.int32),
-                          np.ascontiguousarray(mol.shell_nprim, np.int32),
-                          np.ascontiguousarray(mol.exps, np.float64),
-                          np.ascontiguousarray(mol.coefs, np.float64)]
+        self._mol_keep, _ = _molecule_arrays(mol)
         xyz, sa, sl, sn, ex, co = self._mol_keep
         nbf = c_int()
         check(scff_load_molecule(self._h, xyz.shape[0], _d(xyz), sl.shape[0], _i(sa), _i(sl), _i(sn),
@@ -196,12 +233,15 @@ class Context:
         T = np.ascontiguousarray(T, np.float64)
         if T.ndim == 2:
             T = T[None]
+        _check_T(T, self.nbf)
         check(scff_load_transitions(self._h, T.shape[0], _d(T)))
         self.n_states = T.shape[0]
 
     def load_transitions_device(self, T_dev, stream=None):
         """T_dev: a contiguous float64 device tensor [n_states, nbf, nbf] (e.g. torch on 'cuda')."""
-        ns = int(T_dev.shape[0])
+        import torch
+        ns = int(T_dev.shape[0]) if T_dev.dim() == 3 else -1
+        _check_device_tensor(T_dev, "T_dev", torch.float64, (ns, self.nbf, self.nbf), self.device)
         check(scff_load_transitions_device(self._h, ns, ctypes.c_void_p(T_dev.data_ptr()), _stream_ptr(stream)))
         self.n_states = ns
 
@@ -241,6 +281,12 @@ class Context:
 
     def eval_grid_device(self, grid, f=None, f2=None, precision="fp32", stream=None):
         """Device outputs into torch tensors f ([s,nx,ny,nz,2] float32) / f2 ([s,nx,ny,nz] float32)."""
+        import torch
+        shape = (self.n_states,) + tuple(int(x) for x in grid.n)
+        if f is not None:
+            _check_device_tensor(f, "f", torch.float32, shape + (2,), self.device)
+        if f2 is not None:
+            _check_device_tensor(f2, "f2", torch.float32, shape, self.device)
         g = make_grid(grid.n, grid.qmin, grid.qmax)
         check(scff_eval_grid(self._h, ctypes.byref(g), PRECISIONS[precision],
                              f.data_ptr() if f is not None else None,
@@ -283,9 +329,8 @@ class Server:
         T = np.ascontiguousarray(T, np.float64)
         if T.ndim == 2:
             T = T[None]
-        arrs = [np.ascontiguousarray(mol.xyz, np.float64), np.ascontiguousarray(mol.shell_atom, np.int32),
-                np.ascontiguousarray(mol.shell_l, np.int32), np.ascontiguousarray(mol.shell_nprim, np.int32),
-                np.ascontiguousarray(mol.exps, np.float64), np.ascontiguousarray(mol.coefs, np.float64)]
+        arrs, nbf = _molecule_arrays(mol)
+        _check_T(T, nbf)
         shape = (T.shape[0],) + tuple(grid.n)
         f = np.empty(shape + (2,), np.float32) if want_f else None
         f2 = np.empty(shape, np.float32) if want_f2 else None

@@ -56,7 +56,7 @@ __device__ __forceinline__ bf16x8 bf16x8_of(uint32_t a0, uint32_t a1, uint32_t b
     return __builtin_bit_cast(bf16x8, uintx4{a0, a1, b0, b1});
 }
 
-constexpr int kFoldChunks = 32;   // points kernel: units (256 pairs) per FP32 partial sum
+constexpr int kPointFoldUnits = 4;   // points kernel: units (32 pairs) per FP32 block sum
 
 // ---------------------------------------------------------------- 1D tables
 
@@ -145,7 +145,7 @@ __device__ __forceinline__ void barrier_dma() {
 
 template <int SB, int QZL, int WPE, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
-    const float2* __restrict__ V, int vstride, const int4* __restrict__ terms,
+    const float2* __restrict__ V, int vstride, int vrows, const int4* __restrict__ terms,
     const int4* __restrict__ chunks, ChunkSplit sp, const uint32_t* __restrict__ Tp, int3 n, int3 ntiles,
     int nx_eval, int n_states, float2* __restrict__ f, float* __restrict__ f2, double2* __restrict__ partial,
     long long part_stride) {
@@ -210,8 +210,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         int t0 = threadIdx.x;
         asm volatile("" : "+v"(t0));
         const int p0 = t0 >> 4;
+        // row ids are clamped to the table, so no DMA can leave it whatever
+        // the slot table holds (the host validates the table on request)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(p0 + 16 * j, nptl - 1) + axis];
+        for (int j = 0; j < NJ; ++j)
+            rid[j] = (int)min((unsigned)tc[4 * min(p0 + 16 * j, nptl - 1) + axis], (unsigned)(vrows - 1));
     };
     // DMA of chunk c's raw slices into buffer rbase and its Tp block into tbase
     auto issue_dma = [&](int c, uint32_t rbase, uint32_t tbase) {
@@ -512,16 +515,23 @@ __global__ void mirror_kernel(int3 n, int nx_eval, int n_states, float2* __restr
 template <int SB>
 __global__ __launch_bounds__(64) void points_kernel(
     const VRowDev* __restrict__ rows, const int4* __restrict__ terms,
-    const int* __restrict__ chunk_off, const int* __restrict__ chunk_npp, int n_chunks,
+    const int* __restrict__ chunk_off, const int* __restrict__ chunk_npp, int n_units,
     const float* __restrict__ Tp, const double* __restrict__ qpts, int nq, int n_states,
     float2* __restrict__ f, float* __restrict__ f2) {
     constexpr int SW = 16 * SB;
     const int iq = blockIdx.x * blockDim.x + threadIdx.x;
     if (iq >= nq) return;
     const double qx = qpts[3 * iq], qy = qpts[3 * iq + 1], qz = qpts[3 * iq + 2];
-    float br[SW], bi[SW], tr_[SW], ti[SW];
-    for (int s = 0; s < SW; ++s) br[s] = bi[s] = tr_[s] = ti[s] = 0.f;
-    for (int c = 0; c < n_chunks; ++c) {
+    // FP32 sums over the pairs of kPointFoldUnits units, folded into FP64
+    // totals: the same accumulation as the grid kernel's FP32 path, which
+    // bounds the rounding error of the long, cancelling pair sum
+    float br[SW], bi[SW];
+    double tr_[SW], ti[SW];
+    for (int s = 0; s < SW; ++s) {
+        br[s] = bi[s] = 0.f;
+        tr_[s] = ti[s] = 0.0;
+    }
+    for (int c = 0; c < n_units; ++c) {
         const int npp = chunk_npp[c];
         const int4* tc = terms + chunk_off[c];
         for (int pair = 0; pair < kChunk; ++pair) {
@@ -542,18 +552,18 @@ __global__ __launch_bounds__(64) void points_kernel(
                 bi[s] = fmaf(tp[s], gi, bi[s]);
             }
         }
-        if ((c + 1) % kFoldChunks == 0)
+        if ((c + 1) % kPointFoldUnits == 0 || c + 1 == n_units)
             for (int s = 0; s < SW; ++s) {
-                tr_[s] += br[s];
-                ti[s] += bi[s];
+                tr_[s] += (double)br[s];
+                ti[s] += (double)bi[s];
                 br[s] = bi[s] = 0.f;
             }
     }
     for (int s = 0; s < n_states; ++s) {
-        const float vr = tr_[s] + br[s], vi = ti[s] + bi[s];
+        const double vr = tr_[s], vi = ti[s];
         const size_t o = (size_t)s * nq + iq;
-        if (f) f[o] = make_float2(vr, vi);
-        if (f2) f2[o] = vr * vr + vi * vi;
+        if (f) f[o] = make_float2((float)vr, (float)vi);
+        if (f2) f2[o] = (float)(vr * vr + vi * vi);
     }
 }
 
@@ -572,7 +582,7 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
 }
 
 template <int SB, int QZL, int WPE, bool BF>
-static hipError_t launch_grid_t(const float2* V, int vstride, const int4* terms, const int4* chunks,
+static hipError_t launch_grid_t(const float2* V, int vstride, int vrows, const int4* terms, const int4* chunks,
                                 const ChunkSplit& sp, const uint32_t* Tp, const int n[3], int nx_eval,
                                 int n_states, float2* f, float* f2, double2* part, hipStream_t st) {
     const int3 nn = make_int3(n[0], n[1], n[2]);
@@ -580,7 +590,7 @@ static hipError_t launch_grid_t(const float2* V, int vstride, const int4* terms,
     const long long blocks = (long long)nt.x * nt.y * nt.z * sp.n;
     const long long stride = (long long)n_states * n[0] * n[1] * n[2];
     hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE, BF>), dim3((unsigned)blocks), dim3(256), 0, st, V, vstride,
-                       terms, chunks, sp, Tp, nn, nt, nx_eval, n_states, f, f2, sp.n > 1 ? part : nullptr,
+                       vrows, terms, chunks, sp, Tp, nn, nt, nx_eval, n_states, f, f2, sp.n > 1 ? part : nullptr,
                        stride);
     return hipGetLastError();
 }
@@ -601,12 +611,12 @@ int vtable_stride(const int n[3]) {
     return ((m + 15) / 16) * 16 + 16;
 }
 
-hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride,
+hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride, int vrows,
                        const int4* terms, const int4* chunks, const ChunkSplit& sp, const float* Tp,
                        const uint32_t* tp_bf, const int n[3], int nx_eval, int n_states, float2* f, float* f2,
                        double2* part, hipStream_t st) {
     if (precision != 0 && precision != 1) return hipErrorInvalidValue;
-    if (vstride < vtable_stride(n)) return hipErrorInvalidValue;
+    if (vstride < vtable_stride(n) || vrows < 1) return hipErrorInvalidValue;
     if (nx_eval < 1 || nx_eval > n[0]) return hipErrorInvalidValue;
     if (sp.n < 1 || sp.n > kMaxSplit || sp.lo[0] != 0) return hipErrorInvalidValue;
     for (int j = 0; j < sp.n; ++j)
@@ -614,7 +624,7 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
     if (sp.n > 1 && !part) return hipErrorInvalidValue;
     const uint32_t* tp32 = reinterpret_cast<const uint32_t*>(Tp);
 #define SCFF_GRID(SB_, QZL_, WPE_, BF_) \
-    return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, terms, chunks, sp, BF_ ? tp_bf : tp32, n, nx_eval, \
+    return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, vrows, terms, chunks, sp, BF_ ? tp_bf : tp32, n, nx_eval, \
                                                n_states, f, f2, part, st)
     // <=16 states: 4 q_z per lane (8 q values); 17..32 states: 2 q_z per lane,
     // so the accumulators of both precisions fit 2 waves per SIMD
@@ -652,15 +662,15 @@ hipError_t launch_mirror(const int n[3], int nx_eval, int n_states, float2* f, f
 }
 
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
-                         const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
+                         const int* cnpp, int n_units, const float* Tp, const double* q, int nq,
                          int n_states, float2* f, float* f2, hipStream_t st) {
     const int blocks = (nq + 63) / 64;
     if (state_blocks == 1)
         hipLaunchKernelGGL((points_kernel<1>), dim3(blocks), dim3(64), 0, st, rows, terms, coff, cnpp,
-                           n_chunks, Tp, q, nq, n_states, f, f2);
+                           n_units, Tp, q, nq, n_states, f, f2);
     else
         hipLaunchKernelGGL((points_kernel<2>), dim3(blocks), dim3(64), 0, st, rows, terms, coff, cnpp,
-                           n_chunks, Tp, q, nq, n_states, f, f2);
+                           n_units, Tp, q, nq, n_states, f, f2);
     return hipGetLastError();
 }
 

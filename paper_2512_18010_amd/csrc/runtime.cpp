@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <utility>
 #include <string>
@@ -17,7 +18,7 @@ namespace scff {
 hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int n[3],
                          const double qmin[3], const double dq[3], float2* V, hipStream_t st);
 int vtable_stride(const int n[3]);
-hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride,
+hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride, int vrows,
                        const int4* terms, const int4* chunks, const ChunkSplit& sp, const float* Tp,
                        const uint32_t* tp_bf, const int n[3], int nx_eval, int n_states, float2* f, float* f2,
                        double2* part, hipStream_t st);
@@ -76,6 +77,9 @@ struct scff_ctx {
     // or a synchronisation (an error return in the middle of a call)
     bool async_open = false;
     int symmetry = 0;   // evaluate half of a grid symmetric about q = 0 (scff_set_symmetry)
+    // check the precompute's tables on the host after every precompute
+    // (environment SCFF_VALIDATE set and not "0" when the context is created)
+    bool validate = false;
     int n_cu = 256;     // compute units of the device
     DeviceBuffer d_part;   // FP64 partial results of a split chunk list
 };
@@ -180,6 +184,38 @@ int record(scff_ctx* c, int which, hipStream_t st) {
     return hip_check(hipEventRecord(c->ev[which], st), "event record");
 }
 
+// Host check of the tables the grid kernel indexes with (on request): every
+// term slot names a 1D-table row in [0, rows) and every chunk lies inside the
+// unit and slot arrays.  A violation is an engine bug; it is reported as
+// SCFF_EDEVICE before any kernel reads the tables.
+int validate_prep(scff_ctx* c, hipStream_t st) {
+    const PrepResult& p = c->pres;
+    std::vector<int> slots((size_t)p.n_slots * 4);
+    int rc;
+    if (!slots.empty() &&
+        (rc = hip_check(hipMemcpyAsync(slots.data(), c->prep.slots.p, slots.size() * sizeof(int),
+                                       hipMemcpyDeviceToHost, st), "D2H slots")))
+        return rc;
+    if ((rc = hip_check(hipStreamSynchronize(st), "validation sync"))) return rc;
+    for (size_t i = 0; i < slots.size(); i += 4)
+        for (int a = 0; a < 3; ++a)
+            if (slots[i + a] < 0 || slots[i + a] >= p.n_rows)
+                return fail(SCFF_EDEVICE, "precompute produced a term slot outside the 1D tables (slot " +
+                                              std::to_string(i / 4) + ", axis " + std::to_string(a) + ", row " +
+                                              std::to_string(slots[i + a]) + " of " + std::to_string(p.n_rows) + ")");
+    const std::vector<int>& ch = c->prep.chunk_host;
+    if ((int)ch.size() < 4 * p.n_chunks) return fail(SCFF_EDEVICE, "chunk table shorter than its chunk count");
+    for (int k = 0; k < p.n_chunks; ++k) {
+        const long long u0 = ch[4 * k], nu = ch[4 * k + 1], npp = ch[4 * k + 2], s0 = ch[4 * k + 3];
+        if (u0 < 0 || nu < 1 || nu > kMaxUnitsPerChunk || u0 + nu > p.n_units || npp < 1 ||
+            npp > kMaxTermsPerPair || nu * kChunk * npp > kMaxChunkTerms || s0 < 0 ||
+            s0 + nu * kChunk * npp > p.n_slots)
+            return fail(SCFF_EDEVICE, "precompute produced a chunk outside the unit or slot arrays (chunk " +
+                                          std::to_string(k) + ")");
+    }
+    return SCFF_OK;
+}
+
 int ensure_prepared(scff_ctx* c, hipStream_t st) {
     if (!c->have_mol) return fail(SCFF_ESTATE, "no molecule loaded");
     if (!c->have_T) return fail(SCFF_ESTATE, "no transitions loaded");
@@ -215,6 +251,7 @@ int ensure_prepared(scff_ctx* c, hipStream_t st) {
     if ((rc = record(c, EV_PREP1, st))) return rc;
     c->ev_prep = c->timing;
     c->pres = res;
+    if (c->validate && (rc = validate_prep(c, st))) return rc;
     c->prepared = true;
     return SCFF_OK;
 }
@@ -247,10 +284,17 @@ int build_vtables(scff_ctx* c, const scff_grid* g, hipStream_t st) {
                      "vtable kernel launch");
 }
 
-// every axis runs from -q_max to +q_max, so index i and n-1-i are q and -q
+// every axis holds -q with q: index i and n-1-i are q and -q.  An axis of
+// n > 1 points runs from -q_max to +q_max; a one-point axis holds the single
+// value qmin (its qmax is not used), which is its own negative only at 0.
 bool grid_symmetric(const scff_grid* g) {
-    for (int a = 0; a < 3; ++a)
-        if (g->qmin[a] != -g->qmax[a]) return false;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] == 1) {
+            if (g->qmin[a] != 0.0) return false;
+        } else if (g->qmin[a] != -g->qmax[a]) {
+            return false;
+        }
+    }
     return true;
 }
 
@@ -390,6 +434,8 @@ int scff_create(int device, size_t hbm_budget_bytes, scff_ctx** out) {
     // refused) the same copies go through pageable memory
     if (hipHostMalloc(&c->prep.pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) c->prep.pinned = nullptr;
     c->budget = hbm_budget_bytes;
+    const char* v = std::getenv("SCFF_VALIDATE");
+    c->validate = v && v[0] && std::strcmp(v, "0") != 0;
     *out = c;
     return ok();
 }
@@ -578,7 +624,7 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
     const PrepResult& p = c->pres;
     // f(-q) = f(q)* for real T: on a grid symmetric about q = 0 the planes
     // ix >= ceil(nx/2) are the conjugates of computed ones (symmetric mode)
-    rc = hip_check(launch_grid(p.state_blocks, precision, (const float2*)c->d_vtab.p, c->vtab_stride,
+    rc = hip_check(launch_grid(p.state_blocks, precision, (const float2*)c->d_vtab.p, c->vtab_stride, c->vtab_rows,
                                (const int4*)c->prep.slots.p, (const int4*)c->prep.chunks.p, pl.sp,
                                (const float*)c->prep.tp32.p, (const uint32_t*)c->prep.tpbf.p, g->n, pl.nx_eval,
                                c->n_states, df, df2, part, st),
@@ -644,6 +690,10 @@ int scff_eval_points(scff_ctx* c, int n_q, const double* q, int precision, float
     if (!q) return fail(SCFF_EINVAL, "q is NULL");
     int rc;
     if ((rc = check_precision(precision))) return rc;
+    // points run on the FP32 vector units only (no matrix-core contraction)
+    if (precision != SCFF_FP32)
+        return fail(SCFF_EINVAL, "scff_eval_points supports SCFF_FP32 only (the split-BF16 contraction is a "
+                                 "grid-kernel path)");
     for (int i = 0; i < 3 * n_q; ++i)
         if (!std::isfinite(q[i])) return fail(SCFF_EINVAL, "non-finite q");
     if ((rc = set_device(c))) return rc;

@@ -17,3 +17,11 @@ def pytest_configure(config):
 def oracle_mod():
     import oracle
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter):
+    from tests.metrics import REPORT
+    if REPORT:
+        terminalreporter.section("errors against the FP64 oracle (peak-normalised |f|^2, per transition)")
+        for line in REPORT:
+            terminalreporter.write_line(line)

@@ -10,6 +10,15 @@ import numpy as np
 
 TOL_F2 = {"fp32": 1e-6, "bf16x3": 1e-4}
 
+# Error lines recorded by the GPU tests, printed in the terminal summary of
+# the run (so the error of every transition is visible without -s).
+REPORT = []
+
+
+def report(line: str):
+    REPORT.append(line)
+    print(line, flush=True)
+
 
 def errors(f_test, f_ref):
     """f_*: complex [n_states, ...].  Returns dict of per-state arrays."""

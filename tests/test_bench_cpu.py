@@ -29,3 +29,20 @@ def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
     assert bench.kernel_source_hash() == h0
     (csrc / "kernels.hip").write_text("int a;\nint b2;\n")
     assert bench.kernel_source_hash() != h0
+
+
+def test_roofline_picks_the_binding_pipe():
+    """The roofline object names the pipe with the larger algorithmic time
+    bound: the matrix cores for FP32 contraction with many transitions, the
+    vector units when the split-BF16 contraction is cheap."""
+    sys.path.insert(0, ROOT)
+    import bench
+    K, R, ns, nq = 59236, 234720, 24, 96 ** 3
+    r = bench.grid_roofline(K, R, ns, nq, "fp32", 100.0)
+    a = r["algorithmic"]
+    assert r["bound"] == "mfma" and abs(a["t_mfma_ms"] - 4.0 * K * ns * nq / 157.3e12 * 1e3) < 1e-9
+    assert abs(r["frac"] - a["t_mfma_ms"] / 100.0) < 1e-12
+    r = bench.grid_roofline(K, R, ns, nq, "bf16x3", 50.0)
+    a = r["algorithmic"]
+    assert r["bound"] == "alu" and abs(r["frac"] - a["t_valu_ms"] / 50.0) < 1e-12
+    assert abs(a["t_mfma_ms"] - 3 * 4.0 * K * ns * nq / 2.5166e15 * 1e3) < 1e-9

@@ -213,3 +213,47 @@ def test_symmetric_grid_mode(binding, oracle_mod, precision, nx):
     e = errors(f_sym, oracle_mod.eval_grid(W.mol, W.T, sym, n_threads=NTH))
     log(f"[symmetric nx={nx}] {precision}: peak-normalised |f|^2 err {e['f2_peak_norm'].max():.3e}")
     assert e["f2_peak_norm"].max() <= TOL_F2[precision]
+
+
+@pytest.mark.parametrize("qy", [4.5, 0.0])
+def test_symmetric_mode_one_point_axis(binding, oracle_mod, qy):
+    """A one-point axis holds the single value q_min.  With q_y = -4.5 (and
+    q_max = +4.5, unused) the grid is not symmetric about q = 0, so the mode
+    must evaluate it in full (bit for bit as without the mode); with q_y = 0
+    it is symmetric and the mirrored planes must still match the oracle."""
+    W = wl.make_config(0)
+    g = wl.Grid(n=(12, 1, 37), qmin=(-5.0, -qy, -6.0), qmax=(5.0, qy, 6.0))
+    with binding.Context(0) as ctx:
+        ctx.load_molecule(W.mol)
+        ctx.load_transitions(W.T)
+        ctx.set_options(0.0, 1.0)
+        f_full, f2_full = ctx.eval_grid_host(g, "fp32")
+        ctx.set_symmetry(True)
+        f_sym, f2_sym = ctx.eval_grid_host(g, "fp32")
+    if qy != 0.0:
+        assert np.array_equal(f_sym, f_full) and np.array_equal(f2_sym, f2_full)
+    e = errors(f_sym, oracle_mod.eval_grid(W.mol, W.T, g, n_threads=NTH))
+    log(f"[one-point axis q_y={-qy}] peak-normalised |f|^2 err {e['f2_peak_norm'].max():.3e}")
+    assert e["f2_peak_norm"].max() <= TOL_F2["fp32"]
+
+
+def test_validated_precompute_tables(binding, monkeypatch):
+    """With SCFF_VALIDATE set when the context is created, every precompute's
+    term slots and chunk table are checked on the host before a kernel reads
+    them; the engine's own tables pass, across screening levels, and the
+    results equal an unvalidated context's bit for bit."""
+    W = wl.make_config(0)
+    g = small_case().grid
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("SCFF_VALIDATE", flag)
+        with binding.Context(0) as ctx:
+            ctx.load_molecule(W.mol)
+            ctx.load_transitions(W.T)
+            res = []
+            for eps in (0.0, 1e-9, 1e-6):
+                ctx.set_options(eps, 1.0)
+                res.append(ctx.eval_grid_host(g, "fp32"))
+            outs.append(res)
+    for (fa, f2a), (fb, f2b) in zip(*outs):
+        assert np.array_equal(fa, fb) and np.array_equal(f2a, f2b)

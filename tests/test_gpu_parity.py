@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import workload as wl
-from tests.metrics import TOL_F2, errors
+from tests.metrics import TOL_F2, errors, report
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,7 @@ def check(name, f_gpu, f2_gpu, f_ref, precision):
     np.testing.assert_allclose(f2_gpu, np.abs(f_gpu) ** 2, rtol=2e-6, atol=1e-12 * np.abs(f_gpu).max() ** 2)
     log(f"[{name}] {precision}: max peak-normalised |f|^2 err {e['f2_peak_norm'].max():.3e}, "
         f"complex {e['complex'].max():.3e}, rel(big) {e['f2_rel_big'].max():.3e}")
+    report(f"[{name}] {precision}: " + " ".join(f"{x:.2e}" for x in e["f2_peak_norm"]))
     assert e["f2_peak_norm"].max() <= TOL_F2[precision], e["f2_peak_norm"]
     return e
 
@@ -100,8 +101,12 @@ def test_config1_sampled(eng, oracle_mod, precision):
     sampled_parity(eng, oracle_mod, 1, precision, 256)
 
 
-def test_config2_sampled(eng, oracle_mod):
-    sampled_parity(eng, oracle_mod, 2, "fp32", 128)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_config2_sampled(eng, oracle_mod, precision):
+    """The 190-function, 12-transition molecule on the 128^3 grid, split-BF16
+    against plain FP32: a seeded sample plus every transition's |f|^2
+    maximum against the oracle, the error of each transition logged."""
+    sampled_parity(eng, oracle_mod, 2, precision, 128)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
@@ -180,6 +185,42 @@ def test_conjugate_symmetry_on_gpu(eng):
     g = np.conj(f[:, ::-1, ::-1, ::-1])
     scale = np.abs(f).max()
     assert np.abs(f - g).max() <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_points_at_scale(eng, oracle_mod, cfg):
+    """scff_eval_points on the benchmark molecules (190 functions and 12
+    transitions; 570 functions and 24 transitions, screened at 1e-9): q = 0,
+    the grid corners |q_i| = q_max, points just inside them and seeded
+    random points of the grid's box, against the oracle; the error of a point
+    set is normalised by the peak over the same set."""
+    W = wl.make_config(cfg)
+    qm = W.grid.qmax[0]
+    rng = np.random.Generator(np.random.PCG64(600 + cfg))
+    corners = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], float) * qm
+    axes = np.concatenate([np.eye(3), -np.eye(3)]) * qm
+    q = np.concatenate([np.zeros((1, 3)), corners, 0.999 * corners, axes, 0.98 * axes,
+                        rng.uniform(-qm, qm, size=(64, 3)), rng.uniform(-0.3, 0.3, size=(16, 3))])
+    log(f"case points cfg{cfg}: {len(q)} points")
+    eng.load_molecule(W.mol)
+    eng.load_transitions(W.T)
+    eng.set_options(1e-9 if cfg == 3 else 0.0, 1.0)
+    f, f2 = eng.eval_points(q)
+    ref = oracle_mod.eval_points(W.mol, W.T, q, n_threads=NTH)
+    check(f"cfg{cfg} points", f, f2, ref, "fp32")
+
+
+def test_points_reject_split_bf16(eng):
+    """Points run on the FP32 vector units only: the split-BF16 precision is
+    refused rather than silently computed in FP32."""
+    from paper_2512_18010_amd import binding
+    W = wl.make_config(0)
+    eng.load_molecule(W.mol)
+    eng.load_transitions(W.T)
+    eng.set_options(0.0, 1.0)
+    with pytest.raises(binding.ScffError) as ei:
+        eng.eval_points(np.zeros((3, 3)), precision="bf16x3")
+    assert ei.value.code == binding.SCFF_EINVAL
 
 
 def test_points_parity(eng, oracle_mod):
