@@ -176,6 +176,34 @@ int scff_eval_grid(scff_ctx* ctx, const scff_grid* grid, int precision, float* f
                    int out_on_device, void* hip_stream);
 
 /*
+ * Allocation-free variant of scff_eval_grid, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  It computes exactly what
+ * scff_eval_grid computes into device outputs, with the same kernels, but
+ * calls no hipMalloc, hipFree or allocating library routine: the 1D tables
+ * of the grid, and the FP64 partial sums of a split chunk list when they
+ * fit after the tables, live in a static per-device scratch array of
+ * 256 MiB (held by every device the library runs on until the process ends;
+ * the 190-function, 64^3 problem's tables take 81 MB).
+ *   f, f2          device pointers as for scff_eval_grid with
+ *                  out_on_device = 1 (either may be NULL); asynchronous on
+ *                  hip_stream (NULL = default stream).
+ * Requires the precompute of the loaded problem to have run: after the
+ * last scff_load_*, scff_set_options call, call scff_query or an
+ * evaluation once (else SCFF_ESTATE; the precompute allocates).  A grid
+ * whose 1D tables exceed the scratch (rows x (roundup16(max n) + 16) x 8
+ * bytes > 256 MiB) is rejected with SCFF_EINVAL before any device work; a
+ * split whose partial sums do not fit is not taken (the grid is evaluated
+ * unsplit, equal up to the order of the FP64 sums).  Every call on one GPU
+ * shares that GPU's scratch, which keeps the last call's contents (every
+ * value a call reads is written by that call first): calls that overlap on
+ * one GPU (other streams, other contexts, other threads) race and must be
+ * serialised by the caller.
+ */
+int scff_eval_grid_noalloc(scff_ctx* ctx, const scff_grid* grid, int precision, float* f, float* f2,
+                           void* hip_stream);
+
+/*
  * Symmetric-grid mode (off by default).  The transition densities are real,
  * so f(-q) = f(q)* (Sec. 4: e^{iq.r} is the only complex factor of the
  * integrand).  With enable = 1, scff_eval_grid on a grid symmetric about

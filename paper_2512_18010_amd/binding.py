@@ -93,6 +93,8 @@ scff_load_transitions_device = _fn("scff_load_transitions_device", c_int, [c_voi
 scff_set_options = _fn("scff_set_options", c_int, [c_void_p, c_double, c_double])
 scff_eval_grid = _fn("scff_eval_grid", c_int,
                      [c_void_p, P(scff_grid), c_int, c_void_p, c_void_p, c_int, c_void_p])
+scff_eval_grid_noalloc = _fn("scff_eval_grid_noalloc", c_int,
+                             [c_void_p, P(scff_grid), c_int, c_void_p, c_void_p, c_void_p])
 scff_eval_points = _fn("scff_eval_points", c_int,
                        [c_void_p, c_int, P(c_double), c_int, c_void_p, c_void_p, c_int, c_void_p])
 scff_query = _fn("scff_query", c_int, [c_void_p, P(scff_info)])

@@ -135,6 +135,12 @@ std::string build_basis(Basis& b, int n_atoms, const double* xyz, int n_shells,
 hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStream_t st,
                     const std::function<hipError_t(DeviceBuffer&, size_t)>& alloc);
 
+// ---- static scratch (scratch.hip) ----
+// Bytes of the per-device scratch array of scff_eval_grid_noalloc.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+// Device address of this device's array (device current; resolved once).
+hipError_t scratch_address(int device, void** ptr);
+
 // ---- runtime.cpp ----
 // Thread-local message returned by scff_last_error().
 void set_error(const std::string& msg);

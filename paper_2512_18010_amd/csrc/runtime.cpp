@@ -82,6 +82,7 @@ struct scff_ctx {
     bool validate = false;
     int n_cu = 256;     // compute units of the device
     DeviceBuffer d_part;   // FP64 partial results of a split chunk list
+    void* scratch = nullptr;   // this device's static scratch array (scff_eval_grid_noalloc)
 };
 
 namespace {
@@ -354,6 +355,31 @@ EvalPlan plan_eval(const scff_ctx* c, const scff_grid* g, bool allow_split = tru
     return e;
 }
 
+// The fused grid kernel (with the split reduction and the symmetric-mode
+// mirror when the plan asks for them) on tables V, events around it.
+int run_grid(scff_ctx* c, const scff_grid* g, int precision, const float2* V, int vstride, int vrows,
+             const EvalPlan& pl, double2* part, float2* df, float* df2, hipStream_t st) {
+    int rc;
+    if ((rc = record(c, EV_GRID0, st))) return rc;
+    const PrepResult& p = c->pres;
+    // f(-q) = f(q)* for real T: on a grid symmetric about q = 0 the planes
+    // ix >= ceil(nx/2) are the conjugates of computed ones (symmetric mode)
+    rc = hip_check(launch_grid(p.state_blocks, precision, V, vstride, vrows, (const int4*)c->prep.slots.p,
+                               (const int4*)c->prep.chunks.p, pl.sp, (const float*)c->prep.tp32.p,
+                               (const uint32_t*)c->prep.tpbf.p, g->n, pl.nx_eval, c->n_states, df, df2, part, st),
+                   "grid kernel launch");
+    if (rc) return rc;
+    if (pl.sp.n > 1 &&
+        (rc = hip_check(launch_reduce(part, pl.sp.n, g->n, pl.nx_eval, c->n_states, df, df2, st), "reduce launch")))
+        return rc;
+    if (pl.nx_eval < g->n[0] &&
+        (rc = hip_check(launch_mirror(g->n, pl.nx_eval, c->n_states, df, df2, st), "mirror kernel launch")))
+        return rc;
+    if ((rc = record(c, EV_GRID1, st))) return rc;
+    c->ev_recorded = c->timing;
+    return SCFF_OK;
+}
+
 int check_precision(int precision) {
     if (precision != SCFF_FP32 && precision != SCFF_BF16X3) return fail(SCFF_EINVAL, "unknown precision");
     return SCFF_OK;
@@ -436,6 +462,10 @@ int scff_create(int device, size_t hbm_budget_bytes, scff_ctx** out) {
     c->budget = hbm_budget_bytes;
     const char* v = std::getenv("SCFF_VALIDATE");
     c->validate = v && v[0] && std::strcmp(v, "0") != 0;
+    // resolved here, with the device current, so that the allocation-free
+    // entry point does no set-up of its own; the ordering event likewise
+    if (scratch_address(device, &c->scratch) != hipSuccess) c->scratch = nullptr;
+    if (hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess) c->order_ev = nullptr;
     *out = c;
     return ok();
 }
@@ -620,24 +650,9 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
         else
             pl = plan_eval(c, g, false);
     }
-    if ((rc = record(c, EV_GRID0, st))) return rc;
-    const PrepResult& p = c->pres;
-    // f(-q) = f(q)* for real T: on a grid symmetric about q = 0 the planes
-    // ix >= ceil(nx/2) are the conjugates of computed ones (symmetric mode)
-    rc = hip_check(launch_grid(p.state_blocks, precision, (const float2*)c->d_vtab.p, c->vtab_stride, c->vtab_rows,
-                               (const int4*)c->prep.slots.p, (const int4*)c->prep.chunks.p, pl.sp,
-                               (const float*)c->prep.tp32.p, (const uint32_t*)c->prep.tpbf.p, g->n, pl.nx_eval,
-                               c->n_states, df, df2, part, st),
-                   "grid kernel launch");
-    if (rc) return rc;
-    if (pl.sp.n > 1 &&
-        (rc = hip_check(launch_reduce(part, pl.sp.n, g->n, pl.nx_eval, c->n_states, df, df2, st), "reduce launch")))
+    if ((rc = run_grid(c, g, precision, (const float2*)c->d_vtab.p, c->vtab_stride, c->vtab_rows, pl, part, df,
+                       df2, st)))
         return rc;
-    if (pl.nx_eval < g->n[0] &&
-        (rc = hip_check(launch_mirror(g->n, pl.nx_eval, c->n_states, df, df2, st), "mirror kernel launch")))
-        return rc;
-    if ((rc = record(c, EV_GRID1, st))) return rc;
-    c->ev_recorded = c->timing;
     if (!out_on_device) {
         if ((rc = copy_out(df, f, df2, f2, nout, st))) return rc;
         if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
@@ -645,6 +660,51 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
     } else if ((rc = order_mark(c, st))) {
         return rc;
     }
+    return ok();
+}
+
+int scff_eval_grid_noalloc(scff_ctx* c, const scff_grid* g, int precision, float* f, float* f2, void* hip_stream) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    int rc = validate_grid(g);
+    if (rc) return rc;
+    if ((rc = check_precision(precision))) return rc;
+    if (!c->have_mol) return fail(SCFF_ESTATE, "no molecule loaded");
+    if (!c->have_T) return fail(SCFF_ESTATE, "no transitions loaded");
+    if (!c->prepared)
+        return fail(SCFF_ESTATE, "the precompute of the loaded problem has not run (call scff_query or an "
+                                 "evaluation after the last load or option change)");
+    if (!c->scratch || !c->order_ev) return fail(SCFF_EDEVICE, "static scratch of the device is not available");
+    // 1D tables first, then (when they fit) the partial sums of a split
+    const int stride = vtable_stride(g->n);
+    const size_t vt = (size_t)c->pres.n_rows * stride * sizeof(float2);
+    const size_t vt_al = (vt + 255) & ~(size_t)255;
+    if (vt > kScratchBytes || vt > 0xffffffffull)
+        return fail(SCFF_EINVAL, "1D tables of this grid need " + std::to_string(vt) + " bytes; the static scratch "
+                                 "holds " + std::to_string(kScratchBytes) + " (use scff_eval_grid)");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    c->ev_prep = false;
+    if ((rc = order_after(c, st))) return rc;
+    unsigned char* base = (unsigned char*)c->scratch;
+    float2* V = (float2*)base;
+    double dq[3];
+    for (int a = 0; a < 3; ++a) dq[a] = g->n[a] > 1 ? (g->qmax[a] - g->qmin[a]) / (g->n[a] - 1) : 0.0;
+    if ((rc = record(c, EV_VT0, st))) return rc;
+    if ((rc = hip_check(launch_vtable((const VRowDev*)c->prep.rows.p, c->pres.n_rows, stride, g->n, g->qmin, dq, V,
+                                      st),
+                        "vtable kernel launch")))
+        return rc;
+    const size_t nout = (size_t)g->n[0] * g->n[1] * g->n[2] * (size_t)c->n_states;
+    EvalPlan pl = plan_eval(c, g);
+    double2* part = nullptr;
+    if (pl.sp.n > 1) {
+        if (vt_al + (size_t)pl.sp.n * nout * sizeof(double2) <= kScratchBytes)
+            part = (double2*)(base + vt_al);
+        else
+            pl = plan_eval(c, g, false);
+    }
+    if ((rc = run_grid(c, g, precision, V, stride, c->pres.n_rows, pl, part, (float2*)f, f2, st))) return rc;
+    if ((rc = order_mark(c, st))) return rc;
     return ok();
 }
 
