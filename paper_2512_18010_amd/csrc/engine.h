@@ -147,8 +147,8 @@ void set_error(const std::string& msg);
 // Pack and upload a context's problem for grid g on stream st and wait for
 // it: when this returns, the precompute is complete in device memory, so an
 // evaluation on any other stream may use it.  *bytes_needed receives the
-// device bytes an evaluation on g will hold in total.
-int ctx_prepare(scff_ctx* c, const scff_grid* g, hipStream_t st, size_t* bytes_needed);
+// device bytes an evaluation on g in `precision` will hold in total.
+int ctx_prepare(scff_ctx* c, const scff_grid* g, int precision, hipStream_t st, size_t* bytes_needed);
 // Device bytes a context holds (its buffers are kept between calls).
 size_t ctx_device_bytes(const scff_ctx* c);
 

@@ -210,19 +210,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         int t0 = threadIdx.x;
         asm volatile("" : "+v"(t0));
         const int p0 = t0 >> 4;
-        // row ids are clamped to the table, so no DMA can leave it whatever
-        // the slot table holds (the host validates the table on request)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            rid[j] = (int)min((unsigned)tc[4 * min(p0 + 16 * j, nptl - 1) + axis], (unsigned)(vrows - 1));
+        for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(p0 + 16 * j, nptl - 1) + axis];
     };
     // DMA of chunk c's raw slices into buffer rbase and its Tp block into tbase
     auto issue_dma = [&](int c, uint32_t rbase, uint32_t tbase) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             // wave w of term group j covers terms 16j + 4w .. 16j + 4w + 3
-            if (16 * j + 4 * wave < kNPT)
-                dma_b128(8u * (__umul24(rid[j], vstride) + qoff), V, rbase + (16 * j + 4 * wave) * kParts * 16);
+            // row ids are clamped to the table where they are used (after the
+            // barrier that waits for their loads), so no DMA can leave the
+            // table whatever the slot table holds
+            if (16 * j + 4 * wave < kNPT) {
+                const uint32_t r = min((uint32_t)rid[j], (uint32_t)(vrows - 1));
+                dma_b128(8u * (__umul24(r, vstride) + qoff), V, rbase + (16 * j + 4 * wave) * kParts * 16);
+            }
         }
         const int4 ch = chunks[c];
         const int tpf4 = ch.y * (kChunk * SW / 4);   // float4 of Tp in this chunk
@@ -263,21 +265,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         const int4 ch = chunks[c];
         const int nu = ch.y;
         const int npp = ch.z;
-        // W = Vx * Vy: item = (term, qx) -> 8 lines.  The thread index is
-        // re-read (not kept live across the loop) to spare a register.
+        // W = Vx * Vy: item = (term, qx, pair of q_y lines).  The 16 items of
+        // a term are 16 consecutive threads, so the LDS reads of a quarter
+        // wave touch one term row (no two terms' rows, 64 dwords apart, meet
+        // in a bank).  The thread index is re-read (not kept live across the
+        // loop) to spare a register.
         int i0 = threadIdx.x;
         asm volatile("" : "+v"(i0));
-        for (int i = i0; i < nu * kChunk * npp * 4; i += 256) {
-            const int ptl = i >> 2, xq = i & 3;
+        for (int i = i0; i < nu * kChunk * npp * 16; i += 256) {
+            const int ptl = i >> 4, xq = (i >> 2) & 3, h = i & 3;
             const float2 vx = reinterpret_cast<const float2*>(R + ptl * kParts)[xq];
-            const float4* yr = R + ptl * kParts + 2;
-            float4* wd = reinterpret_cast<float4*>(Wl + ptl * kWStride + xq * 8);
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const float4 y = yr[h];
-                wd[h] = make_float4(vx.x * y.x - vx.y * y.y, vx.x * y.y + vx.y * y.x,
-                                    vx.x * y.z - vx.y * y.w, vx.x * y.w + vx.y * y.z);
-            }
+            const float4 y = R[ptl * kParts + 2 + h];
+            reinterpret_cast<float4*>(Wl + ptl * kWStride + xq * 8)[h] =
+                make_float4(vx.x * y.x - vx.y * y.y, vx.x * y.y + vx.y * y.x, vx.x * y.z - vx.y * y.w,
+                            vx.x * y.w + vx.y * y.z);
         }
         barrier_lds();
         // G of one component pair (index p in the chunk) for this lane's 2
@@ -595,11 +596,13 @@ static hipError_t launch_grid_t(const float2* V, int vstride, int vrows, const i
     return hipGetLastError();
 }
 
-// q_z values per tile: 4 per lane (16) for <= 16 states, 2 per lane (8) above
-static int tile_qz(int state_blocks) { return state_blocks == 1 ? 16 : 8; }
+// q_z values per tile: 4 per lane (16) for <= 16 states and for the
+// split-BF16 contraction (no FP64 fold totals), 2 per lane (8) for the FP32
+// contraction of 17..32 states
+static int tile_qz(int state_blocks, int precision) { return state_blocks == 1 || precision == 1 ? 16 : 8; }
 
-long long grid_tiles(int state_blocks, const int n[3], int nx_eval) {
-    const int tz = tile_qz(state_blocks);
+long long grid_tiles(int state_blocks, int precision, const int n[3], int nx_eval) {
+    const int tz = tile_qz(state_blocks, precision);
     return (long long)((nx_eval + 3) / 4) * ((n[1] + 7) / 8) * ((n[2] + tz - 1) / tz);
 }
 
@@ -626,11 +629,12 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
 #define SCFF_GRID(SB_, QZL_, WPE_, BF_) \
     return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, vrows, terms, chunks, sp, BF_ ? tp_bf : tp32, n, nx_eval, \
                                                n_states, f, f2, part, st)
-    // <=16 states: 4 q_z per lane (8 q values); 17..32 states: 2 q_z per lane,
-    // so the accumulators of both precisions fit 2 waves per SIMD
+    // 4 q_z per lane (8 q values) except for the FP32 contraction of 17..32
+    // states (2 q_z per lane), whose accumulators and FP64 fold totals would
+    // not fit 2 waves per SIMD otherwise
     if (precision == 1) {
         if (state_blocks == 1) SCFF_GRID(1, 4, 2, true);
-        SCFF_GRID(2, 2, 2, true);
+        SCFF_GRID(2, 4, 2, true);
     }
     if (state_blocks == 1) SCFF_GRID(1, 4, 2, false);
     SCFF_GRID(2, 2, 2, false);

@@ -25,7 +25,7 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
 hipError_t launch_reduce(const double2* part, int n_split, const int n[3], int nx_eval, int n_states, float2* f,
                          float* f2, hipStream_t st);
 hipError_t launch_mirror(const int n[3], int nx_eval, int n_states, float2* f, float* f2, hipStream_t st);
-long long grid_tiles(int state_blocks, const int n[3], int nx_eval);
+long long grid_tiles(int state_blocks, int precision, const int n[3], int nx_eval);
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
                          const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
                          int n_states, float2* f, float* f2, hipStream_t st);
@@ -319,11 +319,11 @@ struct EvalPlan {
     ChunkSplit sp;
 };
 
-EvalPlan plan_eval(const scff_ctx* c, const scff_grid* g, bool allow_split = true) {
+EvalPlan plan_eval(const scff_ctx* c, const scff_grid* g, int precision, bool allow_split = true) {
     EvalPlan e{};
     e.nx_eval = (c->symmetry && grid_symmetric(g)) ? (g->n[0] + 1) / 2 : g->n[0];
     const int nch = c->pres.n_chunks;
-    const long long tiles = grid_tiles(c->pres.state_blocks, g->n, e.nx_eval);
+    const long long tiles = grid_tiles(c->pres.state_blocks, precision, g->n, e.nx_eval);
     const long long slots = 2LL * c->n_cu;
     const size_t part1 = (size_t)g->n[0] * g->n[1] * g->n[2] * (size_t)c->n_states * sizeof(double2);
     long long smax = std::min<long long>(kMaxSplit, nch);
@@ -410,7 +410,7 @@ int copy_out(const float2* df, float* f, const float* df2, float* f2, size_t nou
 
 // Precompute a context's problem and report the device bytes an evaluation
 // on g holds in total (precompute buffers, 1D tables, output staging).
-int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, hipStream_t st, size_t* bytes_needed) {
+int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, int precision, hipStream_t st, size_t* bytes_needed) {
     int rc = validate_grid(g);
     if (rc) return rc;
     if ((rc = set_device(c))) return rc;
@@ -427,7 +427,7 @@ int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, hipStream_t st, size_t* b
     // holds when those are large enough (a reused context)
     const size_t vt = (size_t)c->pres.n_rows * stride * sizeof(float2);
     const size_t of = npts * (size_t)c->n_states * sizeof(float2), of2 = npts * (size_t)c->n_states * sizeof(float);
-    const EvalPlan pl = plan_eval(c, g);
+    const EvalPlan pl = plan_eval(c, g, precision);
     const size_t op = pl.sp.n > 1 ? (size_t)pl.sp.n * npts * (size_t)c->n_states * sizeof(double2) : 0;
     const size_t held = c->d_vtab.bytes + c->d_f.bytes + c->d_f2.bytes + c->d_part.bytes;
     *bytes_needed = c->used - held + std::max(c->d_vtab.bytes, vt) + std::max(c->d_f.bytes, of) +
@@ -642,13 +642,13 @@ int scff_eval_grid(scff_ctx* c, const scff_grid* g, int precision, float* f, flo
     // the partial buffer is the last reservation: a split that the context's
     // HBM budget cannot hold falls back to the unsplit evaluation (the same
     // values up to the order of the FP64 sums)
-    EvalPlan pl = plan_eval(c, g);
+    EvalPlan pl = plan_eval(c, g, precision);
     double2* part = nullptr;
     if (pl.sp.n > 1) {
         if (dev_reserve(c, c->d_part, (size_t)pl.sp.n * nout * sizeof(double2)) == SCFF_OK)
             part = (double2*)c->d_part.p;
         else
-            pl = plan_eval(c, g, false);
+            pl = plan_eval(c, g, precision, false);
     }
     if ((rc = run_grid(c, g, precision, (const float2*)c->d_vtab.p, c->vtab_stride, c->vtab_rows, pl, part, df,
                        df2, st)))
@@ -695,13 +695,13 @@ int scff_eval_grid_noalloc(scff_ctx* c, const scff_grid* g, int precision, float
                         "vtable kernel launch")))
         return rc;
     const size_t nout = (size_t)g->n[0] * g->n[1] * g->n[2] * (size_t)c->n_states;
-    EvalPlan pl = plan_eval(c, g);
+    EvalPlan pl = plan_eval(c, g, precision);
     double2* part = nullptr;
     if (pl.sp.n > 1) {
         if (vt_al + (size_t)pl.sp.n * nout * sizeof(double2) <= kScratchBytes)
             part = (double2*)(base + vt_al);
         else
-            pl = plan_eval(c, g, false);
+            pl = plan_eval(c, g, precision, false);
     }
     if ((rc = run_grid(c, g, precision, V, stride, c->pres.n_rows, pl, part, (float2*)f, f2, st))) return rc;
     if ((rc = order_mark(c, st))) return rc;

@@ -317,7 +317,7 @@ void prep_loop(scff_server* s) {
             if (rc == SCFF_OK) loaded = r->mol;
             if (rc == SCFF_OK) rc = scff_load_transitions(c, r->n_states, r->T.data());
             if (rc == SCFF_OK) rc = scff_set_options(c, r->eps, r->spin);
-            if (rc == SCFF_OK) rc = scff::ctx_prepare(c, &r->grid, pst, &bytes);
+            if (rc == SCFF_OK) rc = scff::ctx_prepare(c, &r->grid, r->precision, pst, &bytes);
         } else if (rc == SCFF_OK) {
             // scheduler test mode: footprint of the outputs only
             bytes = (size_t)r->grid.n[0] * r->grid.n[1] * r->grid.n[2] * (size_t)r->n_states * 12;
