@@ -96,7 +96,10 @@ __global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int v
 
 // ---------------------------------------------------------------- grid kernel
 //
-// Workgroup = 4 waves, tile = 4 qx x 8 qy lines x TZ qz (TZ = 4*QZL).
+// Workgroup = NW waves (4 or 8), tile = 4 qx x 8 qy lines x TZ qz
+// (TZ = 4*QZL per q_x line of waves; 8 waves put two waves on each q_x line,
+// one per half of the q_z range, so the chunk staging serves twice the q
+// values).
 // The packed pairs come in units of 8 component pairs with npp terms each
 // (npp <= 9); a chunk is a run of 1..4 consecutive units with the same npp
 // and at most 72 terms (up to 32 pairs when npp <= 2).  Per chunk, for every
@@ -107,9 +110,10 @@ __global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int v
 // buffers are double-buffered: the DMA for chunk c+1 is issued at the start
 // of chunk c and completes under chunk c's W phase and main loop; the row
 // ids it needs were loaded one chunk earlier.  Thread tid always moves slice
-// `part = tid & 15` of terms ptl = tid/16 + 16j, so the LDS destination of a
-// wave's DMA is contiguous (lane * 16 bytes), as the instruction requires.
-// Lane (kk, ln): pair kk of the current MFMA k-step, 2 lines x QZL qz.
+// `part = tid & 15` of terms ptl = tid/16 + (NW*4)j, so the LDS destination
+// of a wave's DMA is contiguous (lane * 16 bytes), as the instruction
+// requires.  Lane (kk, ln): pair kk of the current MFMA k-step, 2 lines x QZL
+// qz.
 
 constexpr int kFoldUnits = 4;  // units (32 pairs) per FP64 fold of the FP32 MFMA sums
 constexpr int kWStride = 34;   // float2 per term row of W (32 lines + pad)
@@ -143,17 +147,21 @@ __device__ __forceinline__ void barrier_dma() {
     asm volatile("s_barrier" ::: "memory");
 }
 
-template <int SB, int QZL, int WPE, bool BF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
+template <int SB, int QZL, int WPE, bool BF, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
     const float2* __restrict__ V, int vstride, int vrows, const int4* __restrict__ terms,
     const int4* __restrict__ chunks, ChunkSplit sp, const uint32_t* __restrict__ Tp, int3 n, int3 ntiles,
     int nx_eval, int n_states, float2* __restrict__ f, float* __restrict__ f2, double2* __restrict__ partial,
     long long part_stride) {
-    constexpr int TZ = 4 * QZL;
+    constexpr int NT = NW * 64;        // threads
+    constexpr int ZH = NW / 4;         // waves per q_x line of the tile (q_z halves)
+    constexpr int TZ = 4 * QZL * ZH;   // q_z values of the tile
     constexpr int ZPARTS = TZ / 2;     // float4 slices of a Z row
     constexpr int SLOTS = 2 * QZL;     // q values per lane
     constexpr int SW = 16 * SB;        // padded state count
-    constexpr int NJ = (kNPT + 15) / 16;       // term groups per slice-thread (5)
+    constexpr int TPP = NT / 16;       // terms per DMA pass (16 slice-threads per term)
+    constexpr int NJ = (kNPT + TPP - 1) / TPP;   // term groups per slice-thread
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves per workgroup");
     constexpr int TPW = kMaxUnitsPerChunk * kChunk * SW;   // Tp words per chunk at most
     static_assert(2 + 4 + ZPARTS <= kParts, "slices per term");
     static_assert(QZL % 2 == 0, "q_z values per lane come in float4 pairs");
@@ -172,6 +180,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wxq = wave & 3;          // q_x line of the tile
+    const int wzh = wave >> 2;         // q_z half of the tile (8 waves)
     const int lane = tid & 63;
     const int kk = lane >> 4;          // pair within an MFMA k-step
     const int ln = lane & 15;          // MFMA column (q) / A-row (state) index
@@ -211,19 +221,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         asm volatile("" : "+v"(t0));
         const int p0 = t0 >> 4;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(p0 + 16 * j, nptl - 1) + axis];
+        for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(p0 + TPP * j, nptl - 1) + axis];
     };
     // DMA of chunk c's raw slices into buffer rbase and its Tp block into tbase
     auto issue_dma = [&](int c, uint32_t rbase, uint32_t tbase) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            // wave w of term group j covers terms 16j + 4w .. 16j + 4w + 3
+            // wave w of term group j covers terms TPP*j + 4w .. TPP*j + 4w + 3
             // row ids are clamped to the table where they are used (after the
             // barrier that waits for their loads), so no DMA can leave the
             // table whatever the slot table holds
-            if (16 * j + 4 * wave < kNPT) {
+            if (TPP * j + 4 * wave < kNPT) {
                 const uint32_t r = min((uint32_t)rid[j], (uint32_t)(vrows - 1));
-                dma_b128(8u * (__umul24(r, vstride) + qoff), V, rbase + (16 * j + 4 * wave) * kParts * 16);
+                dma_b128(8u * (__umul24(r, vstride) + qoff), V, rbase + (TPP * j + 4 * wave) * kParts * 16);
             }
         }
         const int4 ch = chunks[c];
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         // loop) to spare a register.
         int i0 = threadIdx.x;
         asm volatile("" : "+v"(i0));
-        for (int i = i0; i < nu * kChunk * npp * 16; i += 256) {
+        for (int i = i0; i < nu * kChunk * npp * 16; i += NT) {
             const int ptl = i >> 4, xq = (i >> 2) & 3, h = i & 3;
             const float2 vx = reinterpret_cast<const float2*>(R + ptl * kParts)[xq];
             const float4 y = R[ptl * kParts + 2 + h];
@@ -290,8 +300,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             // multiply-adds whose unused high half may name a register with a
             // load still in flight (which would make it wait for that load)
             const int pt = __umul24(p, npp);
-            const float2* wp = Wl + (__umul24(pt, kWStride) + wave * 8 + 2 * lpair);
-            const float2* zp = reinterpret_cast<const float2*>(R) + (__umul24(pt, 2 * kParts) + 12 + zgrp * QZL);
+            const float2* wp = Wl + (__umul24(pt, kWStride) + wxq * 8 + 2 * lpair);
+            const float2* zp = reinterpret_cast<const float2*>(R) +
+                               (__umul24(pt, 2 * kParts) + 12 + wzh * (4 * QZL) + zgrp * QZL);
             auto load = [&](int t, float4& w, float4 (&zz)[QZL / 2]) {
                 w = *reinterpret_cast<const float4*>(wp + t * kWStride);
 #pragma unroll
@@ -424,31 +435,64 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         if (units_done & (kFoldUnits - 1)) fold();
     }
 
-    // epilogue: lane holds states sb*16 + 4*kk + i for the q values of column ln
-    const int qx = qx0 + wave;
+    // Epilogue, coalesced through LDS.  Lane (kk, ln) holds states
+    // sb*16 + 4kk + i of its q values (lines 2*lpair + a, q_z zgrp*QZL + j).
+    // One pass per (sb, i, a): every lane writes its QZL values to the wave's
+    // own LDS region as 16 rows (kk, lpair) of 4*QZL q_z, then the wave reads
+    // the rows back with consecutive lanes on consecutive q_z and stores them,
+    // so every row of the output (fixed state, q_x, q_y) is written as one
+    // contiguous run.  The staging reuses the raw slice buffers (no wave reads
+    // them after the barrier below).
+    constexpr int RQ = 4 * QZL;          // q_z values of a row
+    constexpr int RPI = 64 / RQ;         // rows per wave-wide read
+    barrier_lds();
+    const int qx = qx0 + wxq;
+    const bool plane_ok = qx < nx_eval;
+    // per wave: 16 rows x RQ values; f (float2) or partial (double2) in R0, f2 (float) in R1
+    double2* sp2 = reinterpret_cast<double2*>(R0) + wave * 16 * RQ;
+    float2* sf = reinterpret_cast<float2*>(R0) + wave * 16 * RQ;
+    float* sf2 = reinterpret_cast<float*>(R1) + wave * 16 * RQ;
+    const int wrow = kk * 4 + lpair;     // the row this lane's values belong to
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            const int a = s / QZL, j = s % QZL;
-            const int qy = qy0 + 2 * lpair + a;
-            const int qz = qz0 + zgrp * QZL + j;
-            if (qx >= nx_eval || qy >= n.y || qz >= n.z) continue;
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int st = sb * 16 + 4 * kk + i;
-                if (st >= n_states) continue;
-                const double vr = BF ? (double)acc_r[sb][s][i] : tot_r[sb][s][i];
-                const double vi = BF ? (double)acc_i[sb][s][i] : tot_i[sb][s][i];
-                const size_t o = (((size_t)st * n.x + qx) * n.y + qy) * n.z + qz;
-                if (partial) {   // split pair sum: FP64 partial, summed by reduce_kernel
-                    partial[(size_t)split * part_stride + o] = make_double2(vr, vi);
-                } else {
-                    if (f) f[o] = make_float2((float)vr, (float)vi);
-                    if (f2) f2[o] = (float)(vr * vr + vi * vi);
+            for (int a = 0; a < 2; ++a) {
+#pragma unroll
+                for (int j = 0; j < QZL; ++j) {
+                    const int sl = a * QZL + j;
+                    const double vr = BF ? (double)acc_r[sb][sl][i] : tot_r[sb][sl][i];
+                    const double vi = BF ? (double)acc_i[sb][sl][i] : tot_i[sb][sl][i];
+                    const int e = wrow * RQ + zgrp * QZL + j;
+                    if (partial) {
+                        sp2[e] = make_double2(vr, vi);
+                    } else {
+                        sf[e] = make_float2((float)vr, (float)vi);
+                        sf2[e] = (float)(vr * vr + vi * vi);
+                    }
                 }
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // this wave's rows are in LDS
+#pragma unroll
+                for (int r0 = 0; r0 < 16; r0 += RPI) {
+                    const int row = r0 + lane / RQ, col = lane % RQ;
+                    const int rk = row >> 2, rl = row & 3;
+                    const int st = sb * 16 + 4 * rk + i;
+                    const int qy = qy0 + 2 * rl + a;
+                    const int qz = qz0 + wzh * RQ + col;
+                    const int e = row * RQ + col;
+                    if (plane_ok && st < n_states && qy < n.y && qz < n.z) {
+                        const size_t o = (((size_t)st * n.x + qx) * n.y + qy) * n.z + qz;
+                        if (partial) {   // split pair sum: FP64 partial, summed by reduce_kernel
+                            partial[(size_t)split * part_stride + o] = sp2[e];
+                        } else {
+                            if (f) f[o] = sf[e];
+                            if (f2) f2[o] = sf2[e];
+                        }
+                    }
+                }
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // read before the next pass writes
             }
-        }
 }
 
 // ---------------------------------------------------------------- split reduction
@@ -582,24 +626,28 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
     return hipGetLastError();
 }
 
-template <int SB, int QZL, int WPE, bool BF>
+template <int SB, int QZL, int WPE, bool BF, int NW>
 static hipError_t launch_grid_t(const float2* V, int vstride, int vrows, const int4* terms, const int4* chunks,
                                 const ChunkSplit& sp, const uint32_t* Tp, const int n[3], int nx_eval,
                                 int n_states, float2* f, float* f2, double2* part, hipStream_t st) {
     const int3 nn = make_int3(n[0], n[1], n[2]);
-    const int3 nt = make_int3((nx_eval + 3) / 4, (n[1] + 7) / 8, (n[2] + 4 * QZL - 1) / (4 * QZL));
+    constexpr int TZ = 4 * QZL * (NW / 4);
+    const int3 nt = make_int3((nx_eval + 3) / 4, (n[1] + 7) / 8, (n[2] + TZ - 1) / TZ);
     const long long blocks = (long long)nt.x * nt.y * nt.z * sp.n;
     const long long stride = (long long)n_states * n[0] * n[1] * n[2];
-    hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE, BF>), dim3((unsigned)blocks), dim3(256), 0, st, V, vstride,
+    hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE, BF, NW>), dim3((unsigned)blocks), dim3(NW * 64), 0, st, V, vstride,
                        vrows, terms, chunks, sp, Tp, nn, nt, nx_eval, n_states, f, f2, sp.n > 1 ? part : nullptr,
                        stride);
     return hipGetLastError();
 }
 
-// q_z values per tile: 4 per lane (16) for <= 16 states and for the
-// split-BF16 contraction (no FP64 fold totals), 2 per lane (8) for the FP32
-// contraction of 17..32 states
-static int tile_qz(int state_blocks, int precision) { return state_blocks == 1 || precision == 1 ? 16 : 8; }
+// Every variant's tile covers 16 q_z values: 4 per lane on one wave per q_x
+// line, except the FP32 contraction of 17..32 states, whose accumulators and
+// FP64 fold totals leave room for 2 q_z per lane only: it runs 8 waves per
+// workgroup (two per q_x line).  Workgroups resident per CU: two of 4 waves,
+// or one of 8 (2 waves per SIMD either way).
+static int tile_qz(int, int) { return 16; }
+int grid_wg_per_cu(int state_blocks, int precision) { return state_blocks == 2 && precision == 0 ? 1 : 2; }
 
 long long grid_tiles(int state_blocks, int precision, const int n[3], int nx_eval) {
     const int tz = tile_qz(state_blocks, precision);
@@ -626,18 +674,18 @@ hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vst
         if (sp.lo[j + 1] < sp.lo[j]) return hipErrorInvalidValue;
     if (sp.n > 1 && !part) return hipErrorInvalidValue;
     const uint32_t* tp32 = reinterpret_cast<const uint32_t*>(Tp);
-#define SCFF_GRID(SB_, QZL_, WPE_, BF_) \
-    return launch_grid_t<SB_, QZL_, WPE_, BF_>(V, vstride, vrows, terms, chunks, sp, BF_ ? tp_bf : tp32, n, nx_eval, \
+#define SCFF_GRID(SB_, QZL_, WPE_, BF_, NW_) \
+    return launch_grid_t<SB_, QZL_, WPE_, BF_, NW_>(V, vstride, vrows, terms, chunks, sp, BF_ ? tp_bf : tp32, n, nx_eval, \
                                                n_states, f, f2, part, st)
     // 4 q_z per lane (8 q values) except for the FP32 contraction of 17..32
-    // states (2 q_z per lane), whose accumulators and FP64 fold totals would
-    // not fit 2 waves per SIMD otherwise
+    // states (2 q_z per lane, 8 waves per tile), whose accumulators and FP64
+    // fold totals would not fit 2 waves per SIMD otherwise
     if (precision == 1) {
-        if (state_blocks == 1) SCFF_GRID(1, 4, 2, true);
-        SCFF_GRID(2, 4, 2, true);
+        if (state_blocks == 1) SCFF_GRID(1, 4, 2, true, 4);
+        SCFF_GRID(2, 4, 2, true, 4);
     }
-    if (state_blocks == 1) SCFF_GRID(1, 4, 2, false);
-    SCFF_GRID(2, 2, 2, false);
+    if (state_blocks == 1) SCFF_GRID(1, 4, 2, false, 4);
+    SCFF_GRID(2, 2, 2, false, 8);
 #undef SCFF_GRID
 }
 

@@ -26,6 +26,7 @@ hipError_t launch_reduce(const double2* part, int n_split, const int n[3], int n
                          float* f2, hipStream_t st);
 hipError_t launch_mirror(const int n[3], int nx_eval, int n_states, float2* f, float* f2, hipStream_t st);
 long long grid_tiles(int state_blocks, int precision, const int n[3], int nx_eval);
+int grid_wg_per_cu(int state_blocks, int precision);
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
                          const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
                          int n_states, float2* f, float* f2, hipStream_t st);
@@ -302,7 +303,7 @@ bool grid_symmetric(const scff_grid* g) {
 // How scff_eval_grid evaluates grid g: the planes it computes (ix < nx_eval;
 // the rest are mirrored in the symmetric mode) and the split of the chunk
 // list.  Every tile costs the same (it runs the whole chunk list), and the
-// device holds two workgroups per CU at once (the grid kernel's occupancy),
+// device holds two workgroups of 4 waves (or one of 8) per CU at once (the grid kernel's occupancy),
 // so a launch of `tiles` workgroups takes ceil(tiles / slots) rounds: 64 or
 // 1728 tiles on 512 slots leave most of one round idle.  Cutting the chunk
 // list into S ranges of about equal work (a chunk costs units * (npp + 2):
@@ -324,7 +325,7 @@ EvalPlan plan_eval(const scff_ctx* c, const scff_grid* g, int precision, bool al
     e.nx_eval = (c->symmetry && grid_symmetric(g)) ? (g->n[0] + 1) / 2 : g->n[0];
     const int nch = c->pres.n_chunks;
     const long long tiles = grid_tiles(c->pres.state_blocks, precision, g->n, e.nx_eval);
-    const long long slots = 2LL * c->n_cu;
+    const long long slots = (long long)grid_wg_per_cu(c->pres.state_blocks, precision) * c->n_cu;
     const size_t part1 = (size_t)g->n[0] * g->n[1] * g->n[2] * (size_t)c->n_states * sizeof(double2);
     long long smax = std::min<long long>(kMaxSplit, nch);
     smax = std::min<long long>(smax, part1 ? (long long)(kMaxPartBytes / part1) : kMaxSplit);
