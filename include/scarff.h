@@ -257,6 +257,52 @@ int scff_query(scff_ctx* ctx, scff_info* info);
 int scff_export_vtensors(scff_ctx* ctx, const scff_grid* grid, long long* n_terms_out, float* vx,
                          float* vy, float* vz, float* tp);
 
+/*
+ * Separable integral (paper Sec. 5.3: integrals of the form
+ * I = int d^3q f(q_x) g(q_y) h(q_z) f_S(q), evaluated from the 1D V-tensors
+ * with a cost linear in the axis sizes instead of their product):
+ *     out_s = sum_{ix,iy,iz} wx[ix] wy[iy] wz[iz] f_s(q_ix, q_iy, q_iz)
+ *           = sum_t Tp_s(t) (sum_ix wx[ix] V^x_t(q_ix)) (sum_iy ...) (sum_iz ...)
+ * on the grid's axes (q_a = linspace(qmin[a], qmax[a], n[a])).  The caller
+ * folds its functions and quadrature weights into the weights (e.g. f(q_x)
+ * times a trapezoid weight).
+ *   wx, wy, wz   complex128 interleaved [n[a]][2], host arrays
+ *   out          complex128 [n_states][2], host array
+ * Everything runs in FP64 on the device (rows, products, FP64 transition
+ * weights), with the context's screening and spin factor; the call returns
+ * when out is written.  SCFF_EINVAL for NULL or non-finite arguments,
+ * SCFF_ESTATE before a molecule and transitions are loaded.
+ */
+int scff_eval_separable(scff_ctx* ctx, const scff_grid* grid, const double* wx, const double* wy,
+                        const double* wz, double* out);
+
+/*
+ * Low-momentum limit (paper Sec. 6, oscillator-strength reconstruction):
+ * f_s(q) = f_s(0) + i q . mu_s + O(q^2) with the transition dipole
+ * mu_s = grad_q Im f_s at q = 0 (= s_f sum T_{mu nu} <phi_mu| r |phi_nu>).
+ * mu_s is evaluated exactly from the 1D V-tensor rows' values and first
+ * derivatives at q = 0, in FP64.  With the transition energies dE (a.u.),
+ * f0_s = (2/3) dE_s |mu_s|^2 (atomic units, m_e = 1).
+ *   dE   [n_states] host, or NULL (then f0 must be NULL)
+ *   mu   [n_states][3] host, required
+ *   f0   [n_states] host, or NULL
+ */
+int scff_dipole(scff_ctx* ctx, const double* dE, double* mu, double* f0);
+
+/*
+ * The paper's fit form of the same limit (Sec. 6): the angular average
+ * <|f_s(q)|^2>_Omega on 8 shells |q| = q_fit k / 8 (k = 1..8), each averaged
+ * with the product rule of 6 Gauss-Legendre nodes in cos(theta) and 12
+ * equally spaced azimuths (exact for polynomials of degree < 12 on the
+ * sphere), |f|^2 evaluated on the device in FP64; then the least-squares fit
+ * <|f|^2> = A + B q^2 + C q^4, whose B = |mu|^2 / 3 when f(0) = 0, and
+ * f0_fit_s = 2 dE_s B_s.
+ *   q_fit   fit range in a.u. (> 0; the paper uses about 0.05-0.25 keV)
+ *   coef    [n_states][3] = (A, B, C), host, required
+ *   f0_fit  [n_states] host, or NULL (needs dE)
+ */
+int scff_dipole_fit(scff_ctx* ctx, double q_fit, const double* dE, double* coef, double* f0_fit);
+
 /* ---- serving: continuous batching of independent requests -------------- */
 typedef struct scff_server scff_server;
 

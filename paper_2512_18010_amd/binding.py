@@ -104,6 +104,10 @@ scff_last_timing = _fn("scff_last_timing", c_int, [c_void_p, P(c_float), P(c_flo
 scff_export_vtensors = _fn("scff_export_vtensors", c_int,
                            [c_void_p, P(scff_grid), P(c_longlong), c_void_p, c_void_p, c_void_p,
                             c_void_p])
+scff_eval_separable = _fn("scff_eval_separable", c_int,
+                          [c_void_p, P(scff_grid), P(c_double), P(c_double), P(c_double), P(c_double)])
+scff_dipole = _fn("scff_dipole", c_int, [c_void_p, P(c_double), P(c_double), P(c_double)])
+scff_dipole_fit = _fn("scff_dipole_fit", c_int, [c_void_p, c_double, P(c_double), P(c_double), P(c_double)])
 scff_server_create = _fn("scff_server_create", c_int, [c_int, c_size_t, c_int, P(c_void_p)])
 scff_server_submit = _fn("scff_server_submit", c_int, [c_void_p, P(scff_request), P(c_ulonglong)])
 scff_server_wait = _fn("scff_server_wait", c_int,
@@ -303,6 +307,49 @@ class Context:
         check(scff_eval_points(self._h, nq, _d(q), PRECISIONS[precision], f.ctypes.data,
                                f2.ctypes.data, 0, None))
         return f.view(np.complex64)[..., 0], f2
+
+    def eval_separable(self, grid, wx, wy, wz):
+        """sum over the grid of wx[ix] wy[iy] wz[iz] f_s(q) per transition (complex128 [n_states])."""
+        ws = []
+        for a, w in enumerate((wx, wy, wz)):
+            w = np.ascontiguousarray(np.asarray(w, np.complex128).reshape(-1))
+            if w.shape[0] != int(grid.n[a]):
+                raise ValueError(f"weights of axis {a} must have {grid.n[a]} values, got {w.shape[0]}")
+            ws.append(w)
+        out = np.empty(self.n_states, np.complex128)
+        g = make_grid(grid.n, grid.qmin, grid.qmax)
+        check(scff_eval_separable(self._h, ctypes.byref(g), *[w.view(np.float64).ctypes.data_as(P(c_double))
+                                                              for w in ws],
+                                  out.view(np.float64).ctypes.data_as(P(c_double))))
+        return out
+
+    def dipole(self, dE=None):
+        """(mu [n_states, 3], f0 [n_states] or None): transition dipoles and oscillator strengths."""
+        mu = np.empty((self.n_states, 3), np.float64)
+        f0 = None
+        dEa = None
+        if dE is not None:
+            dEa = np.ascontiguousarray(np.asarray(dE, np.float64).reshape(-1))
+            if dEa.shape[0] != self.n_states:
+                raise ValueError(f"dE must hold {self.n_states} values")
+            f0 = np.empty(self.n_states, np.float64)
+        check(scff_dipole(self._h, _d(dEa) if dEa is not None else None, _d(mu),
+                          _d(f0) if f0 is not None else None))
+        return mu, f0
+
+    def dipole_fit(self, q_fit, dE=None):
+        """(coef [n_states, 3] = A, B, C of <|f|^2> = A + B q^2 + C q^4, f0_fit or None)."""
+        coef = np.empty((self.n_states, 3), np.float64)
+        f0 = None
+        dEa = None
+        if dE is not None:
+            dEa = np.ascontiguousarray(np.asarray(dE, np.float64).reshape(-1))
+            if dEa.shape[0] != self.n_states:
+                raise ValueError(f"dE must hold {self.n_states} values")
+            f0 = np.empty(self.n_states, np.float64)
+        check(scff_dipole_fit(self._h, float(q_fit), _d(dEa) if dEa is not None else None, _d(coef),
+                              _d(f0) if f0 is not None else None))
+        return coef, f0
 
     def export_vtensors(self, grid):
         g = make_grid(grid.n, grid.qmin, grid.qmax)

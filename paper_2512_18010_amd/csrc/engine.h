@@ -110,7 +110,8 @@ struct PrepInputs {
 struct PrepWork {
     DeviceBuffer rows_all, rowsum, trow, tbound, wt, cpmn, tp64, bsum, part, small, nk, nv, vbase,
         tmp, key, val, vinfo, tmp2, cnpp, csize, coff, tmp3, slots, tp32, tpbf, row_used, newid, tmp4,
-        rows, uhist, chunks;
+        rows, uhist, chunks,
+        vcp;   // per packed pair: its component pair (index of tp64), -1 for padding
     std::vector<int> chunk_host;   // staging of the chunk table (kept until the next prep)
     // pinned host memory of the context (kPinnedBytes, or NULL if it could
     // not be allocated): small readbacks and the chunk table travel through

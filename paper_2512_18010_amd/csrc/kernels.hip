@@ -33,6 +33,7 @@
 #include <type_traits>
 
 #include "engine.h"
+#include "vrow.h"
 
 namespace scff {
 
@@ -61,17 +62,8 @@ constexpr int kPointFoldUnits = 4;   // points kernel: units (32 pairs) per FP32
 // ---------------------------------------------------------------- 1D tables
 
 __device__ __forceinline__ float2 eval_row(const VRowDev& r, double q) {
-    // phase = q * P, reduced to revolutions in [-1/2, 1/2]
-    const double rev = q * r.P * 0.15915494309189535;  // 1/(2 pi)
-    const double red = rev - rint(rev);
-    double s, c;
-    sincospi(2.0 * red, &s, &c);
-    const double q2 = q * q;
-    const double g = exp(-q2 * r.inv4p);
-    // sum_u e_u (i q)^u = (e0 - e2 q^2 + e4 q^4) + i q (e1 - e3 q^2)
-    const double pr = fma(fma(r.e[4], q2, -r.e[2]), q2, r.e[0]);
-    const double pi = q * fma(-r.e[3], q2, r.e[1]);
-    return make_float2((float)(g * (c * pr - s * pi)), (float)(g * (c * pi + s * pr)));
+    const double2 v = eval_row_fp64(r, q);
+    return make_float2((float)v.x, (float)v.y);
 }
 
 __global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int vstride,

@@ -343,7 +343,7 @@ __global__ void layout_kernel(const int* __restrict__ order, const int4* __restr
                               const int4* __restrict__ trow, const double* __restrict__ w,
                               const double* __restrict__ thr, const double* __restrict__ tp64, int ns,
                               int SW, int4* __restrict__ slots, float* __restrict__ tp32,
-                              uint32_t* __restrict__ tpbf, int* __restrict__ row_used) {
+                              uint32_t* __restrict__ tpbf, int* __restrict__ row_used, int* __restrict__ vcp) {
     for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < n_vpairs; o += gridDim.x * blockDim.x) {
         const int c = o / kChunk, j = o - c * kChunk;
         const int npp = cnpp[c];
@@ -367,6 +367,7 @@ __global__ void layout_kernel(const int* __restrict__ order, const int4* __restr
             }
         }
         for (int q = len; q < npp; ++q) dst[q] = make_int4(-1, -1, -1, 0);
+        vcp[o] = k;   // component pair of this packed pair (-1: padding), for the FP64 weights
         for (int st = 0; st < SW; ++st) {
             const float v = (k >= 0 && st < ns) ? (float)tp64[(size_t)k * ns + st] : 0.0f;
             tp32[(size_t)o * SW + st] = v;
@@ -571,6 +572,7 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
     CK(alloc(w.slots, (size_t)nslots * sizeof(int4)));
     CK(alloc(w.tp32, (size_t)n_vpairs * SW * sizeof(float)));
     CK(alloc(w.tpbf, (size_t)n_vpairs * SW * sizeof(uint32_t)));
+    CK(alloc(w.vcp, (size_t)n_vpairs * sizeof(int)));
     CK(alloc(w.row_used, (size_t)NR * sizeof(int)));
     CK(alloc(w.newid, (size_t)NR * sizeof(int)));
     CK(hipMemsetAsync(w.row_used.p, 0, (size_t)NR * sizeof(int), st));
@@ -578,7 +580,7 @@ hipError_t run_prep(const PrepInputs& in, PrepWork& w, PrepResult& res, hipStrea
                        (const int4*)w.vinfo.p, NV, n_vpairs, (const int*)w.cnpp.p, (const int*)w.coff.p,
                        in.cp_first, in.cp_nterms, (const int4*)w.trow.p, (const double*)w.wt.p,
                        (const double*)thr, (const double*)w.tp64.p, ns, SW, (int4*)w.slots.p,
-                       (float*)w.tp32.p, (uint32_t*)w.tpbf.p, (int*)w.row_used.p);
+                       (float*)w.tp32.p, (uint32_t*)w.tpbf.p, (int*)w.row_used.p, (int*)w.vcp.p);
     CK(hipGetLastError());
     size_t tmp4 = 0;
     CK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp4, (int*)w.row_used.p, (int*)w.newid.p, (int)NR, st));

@@ -30,6 +30,16 @@ int grid_wg_per_cu(int state_blocks, int precision);
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
                          const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
                          int n_states, float2* f, float* f2, hipStream_t st);
+hipError_t launch_separable(const VRowDev* rows, int nrows, const int4* slots, const int* coff, const int* cnpp,
+                            int n_units, const double* tp64, const int* vcp, int ns, const double2* w, const int n[3],
+                            const double qmin[3], const double dq[3], double2* S, double2* G, double2* out,
+                            hipStream_t st);
+hipError_t launch_dipole(const VRowDev* rows, int nrows, const int4* slots, const int* coff, const int* cnpp,
+                         int n_units, const double* tp64, const int* vcp, int ns, double2* S, double2* G,
+                         double2* out, hipStream_t st);
+hipError_t launch_points64(const VRowDev* rows, const int4* slots, const int* coff, const int* cnpp, int n_units,
+                           const double* tp64, const int* vcp, int ns, const double* q, int nq, double* f2,
+                           hipStream_t st);
 }  // namespace scff
 
 using namespace scff;
@@ -83,6 +93,9 @@ struct scff_ctx {
     bool validate = false;
     int n_cu = 256;     // compute units of the device
     DeviceBuffer d_part;   // FP64 partial results of a split chunk list
+    // FP64 low-momentum and separable work: weights / points, per-row and
+    // per-pair values, per-state results
+    DeviceBuffer d_lq_in, d_lq_S, d_lq_G, d_lq_out;
     void* scratch = nullptr;   // this device's static scratch array (scff_eval_grid_noalloc)
 };
 
@@ -387,14 +400,14 @@ int check_precision(int precision) {
 }
 
 void free_all(scff_ctx* c) {
-    for (DeviceBuffer* b : {&c->d_mol, &c->d_T, &c->d_vtab, &c->d_part,
-                            &c->d_f, &c->d_f2, &c->d_q})
+    for (DeviceBuffer* b : {&c->d_mol, &c->d_T, &c->d_vtab, &c->d_part, &c->d_f, &c->d_f2, &c->d_q,
+                            &c->d_lq_in, &c->d_lq_S, &c->d_lq_G, &c->d_lq_out})
         dev_free(c, *b);
     PrepWork& w = c->prep;
     for (DeviceBuffer* b : {&w.rows_all, &w.rowsum, &w.trow, &w.tbound, &w.wt, &w.cpmn, &w.tp64, &w.bsum,
                             &w.part, &w.small, &w.nk, &w.nv, &w.vbase, &w.tmp, &w.key, &w.val, &w.vinfo,
                             &w.tmp2, &w.cnpp, &w.csize, &w.coff, &w.tmp3, &w.slots, &w.tp32, &w.tpbf,
-                            &w.row_used, &w.newid, &w.tmp4, &w.rows})
+                            &w.row_used, &w.newid, &w.tmp4, &w.rows, &w.uhist, &w.chunks, &w.vcp})
         dev_free(c, *b);
 }
 
@@ -844,6 +857,221 @@ int scff_export_vtensors(scff_ctx* c, const scff_grid* g, long long* n_terms_out
                         tp[(size_t)s * p.terms_kept + t] = tp32[(size_t)(ch * kChunk + j) * SW + s];
                 ++t;
             }
+    }
+    return ok();
+}
+
+namespace {
+
+// Precompute on the default stream and wait (host-result calls).
+int prepare_sync(scff_ctx* c) {
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    if ((rc = order_after(c, nullptr))) return rc;
+    return ensure_prepared(c, nullptr);
+}
+
+int finish_sync(scff_ctx* c) {
+    int rc = hip_check(hipStreamSynchronize(nullptr), "stream sync");
+    if (rc == SCFF_OK) order_done(c);
+    return rc;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on the
+// three-term recurrence of the Legendre polynomials).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-15) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+int scff_eval_separable(scff_ctx* c, const scff_grid* g, const double* wx, const double* wy, const double* wz,
+                        double* out) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    int rc = validate_grid(g);
+    if (rc) return rc;
+    if (!wx || !wy || !wz || !out) return fail(SCFF_EINVAL, "weights and output must not be NULL");
+    const double* ws[3] = {wx, wy, wz};
+    for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < 2 * g->n[a]; ++i)
+            if (!std::isfinite(ws[a][i])) return fail(SCFF_EINVAL, "non-finite weight");
+    if ((rc = prepare_sync(c))) return rc;
+    const PrepResult& p = c->pres;
+    const size_t nw = (size_t)g->n[0] + g->n[1] + g->n[2];
+    const size_t nv = (size_t)p.n_units * kChunk;
+    if ((rc = dev_reserve(c, c->d_lq_in, nw * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_lq_S, (size_t)p.n_rows * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_lq_G, nv * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_lq_out, (size_t)c->n_states * sizeof(double2))))
+        return rc;
+    size_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+        if ((rc = hip_check(hipMemcpyAsync((double2*)c->d_lq_in.p + off, ws[a], g->n[a] * sizeof(double2),
+                                           hipMemcpyHostToDevice, nullptr),
+                            "upload weights")))
+            return rc;
+        off += g->n[a];
+    }
+    double dq[3];
+    for (int a = 0; a < 3; ++a) dq[a] = g->n[a] > 1 ? (g->qmax[a] - g->qmin[a]) / (g->n[a] - 1) : 0.0;
+    if ((rc = hip_check(launch_separable((const VRowDev*)c->prep.rows.p, p.n_rows, (const int4*)c->prep.slots.p,
+                                         (const int*)c->prep.coff.p, (const int*)c->prep.cnpp.p, p.n_units,
+                                         (const double*)c->prep.tp64.p, (const int*)c->prep.vcp.p, c->n_states,
+                                         (const double2*)c->d_lq_in.p, g->n, g->qmin, dq, (double2*)c->d_lq_S.p,
+                                         (double2*)c->d_lq_G.p, (double2*)c->d_lq_out.p, nullptr),
+                        "separable kernels")))
+        return rc;
+    if ((rc = hip_check(hipMemcpyAsync(out, c->d_lq_out.p, (size_t)c->n_states * sizeof(double2),
+                                       hipMemcpyDeviceToHost, nullptr),
+                        "D2H separable")))
+        return rc;
+    if ((rc = finish_sync(c))) return rc;
+    return ok();
+}
+
+int scff_dipole(scff_ctx* c, const double* dE, double* mu, double* f0) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (!mu) return fail(SCFF_EINVAL, "mu must not be NULL");
+    if (f0 && !dE) return fail(SCFF_EINVAL, "oscillator strengths need the transition energies dE");
+    int rc;
+    if ((rc = prepare_sync(c))) return rc;
+    const PrepResult& p = c->pres;
+    const int ns = c->n_states;
+    if (dE)
+        for (int s = 0; s < ns; ++s)
+            if (!std::isfinite(dE[s])) return fail(SCFF_EINVAL, "non-finite transition energy");
+    const size_t nv = (size_t)p.n_units * kChunk;
+    if ((rc = dev_reserve(c, c->d_lq_S, (size_t)p.n_rows * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_lq_G, 4 * nv * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_lq_out, (size_t)ns * 4 * sizeof(double2))))
+        return rc;
+    if ((rc = hip_check(launch_dipole((const VRowDev*)c->prep.rows.p, p.n_rows, (const int4*)c->prep.slots.p,
+                                      (const int*)c->prep.coff.p, (const int*)c->prep.cnpp.p, p.n_units,
+                                      (const double*)c->prep.tp64.p, (const int*)c->prep.vcp.p, ns,
+                                      (double2*)c->d_lq_S.p, (double2*)c->d_lq_G.p, (double2*)c->d_lq_out.p,
+                                      nullptr),
+                        "dipole kernels")))
+        return rc;
+    std::vector<double2> r((size_t)ns * 4);
+    if ((rc = hip_check(hipMemcpyAsync(r.data(), c->d_lq_out.p, r.size() * sizeof(double2), hipMemcpyDeviceToHost,
+                                       nullptr),
+                        "D2H dipole")))
+        return rc;
+    if ((rc = finish_sync(c))) return rc;
+    for (int s = 0; s < ns; ++s) {
+        // f'(0) = i * (derivative / i): the imaginary part is the real sum
+        double m2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            mu[3 * s + a] = r[4 * (size_t)s + 1 + a].x;
+            m2 += mu[3 * s + a] * mu[3 * s + a];
+        }
+        if (f0) f0[s] = 2.0 / 3.0 * dE[s] * m2;
+    }
+    return ok();
+}
+
+int scff_dipole_fit(scff_ctx* c, double q_fit, const double* dE, double* coef, double* f0_fit) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (!coef) return fail(SCFF_EINVAL, "coef must not be NULL");
+    if (!(q_fit > 0.0) || !std::isfinite(q_fit)) return fail(SCFF_EINVAL, "q_fit must be positive and finite");
+    if (f0_fit && !dE) return fail(SCFF_EINVAL, "oscillator strengths need the transition energies dE");
+    int rc;
+    if ((rc = prepare_sync(c))) return rc;
+    const PrepResult& p = c->pres;
+    const int ns = c->n_states;
+    // kFitShells radii q_k = q_fit k / kFitShells; on each, the product rule
+    // of kFitTheta Gauss-Legendre nodes in cos(theta) and kFitPhi equally
+    // spaced phi (exact for the sphere average of polynomials of degree < 12)
+    constexpr int kFitShells = 8, kFitTheta = 6, kFitPhi = 12;
+    std::vector<double> xt, wt;
+    gauss_legendre(kFitTheta, xt, wt);
+    const int ndir = kFitTheta * kFitPhi, nq = kFitShells * ndir;
+    std::vector<double> q(3 * (size_t)nq), wdir(ndir);
+    for (int k = 0; k < kFitShells; ++k) {
+        const double r = q_fit * (k + 1) / kFitShells;
+        for (int t = 0; t < kFitTheta; ++t)
+            for (int ph = 0; ph < kFitPhi; ++ph) {
+                const double ct = xt[t], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+                const double phi = 2.0 * M_PI * ph / kFitPhi;
+                const size_t i = (size_t)k * ndir + t * kFitPhi + ph;
+                q[3 * i] = r * st * std::cos(phi);
+                q[3 * i + 1] = r * st * std::sin(phi);
+                q[3 * i + 2] = r * ct;
+                wdir[t * kFitPhi + ph] = wt[t] / (2.0 * kFitPhi);
+            }
+    }
+    if ((rc = dev_reserve(c, c->d_lq_in, q.size() * sizeof(double))) ||
+        (rc = dev_reserve(c, c->d_lq_out, (size_t)ns * nq * sizeof(double))))
+        return rc;
+    if ((rc = hip_check(hipMemcpyAsync(c->d_lq_in.p, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice,
+                                       nullptr),
+                        "upload points")))
+        return rc;
+    if ((rc = hip_check(launch_points64((const VRowDev*)c->prep.rows.p, (const int4*)c->prep.slots.p,
+                                        (const int*)c->prep.coff.p, (const int*)c->prep.cnpp.p, p.n_units,
+                                        (const double*)c->prep.tp64.p, (const int*)c->prep.vcp.p, ns,
+                                        (const double*)c->d_lq_in.p, nq, (double*)c->d_lq_out.p, nullptr),
+                        "points64 kernel")))
+        return rc;
+    std::vector<double> f2((size_t)ns * nq);
+    if ((rc = hip_check(hipMemcpyAsync(f2.data(), c->d_lq_out.p, f2.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                       nullptr),
+                        "D2H |f|^2")))
+        return rc;
+    if ((rc = finish_sync(c))) return rc;
+    for (int s = 0; s < ns; ++s) {
+        // least squares of <|f|^2>(x) = a0 + a1 x + a2 x^2 in x = (q / q_fit)^2
+        double M[3][3] = {}, v[3] = {};
+        for (int k = 0; k < kFitShells; ++k) {
+            double avg = 0.0;
+            for (int d = 0; d < ndir; ++d) avg += wdir[d] * f2[(size_t)s * nq + (size_t)k * ndir + d];
+            const double x = std::pow((k + 1.0) / kFitShells, 2), b[3] = {1.0, x, x * x};
+            for (int i = 0; i < 3; ++i) {
+                v[i] += b[i] * avg;
+                for (int j = 0; j < 3; ++j) M[i][j] += b[i] * b[j];
+            }
+        }
+        // Gaussian elimination with partial pivoting on the 3 x 3 normal equations
+        int piv[3] = {0, 1, 2};
+        for (int col = 0; col < 3; ++col) {
+            int best = col;
+            for (int r2 = col + 1; r2 < 3; ++r2)
+                if (std::fabs(M[piv[r2]][col]) > std::fabs(M[piv[best]][col])) best = r2;
+            std::swap(piv[col], piv[best]);
+            for (int r2 = col + 1; r2 < 3; ++r2) {
+                const double m = M[piv[r2]][col] / M[piv[col]][col];
+                for (int j = col; j < 3; ++j) M[piv[r2]][j] -= m * M[piv[col]][j];
+                v[piv[r2]] -= m * v[piv[col]];
+            }
+        }
+        double a[3];
+        for (int i = 2; i >= 0; --i) {
+            double t = v[piv[i]];
+            for (int j = i + 1; j < 3; ++j) t -= M[piv[i]][j] * a[j];
+            a[i] = t / M[piv[i]][i];
+        }
+        coef[3 * s] = a[0];
+        coef[3 * s + 1] = a[1] / (q_fit * q_fit);
+        coef[3 * s + 2] = a[2] / (q_fit * q_fit * q_fit * q_fit);
+        if (f0_fit) f0_fit[s] = 2.0 * dE[s] * coef[3 * s + 1];
     }
     return ok();
 }
