@@ -344,15 +344,30 @@ typedef struct {
      * [2] waiting for admission and a run slot, [3] run (tables, grid
      * kernel, copy into pinned staging), [4] copy to the caller's buffers */
     long long ns_stage[5];
+    /* batch launches, the requests they carried, and graph executables
+     * instantiated / reused with updated parameters */
+    long long batches, batched_requests, graphs_instantiated, graphs_updated;
 } scff_server_stats;
 
-/* Create a server on `device`.  Requests are admitted while the device
- * bytes of all in-flight requests fit `hbm_budget_bytes` (0 = 64 GiB) and at
- * most `max_inflight` requests run at once (1..64).  Requests that do not
- * fit wait in FIFO order.  A request larger than the whole budget fails
- * with SCFF_ENOMEM.  The server keeps up to (8 prep threads + max_inflight)
- * idle contexts for reuse, each holding at most budget / (2 x that count)
- * device bytes; this idle memory is not counted against the budget.
+/* Create a server on `device`.  A request is prepared (basis, pair
+ * precompute, screening, packing: its exact device footprint is then known)
+ * by one of 8 prep threads, admitted in FIFO order while the device bytes of
+ * all admitted requests fit `hbm_budget_bytes` (0 = 64 GiB) and at most
+ * `max_inflight` requests are admitted (1..64), and run by one of two batch
+ * runners: every admitted request waiting for a runner joins its next batch,
+ * whose launches (each request's 1D tables, one persistent grid kernel per
+ * kernel variant consuming the (request, tile) items of all its requests
+ * from a device queue, split reductions, result copies) are captured into a
+ * HIP graph; an executable graph is kept per launch topology (up to 32 per
+ * runner) and replayed with the next batch's parameters.  A request's
+ * results are identical alone and in any batch.  A request larger than the
+ * whole budget fails with SCFF_ENOMEM.
+ * Device memory: the budget caps the admitted requests together with the
+ * prepared requests waiting for admission (a new prep starts only while
+ * both leave room, or when nothing is prepared ahead); on top of it come
+ * the preps in progress (at most 8 requests) and the idle contexts kept for
+ * reuse: up to (8 + max_inflight) of them, each holding at most
+ * budget / (2 x that count) device bytes, so at most budget / 2 in total.
  * An idle context keeps the molecule of its last request in device memory:
  * a request on the same molecule (equal geometry, shells, exponents,
  * coefficients and normalise flag) is given that context and skips the

@@ -71,7 +71,9 @@ class scff_server_stats(ctypes.Structure):
                 ("cancelled", c_longlong), ("queued", c_longlong), ("inflight", c_longlong),
                 ("admitted_bytes", c_size_t), ("budget_bytes", c_size_t),
                 ("peak_admitted_bytes", c_size_t), ("peak_inflight", c_longlong),
-                ("mol_cache_hits", c_longlong), ("ns_stage", c_longlong * 5)]
+                ("mol_cache_hits", c_longlong), ("ns_stage", c_longlong * 5),
+                ("batches", c_longlong), ("batched_requests", c_longlong),
+                ("graphs_instantiated", c_longlong), ("graphs_updated", c_longlong)]
 
 
 def _fn(name, res, args):

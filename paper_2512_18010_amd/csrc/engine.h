@@ -33,6 +33,24 @@ struct ChunkSplit {
     int n;                   // number of ranges (1 = no split)
     int lo[kMaxSplit + 1];   // range j is chunks [lo[j], lo[j+1]); lo[0] = 0, lo[n] = n_chunks
 };
+// Everything the fused grid kernel needs for one evaluation (one request of
+// a batch): the 1D tables, the term slots and chunk list, the packed
+// weights, the grid and its tiling, the split of the chunk list and the
+// outputs.  Filled on the host; the batch kernel reads it from device memory.
+struct GridDesc {
+    const float2* V;          // 1D tables [rows][vstride]
+    int vstride, vrows;
+    const int4* terms;        // term slots (row ids)
+    const int4* chunks;       // chunk table (first unit, units, npp, first slot)
+    ChunkSplit sp;
+    const uint32_t* Tp;       // packed weights (FP32 bits or split-BF16 halves)
+    int3 n, ntiles;           // grid points and tiles per axis
+    int nx_eval, n_states;
+    float2* f;                // outputs (NULL to skip), or
+    float* f2;
+    double2* partial;         // FP64 partial sums of a split (NULL: unsplit)
+    long long part_stride;
+};
 // States per MFMA row block.
 constexpr int kStateBlock = 16;
 constexpr int kMaxStates = 32;
@@ -152,5 +170,33 @@ void set_error(const std::string& msg);
 int ctx_prepare(scff_ctx* c, const scff_grid* g, int precision, hipStream_t st, size_t* bytes_needed);
 // Device bytes a context holds (its buffers are kept between calls).
 size_t ctx_device_bytes(const scff_ctx* c);
+
+// Two-phase evaluation of a prepared context for the server's batch runner:
+// ctx_batch_reserve reserves every device buffer the evaluation needs (1D
+// tables, device outputs, split partial sums) and fills the grid kernel's
+// descriptor, without launching anything; ctx_batch_tables and
+// ctx_batch_finish then only enqueue work (1D tables; split reduction and
+// the copy of f / |f|^2 to host memory), so a batch's launches can be
+// captured into a graph.
+struct BatchEval {
+    GridDesc desc;
+    int cls = 0;               // grid kernel variant
+    long long blocks = 0;      // tiles x splits of the evaluation
+    int n_split = 1, nx_eval = 0;
+    size_t nout = 0;           // output values (n_states x grid points)
+};
+int ctx_batch_reserve(scff_ctx* c, const scff_grid* g, int precision, bool want_f, bool want_f2, BatchEval* be);
+int ctx_batch_tables(scff_ctx* c, const scff_grid* g, hipStream_t st);
+int ctx_batch_finish(scff_ctx* c, const scff_grid* g, const BatchEval& be, float* host_f, float* host_f2,
+                     hipStream_t st);
+// After the batch's stream has been synchronised: the context has no
+// asynchronous work pending.
+void ctx_batch_done(scff_ctx* c);
+// Grid kernel launchers (kernels.hip)
+int grid_wg_per_cu(int state_blocks, int precision);
+hipError_t launch_grid_batch(int cls, const GridDesc* descs, const int2* items, int n_items, int* counter, int wgs,
+                             hipStream_t st);
+hipError_t launch_zero_counters(int* c, int n, hipStream_t st);
+int ctx_n_cu(const scff_ctx* c);
 
 }  // namespace scff

@@ -125,7 +125,35 @@ __device__ __forceinline__ uint32_t lds_addr(T* p) { return (uint32_t)(uintptr_t
 // explicitly by barrier_dma.
 __device__ __forceinline__ void dma_b128(uint32_t voff, const void* sbase, uint32_t lds_byte) {
     const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_byte);
-    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(sbase), "{m0}"(m0) : "memory");
+    // the base is wave-uniform; say so, so that it lives in scalar registers
+    // also where it was loaded from memory (the batch kernel's descriptors)
+    // (readfirstlane returns a signed int: each half is widened through
+    // uint32_t, never sign-extended into the other half)
+    const uint64_t b = (uint64_t)(uintptr_t)sbase;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    const uint64_t bu = ((uint64_t)hi << 32) | (uint64_t)lo;
+    // s_nop 4: five wait states between a VALU write of the base or M0
+    // (v_readfirstlane) and their read by the VMEM instruction, which the
+    // compiler cannot see inside the asm; also covers the M0 write (one)
+    asm volatile("s_nop 4\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(bu), "{m0}"(m0) : "memory");
+}
+
+typedef int sint4 __attribute__((ext_vector_type(4)));
+
+// One 16-byte entry of a wave-uniform table (the chunk table) read through
+// the scalar cache into scalar registers.  A load the compiler would issue
+// itself after the DMA asm (which clobbers memory) goes through vector
+// memory, and its wait would also wait for the DMA in flight.  The wait for
+// the result is in the same asm block; s_nop 4 covers a VALU-written base.
+__device__ __forceinline__ int4 sload_int4(const int4* p) {
+    const uint64_t b = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    const uint64_t bu = ((uint64_t)hi << 32) | (uint64_t)lo;
+    sint4 r;
+    asm volatile("s_nop 4\n\ts_load_dwordx4 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(bu) : "memory");
+    return make_int4(r.x, r.y, r.z, r.w);
 }
 
 // LDS-only barrier: prior LDS reads/writes of this wave complete, DMA may
@@ -139,12 +167,26 @@ __device__ __forceinline__ void barrier_dma() {
     asm volatile("s_barrier" ::: "memory");
 }
 
-template <int SB, int QZL, int WPE, bool BF, int NW>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(
-    const float2* __restrict__ V, int vstride, int vrows, const int4* __restrict__ terms,
-    const int4* __restrict__ chunks, ChunkSplit sp, const uint32_t* __restrict__ Tp, int3 n, int3 ntiles,
-    int nx_eval, int n_states, float2* __restrict__ f, float* __restrict__ f2, double2* __restrict__ partial,
-    long long part_stride) {
+// One tile of one evaluation (blk = split * tiles + tile, as the single-request
+// launch numbers its workgroups).  Shared by the single-request kernel (one
+// tile per workgroup) and the persistent batch kernel (tiles of several
+// requests popped from a queue), so a tile's values do not depend on which
+// of the two computed it.
+template <int SB, int QZL, bool BF, int NW>
+__device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
+    const float2* __restrict__ V = d.V;
+    const int vstride = d.vstride, vrows = d.vrows;
+    const int4* __restrict__ terms = d.terms;
+    const int4* __restrict__ chunks = d.chunks;
+    const ChunkSplit& sp = d.sp;
+    const uint32_t* __restrict__ Tp = d.Tp;
+    const int3 n = d.n, ntiles = d.ntiles;
+    const int nx_eval = d.nx_eval, n_states = d.n_states;
+    float2* __restrict__ f = d.f;
+    float* __restrict__ f2 = d.f2;
+    double2* __restrict__ partial = d.partial;
+    const long long part_stride = d.part_stride;
+
     constexpr int NT = NW * 64;        // threads
     constexpr int ZH = NW / 4;         // waves per q_x line of the tile (q_z halves)
     constexpr int TZ = 4 * QZL * ZH;   // q_z values of the tile
@@ -181,7 +223,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WP
     const int zgrp = ln & 3;           // qz values zgrp*QZL .. zgrp*QZL+QZL-1
 
     // block = (split of the chunk list, tile); a split sums chunks [c_lo, c_hi)
-    int b = blockIdx.x;
+    int b = blk;
     const int split = b / (ntiles.x * ntiles.y * ntiles.z);
     b -= split * (ntiles.x * ntiles.y * ntiles.z);
     const int c_lo = sp.lo[split], c_hi = sp.lo[split + 1];
@@ -205,7 +247,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WP
     // row ids of the slices of chunk c (loaded one chunk ahead of the DMA)
     int rid[NJ];
     auto load_rows = [&](int c) {
-        const int4 ch = chunks[c];   // (first unit, units, npp, first slot)
+        const int4 ch = sload_int4(chunks + c);   // (first unit, units, npp, first slot)
         const int nptl = ch.y * kChunk * ch.z;
         const int* tc = reinterpret_cast<const int*>(terms + ch.w);
         // lane indices recomputed here rather than kept live across the loop
@@ -228,7 +270,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WP
                 dma_b128(8u * (__umul24(r, vstride) + qoff), V, rbase + (TPP * j + 4 * wave) * kParts * 16);
             }
         }
-        const int4 ch = chunks[c];
+        const int4 ch = sload_int4(chunks + c);
         const int tpf4 = ch.y * (kChunk * SW / 4);   // float4 of Tp in this chunk
         if (64 * wave < tpf4 && lane < tpf4 - 64 * wave)
             dma_b128(16u * (64 * wave + lane), Tp + (size_t)ch.x * kChunk * SW, tbase + 1024 * wave);
@@ -264,7 +306,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WP
     int units_done = 0;   // units contracted so far (fold cadence of the FP32 path)
 
     auto chunk_body = [&](int c, const float4* R, const uint32_t* T) {
-        const int4 ch = chunks[c];
+        const int4 ch = sload_int4(chunks + c);
         const int nu = ch.y;
         const int npp = ch.z;
         // W = Vx * Vy: item = (term, qx, pair of q_y lines).  The 16 items of
@@ -487,6 +529,37 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WP
             }
 }
 
+template <int SB, int QZL, int WPE, bool BF, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_kernel(GridDesc d) {
+    grid_tile<SB, QZL, BF, NW>(d, blockIdx.x);
+}
+
+// Persistent batch kernel: every workgroup pops (request, tile) items from a
+// device queue (items[i] = (descriptor index, tile of that request's launch))
+// through an atomic counter until the queue is exhausted, so the tiles of
+// several requests share one launch.  Every workgroup leaves the loop once
+// the counter passes n_items; the counter must be 0 at launch.
+template <int SB, int QZL, int WPE, bool BF, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void grid_batch_kernel(
+    const GridDesc* __restrict__ descs, const int2* __restrict__ items, int n_items, int* __restrict__ counter) {
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();   // the previous tile's LDS use (epilogue staging) is over
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        grid_tile<SB, QZL, BF, NW>(descs[w.x], w.y);
+    }
+}
+
+// Zeroes the batch queue counters (a kernel rather than a memset, so a
+// captured graph replays it faithfully).
+__global__ void zero_counters_kernel(int* __restrict__ c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
 // ---------------------------------------------------------------- split reduction
 //
 // Sum of the FP64 partial results of the chunk-list splits (fixed order) for
@@ -618,28 +691,17 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
     return hipGetLastError();
 }
 
-template <int SB, int QZL, int WPE, bool BF, int NW>
-static hipError_t launch_grid_t(const float2* V, int vstride, int vrows, const int4* terms, const int4* chunks,
-                                const ChunkSplit& sp, const uint32_t* Tp, const int n[3], int nx_eval,
-                                int n_states, float2* f, float* f2, double2* part, hipStream_t st) {
-    const int3 nn = make_int3(n[0], n[1], n[2]);
-    constexpr int TZ = 4 * QZL * (NW / 4);
-    const int3 nt = make_int3((nx_eval + 3) / 4, (n[1] + 7) / 8, (n[2] + TZ - 1) / TZ);
-    const long long blocks = (long long)nt.x * nt.y * nt.z * sp.n;
-    const long long stride = (long long)n_states * n[0] * n[1] * n[2];
-    hipLaunchKernelGGL((grid_kernel<SB, QZL, WPE, BF, NW>), dim3((unsigned)blocks), dim3(NW * 64), 0, st, V, vstride,
-                       vrows, terms, chunks, sp, Tp, nn, nt, nx_eval, n_states, f, f2, sp.n > 1 ? part : nullptr,
-                       stride);
-    return hipGetLastError();
-}
-
+// Kernel variant of an evaluation: class = (state blocks - 1) + 2 * precision.
+//   4 q_z per lane (8 q values) except for the FP32 contraction of 17..32
+//   states (2 q_z per lane, 8 waves per tile), whose accumulators and FP64
+//   fold totals would not fit 2 waves per SIMD otherwise.
 // Every variant's tile covers 16 q_z values: 4 per lane on one wave per q_x
-// line, except the FP32 contraction of 17..32 states, whose accumulators and
-// FP64 fold totals leave room for 2 q_z per lane only: it runs 8 waves per
-// workgroup (two per q_x line).  Workgroups resident per CU: two of 4 waves,
-// or one of 8 (2 waves per SIMD either way).
+// line, or 2 per lane on two waves per line.  Workgroups resident per CU: two
+// of 4 waves, or one of 8 (2 waves per SIMD either way).
 static int tile_qz(int, int) { return 16; }
 int grid_wg_per_cu(int state_blocks, int precision) { return state_blocks == 2 && precision == 0 ? 1 : 2; }
+int grid_class(int state_blocks, int precision) { return (state_blocks - 1) + 2 * precision; }
+static int class_waves(int cls) { return cls == 1 ? 8 : 4; }
 
 long long grid_tiles(int state_blocks, int precision, const int n[3], int nx_eval) {
     const int tz = tile_qz(state_blocks, precision);
@@ -654,31 +716,83 @@ int vtable_stride(const int n[3]) {
     return ((m + 15) / 16) * 16 + 16;
 }
 
-hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride, int vrows,
-                       const int4* terms, const int4* chunks, const ChunkSplit& sp, const float* Tp,
-                       const uint32_t* tp_bf, const int n[3], int nx_eval, int n_states, float2* f, float* f2,
-                       double2* part, hipStream_t st) {
+hipError_t grid_desc(int state_blocks, int precision, const float2* V, int vstride, int vrows, const int4* terms,
+                     const int4* chunks, const ChunkSplit& sp, const float* Tp, const uint32_t* tp_bf,
+                     const int n[3], int nx_eval, int n_states, float2* f, float* f2, double2* part, GridDesc* d,
+                     long long* blocks) {
     if (precision != 0 && precision != 1) return hipErrorInvalidValue;
+    if (state_blocks != 1 && state_blocks != 2) return hipErrorInvalidValue;
     if (vstride < vtable_stride(n) || vrows < 1) return hipErrorInvalidValue;
     if (nx_eval < 1 || nx_eval > n[0]) return hipErrorInvalidValue;
     if (sp.n < 1 || sp.n > kMaxSplit || sp.lo[0] != 0) return hipErrorInvalidValue;
     for (int j = 0; j < sp.n; ++j)
         if (sp.lo[j + 1] < sp.lo[j]) return hipErrorInvalidValue;
     if (sp.n > 1 && !part) return hipErrorInvalidValue;
-    const uint32_t* tp32 = reinterpret_cast<const uint32_t*>(Tp);
-#define SCFF_GRID(SB_, QZL_, WPE_, BF_, NW_) \
-    return launch_grid_t<SB_, QZL_, WPE_, BF_, NW_>(V, vstride, vrows, terms, chunks, sp, BF_ ? tp_bf : tp32, n, nx_eval, \
-                                               n_states, f, f2, part, st)
-    // 4 q_z per lane (8 q values) except for the FP32 contraction of 17..32
-    // states (2 q_z per lane, 8 waves per tile), whose accumulators and FP64
-    // fold totals would not fit 2 waves per SIMD otherwise
-    if (precision == 1) {
-        if (state_blocks == 1) SCFF_GRID(1, 4, 2, true, 4);
-        SCFF_GRID(2, 4, 2, true, 4);
+    const int tz = tile_qz(state_blocks, precision);
+    d->V = V;
+    d->vstride = vstride;
+    d->vrows = vrows;
+    d->terms = terms;
+    d->chunks = chunks;
+    d->sp = sp;
+    d->Tp = precision == 1 ? tp_bf : reinterpret_cast<const uint32_t*>(Tp);
+    d->n = make_int3(n[0], n[1], n[2]);
+    d->ntiles = make_int3((nx_eval + 3) / 4, (n[1] + 7) / 8, (n[2] + tz - 1) / tz);
+    d->nx_eval = nx_eval;
+    d->n_states = n_states;
+    d->f = f;
+    d->f2 = f2;
+    d->partial = sp.n > 1 ? part : nullptr;
+    d->part_stride = (long long)n_states * n[0] * n[1] * n[2];
+    *blocks = (long long)d->ntiles.x * d->ntiles.y * d->ntiles.z * sp.n;
+    return hipSuccess;
+}
+
+hipError_t launch_grid_desc(int cls, const GridDesc& d, long long blocks, hipStream_t st) {
+    const dim3 grid((unsigned)blocks);
+    switch (cls) {
+        case 0: hipLaunchKernelGGL((grid_kernel<1, 4, 2, false, 4>), grid, dim3(256), 0, st, d); break;
+        case 1: hipLaunchKernelGGL((grid_kernel<2, 2, 2, false, 8>), grid, dim3(512), 0, st, d); break;
+        case 2: hipLaunchKernelGGL((grid_kernel<1, 4, 2, true, 4>), grid, dim3(256), 0, st, d); break;
+        case 3: hipLaunchKernelGGL((grid_kernel<2, 4, 2, true, 4>), grid, dim3(256), 0, st, d); break;
+        default: return hipErrorInvalidValue;
     }
-    if (state_blocks == 1) SCFF_GRID(1, 4, 2, false, 4);
-    SCFF_GRID(2, 2, 2, false, 8);
-#undef SCFF_GRID
+    return hipGetLastError();
+}
+
+// Persistent launch over a queue of (descriptor, tile) items of class cls:
+// `wgs` workgroups (the device's resident capacity), each looping until the
+// queue is exhausted.  *counter must be 0 when the launch starts.
+hipError_t launch_grid_batch(int cls, const GridDesc* descs, const int2* items, int n_items, int* counter, int wgs,
+                             hipStream_t st) {
+    if (n_items < 1 || wgs < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)wgs), block(class_waves(cls) * 64);
+    switch (cls) {
+        case 0: hipLaunchKernelGGL((grid_batch_kernel<1, 4, 2, false, 4>), grid, block, 0, st, descs, items, n_items, counter); break;
+        case 1: hipLaunchKernelGGL((grid_batch_kernel<2, 2, 2, false, 8>), grid, block, 0, st, descs, items, n_items, counter); break;
+        case 2: hipLaunchKernelGGL((grid_batch_kernel<1, 4, 2, true, 4>), grid, block, 0, st, descs, items, n_items, counter); break;
+        case 3: hipLaunchKernelGGL((grid_batch_kernel<2, 4, 2, true, 4>), grid, block, 0, st, descs, items, n_items, counter); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(int* c, int n, hipStream_t st) {
+    if (n < 1 || n > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, st, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid(int state_blocks, int precision, const float2* V, int vstride, int vrows,
+                       const int4* terms, const int4* chunks, const ChunkSplit& sp, const float* Tp,
+                       const uint32_t* tp_bf, const int n[3], int nx_eval, int n_states, float2* f, float* f2,
+                       double2* part, hipStream_t st) {
+    GridDesc d;
+    long long blocks = 0;
+    const hipError_t e = grid_desc(state_blocks, precision, V, vstride, vrows, terms, chunks, sp, Tp, tp_bf, n,
+                                   nx_eval, n_states, f, f2, part, &d, &blocks);
+    if (e != hipSuccess) return e;
+    return launch_grid_desc(grid_class(state_blocks, precision), d, blocks, st);
 }
 
 hipError_t launch_reduce(const double2* part, int n_split, const int n[3], int nx_eval, int n_states, float2* f,

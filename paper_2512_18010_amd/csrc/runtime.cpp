@@ -26,7 +26,11 @@ hipError_t launch_reduce(const double2* part, int n_split, const int n[3], int n
                          float* f2, hipStream_t st);
 hipError_t launch_mirror(const int n[3], int nx_eval, int n_states, float2* f, float* f2, hipStream_t st);
 long long grid_tiles(int state_blocks, int precision, const int n[3], int nx_eval);
-int grid_wg_per_cu(int state_blocks, int precision);
+int grid_class(int state_blocks, int precision);
+hipError_t grid_desc(int state_blocks, int precision, const float2* V, int vstride, int vrows, const int4* terms,
+                     const int4* chunks, const ChunkSplit& sp, const float* Tp, const uint32_t* tp_bf,
+                     const int n[3], int nx_eval, int n_states, float2* f, float* f2, double2* part, GridDesc* d,
+                     long long* blocks);
 hipError_t launch_points(int state_blocks, const VRowDev* rows, const int4* terms, const int* coff,
                          const int* cnpp, int n_chunks, const float* Tp, const double* q, int nq,
                          int n_states, float2* f, float* f2, hipStream_t st);
@@ -450,6 +454,72 @@ int scff::ctx_prepare(scff_ctx* c, const scff_grid* g, int precision, hipStream_
 }
 
 size_t scff::ctx_device_bytes(const scff_ctx* c) { return c ? c->used : 0; }
+
+int scff::ctx_n_cu(const scff_ctx* c) { return c->n_cu; }
+
+int scff::ctx_batch_reserve(scff_ctx* c, const scff_grid* g, int precision, bool want_f, bool want_f2,
+                            BatchEval* be) {
+    int rc = validate_grid(g);
+    if (rc) return rc;
+    if ((rc = check_precision(precision))) return rc;
+    if (!c->prepared) return fail(SCFF_ESTATE, "batch evaluation of a context that is not prepared");
+    if ((rc = set_device(c))) return rc;
+    const size_t nout = (size_t)g->n[0] * g->n[1] * g->n[2] * (size_t)c->n_states;
+    const int stride = vtable_stride(g->n);
+    if ((size_t)c->pres.n_rows * stride * sizeof(float2) > 0xffffffffull)
+        return fail(SCFF_EINVAL, "1D tables of this grid exceed 4 GiB: evaluate it in slabs");
+    if ((rc = dev_reserve(c, c->d_vtab, (size_t)c->pres.n_rows * stride * sizeof(float2)))) return rc;
+    if (want_f && (rc = dev_reserve(c, c->d_f, nout * sizeof(float2)))) return rc;
+    if (want_f2 && (rc = dev_reserve(c, c->d_f2, nout * sizeof(float)))) return rc;
+    EvalPlan pl = plan_eval(c, g, precision);
+    double2* part = nullptr;
+    if (pl.sp.n > 1) {
+        if (dev_reserve(c, c->d_part, (size_t)pl.sp.n * nout * sizeof(double2)) == SCFF_OK)
+            part = (double2*)c->d_part.p;
+        else
+            pl = plan_eval(c, g, precision, false);
+    }
+    const PrepResult& p = c->pres;
+    hipError_t e = grid_desc(p.state_blocks, precision, (const float2*)c->d_vtab.p, stride, p.n_rows,
+                             (const int4*)c->prep.slots.p, (const int4*)c->prep.chunks.p, pl.sp,
+                             (const float*)c->prep.tp32.p, (const uint32_t*)c->prep.tpbf.p, g->n, pl.nx_eval,
+                             c->n_states, want_f ? (float2*)c->d_f.p : nullptr, want_f2 ? (float*)c->d_f2.p : nullptr,
+                             part, &be->desc, &be->blocks);
+    if (e != hipSuccess) return hip_check(e, "grid descriptor");
+    be->cls = grid_class(p.state_blocks, precision);
+    be->n_split = pl.sp.n;
+    be->nx_eval = pl.nx_eval;
+    be->nout = nout;
+    c->vtab_rows = p.n_rows;
+    c->vtab_stride = stride;
+    c->async_open = true;   // device work follows on the batch stream
+    return ok();
+}
+
+int scff::ctx_batch_tables(scff_ctx* c, const scff_grid* g, hipStream_t st) {
+    double dq[3];
+    for (int a = 0; a < 3; ++a) dq[a] = g->n[a] > 1 ? (g->qmax[a] - g->qmin[a]) / (g->n[a] - 1) : 0.0;
+    return hip_check(launch_vtable((const VRowDev*)c->prep.rows.p, c->vtab_rows, c->vtab_stride, g->n, g->qmin, dq,
+                                   (float2*)c->d_vtab.p, st),
+                     "vtable kernel launch");
+}
+
+int scff::ctx_batch_finish(scff_ctx* c, const scff_grid* g, const BatchEval& be, float* host_f, float* host_f2,
+                           hipStream_t st) {
+    int rc;
+    float2* df = be.desc.partial ? (host_f ? (float2*)c->d_f.p : nullptr) : be.desc.f;
+    float* df2 = be.desc.partial ? (host_f2 ? (float*)c->d_f2.p : nullptr) : be.desc.f2;
+    if (be.n_split > 1 &&
+        (rc = hip_check(launch_reduce(be.desc.partial, be.n_split, g->n, be.nx_eval, c->n_states, df, df2, st),
+                        "reduce launch")))
+        return rc;
+    if (be.nx_eval < g->n[0] &&
+        (rc = hip_check(launch_mirror(g->n, be.nx_eval, c->n_states, df, df2, st), "mirror kernel launch")))
+        return rc;
+    return copy_out(df, host_f, df2, host_f2, be.nout, st);
+}
+
+void scff::ctx_batch_done(scff_ctx* c) { order_done(c); }
 
 extern "C" {
 

@@ -8,10 +8,14 @@
 //             when its footprint fits the HBM budget next to everything in
 //             flight and a run slot is free; requests arriving meanwhile
 //             queue behind it, so no request starves
-//   run       (run slot, one HIP stream each) 1D tables, fused generator +
-//             MFMA kernel, copy of the results into a pinned staging
-//             buffer of the server (a DMA at full link speed); several
-//             requests run at once and their kernels overlap on the device
+//   run       (batch runners, one HIP stream each) every admitted request
+//             waiting for a runner joins its next batch: one graph-captured
+//             launch sequence per batch (1D tables of each request, one
+//             persistent grid kernel per kernel variant popping the
+//             (request, tile) items of all its requests from a device queue,
+//             split reductions, copies of the results into pinned staging
+//             buffers of the server); two runners alternate, so one batch
+//             is assembled while the other runs
 //   copy      (copy threads) staging buffer -> the caller's host buffers;
 //             the run slot and the device memory are released before this,
 //             so the next request's kernels do not wait for host copies
@@ -127,6 +131,9 @@ struct scff_server {
     std::vector<scff_ctx*> to_free;    // contexts to destroy outside the lock
     size_t pool_cap = 0;               // idle contexts kept at most
     size_t pool_ctx_max = 0;           // largest context (device bytes) kept idle
+    size_t staged = 0;                 // device bytes of prepared requests waiting for admission
+    long long batches = 0, batched_requests = 0;             // batch launches and the requests in them
+    long long graphs_instantiated = 0, graphs_updated = 0;   // graph executables created / reused
 };
 
 namespace {
@@ -262,7 +269,11 @@ void prep_loop(scff_server* s) {
         Req* r;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_prep.wait(lk, [&] { return s->stop || !s->prep_q.empty(); });
+            // a new prep starts while the admitted and the prepared-but-waiting
+            // requests leave room in the budget (or nothing is prepared ahead)
+            s->cv_prep.wait(lk, [&] {
+                return s->stop || (!s->prep_q.empty() && (s->admitted + s->staged < s->budget || s->staged == 0));
+            });
             if (s->stop) {
                 if (pst) (void)hipStreamDestroy(pst);
                 return;
@@ -343,6 +354,7 @@ void prep_loop(scff_server* s) {
             r->bytes = bytes;
             r->t_prep1 = Clock::now();
             r->state = St::Ready;
+            s->staged += r->bytes;
         }
         unref(s, t);   // the prep reference
         unref(s, t);   // the prep_q entry
@@ -368,6 +380,8 @@ void sched_loop(scff_server* s) {
             }
             if (r->state != St::Ready) break;                 // head not prepared yet
             if (r->bytes > s->budget) {                       // can never fit
+                s->staged -= r->bytes;
+                s->cv_prep.notify_all();
                 s->admit_q.pop_front();
                 unref(s, t);
                 give_ctx(s, r->ctx, r->ctx_mol);
@@ -386,6 +400,7 @@ void sched_loop(scff_server* s) {
             unref(s, t);
             r->state = St::Running;
             s->admitted += r->bytes;
+            s->staged -= r->bytes;
             if (s->admitted > s->peak_admitted) s->peak_admitted = s->admitted;
             ++s->inflight;
             if (s->inflight > s->peak_inflight) s->peak_inflight = s->inflight;
@@ -397,64 +412,273 @@ void sched_loop(scff_server* s) {
     }
 }
 
-void run_loop(scff_server* s) {
+// A batch runner: takes every admitted request waiting for it (up to
+// max_inflight), and runs them as one batch on its own stream:
+//   reserve   each request's device buffers (tables, outputs, split sums)
+//             and its grid-kernel descriptor, nothing launched yet;
+//   capture   into a graph: upload of the descriptors and of the queue of
+//             (request, tile) items, counter reset (a kernel), each
+//             request's 1D tables, one persistent grid kernel per kernel
+//             variant present, popping the items of all requests of that
+//             variant from the queue, then each request's split reduction
+//             and the copy of its results into its pinned staging buffer;
+//   replay    the graph: an executable graph is kept per launch topology and
+//             its parameters updated for the next batch of the same
+//             topology (hipGraphExecUpdate), else one is instantiated.
+// Two runners alternate, so one batch is assembled while the other runs.
+struct Runner {
     hipStream_t st = nullptr;
+    void* d_buf = nullptr;     // descriptors, then items
+    size_t d_cap = 0;
+    int* d_cnt = nullptr;      // one queue counter per kernel variant
+    void* h_buf = nullptr;     // pinned staging of descriptors and items
+    size_t h_cap = 0;
+    std::vector<std::pair<std::string, hipGraphExec_t>> execs;   // by topology, most recent last
+    long long graphs_instantiated = 0, graphs_updated = 0;
+};
+
+constexpr size_t kMaxExecs = 32;
+constexpr int kRunners = 2;
+constexpr int kVariants = 4;
+
+int grow_device(void** p, size_t* cap, size_t need) {
+    if (*cap >= need) return SCFF_OK;
+    size_t c = std::max<size_t>(need, 2 * *cap);
+    c = std::max<size_t>(c, 4096);
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc(p, c) != hipSuccess) return sfail(SCFF_ENOMEM, "batch queue allocation failed");
+    *cap = c;
+    return SCFF_OK;
+}
+
+int grow_pinned(void** p, size_t* cap, size_t need) {
+    if (*cap >= need) return SCFF_OK;
+    size_t c = std::max<size_t>(need, 2 * *cap);
+    c = std::max<size_t>(c, 4096);
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipHostMalloc(p, c, hipHostMallocDefault) != hipSuccess) return sfail(SCFF_ENOMEM, "pinned queue allocation failed");
+    *cap = c;
+    return SCFF_OK;
+}
+
+struct Member {
+    Req* r;
+    void* stage = nullptr;
+    scff::BatchEval be;
+    int rc = SCFF_OK;
+    std::string err;
+};
+
+// Runs the batch's device work; returns SCFF_OK or the error of a launch (then
+// every member that had not failed alone fails with it).
+int run_batch(scff_server* s, Runner& R, std::vector<Member>& ms) {
+    std::vector<Member*> live;
+    for (Member& m : ms)
+        if (m.rc == SCFF_OK) live.push_back(&m);
+    if (live.empty()) return SCFF_OK;
+    // queue of (descriptor, tile) items, grouped by kernel variant, requests in ticket order
+    std::vector<int2> items;
+    int off[kVariants + 1] = {};
+    for (int v = 0; v < kVariants; ++v) {
+        off[v] = (int)items.size();
+        for (size_t i = 0; i < live.size(); ++i)
+            if (live[i]->be.cls == v)
+                for (long long b = 0; b < live[i]->be.blocks; ++b) items.push_back(make_int2((int)i, (int)b));
+    }
+    off[kVariants] = (int)items.size();
+    const size_t dbytes = (live.size() * sizeof(scff::GridDesc) + 255) & ~(size_t)255;
+    const size_t need = dbytes + items.size() * sizeof(int2);
+    int rc;
+    if ((rc = grow_device(&R.d_buf, &R.d_cap, need)) || (rc = grow_pinned(&R.h_buf, &R.h_cap, need))) return rc;
+    for (size_t i = 0; i < live.size(); ++i)
+        std::memcpy((char*)R.h_buf + i * sizeof(scff::GridDesc), &live[i]->be.desc, sizeof(scff::GridDesc));
+    std::memcpy((char*)R.h_buf + dbytes, items.data(), items.size() * sizeof(int2));
+    const auto* d_desc = (const scff::GridDesc*)R.d_buf;
+    const auto* d_items = (const int2*)((const char*)R.d_buf + dbytes);
+    // launch topology: per member its variant, split and outputs; per variant whether it runs
+    std::string topo;
+    for (Member* m : live)
+        topo += std::to_string(m->be.cls) + (m->be.n_split > 1 ? "s" : "u") + (m->r->f ? "f" : "-") +
+                (m->r->f2 ? "g" : "-") + ";";
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return sfail(SCFF_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
+    rc = SCFF_OK;
+    std::string err;
+    auto hip_ok = [&](hipError_t x, const char* what) {
+        if (x != hipSuccess && rc == SCFF_OK) {
+            rc = SCFF_EDEVICE;
+            err = std::string(what) + ": " + hipGetErrorString(x);
+        }
+        return rc == SCFF_OK;
+    };
+    if (hip_ok(hipMemcpyAsync(R.d_buf, R.h_buf, need, hipMemcpyHostToDevice, R.st), "queue upload") &&
+        hip_ok(scff::launch_zero_counters(R.d_cnt, kVariants, R.st), "counter reset")) {
+        for (Member* m : live)
+            if (rc == SCFF_OK && scff::ctx_batch_tables(m->r->ctx, &m->r->grid, R.st) != SCFF_OK) {
+                rc = SCFF_EDEVICE;
+                err = scff_last_error();
+            }
+        const int ncu = scff::ctx_n_cu(live[0]->r->ctx);
+        for (int v = 0; v < kVariants && rc == SCFF_OK; ++v) {
+            const int n = off[v + 1] - off[v];
+            if (n == 0) continue;
+            topo += "k" + std::to_string(v);
+            const int wgs = std::min(n, ncu * scff::grid_wg_per_cu(v % 2 + 1, v / 2));
+            hip_ok(scff::launch_grid_batch(v, d_desc, d_items + off[v], n, R.d_cnt + v, wgs, R.st), "batch grid kernel");
+        }
+        for (Member* m : live) {
+            if (rc != SCFF_OK) break;
+            const size_t np = m->be.nout;
+            float* sf = m->r->f ? (float*)m->stage : nullptr;
+            float* sf2 = m->r->f2 ? (float*)m->stage + 2 * np : nullptr;
+            if (scff::ctx_batch_finish(m->r->ctx, &m->r->grid, m->be, sf, sf2, R.st) != SCFF_OK) {
+                rc = SCFF_EDEVICE;
+                err = scff_last_error();
+            }
+        }
+    }
+    e = hipStreamEndCapture(R.st, &graph);
+    if (rc == SCFF_OK && e != hipSuccess) {
+        rc = SCFF_EDEVICE;
+        err = std::string("stream capture: ") + hipGetErrorString(e);
+    }
+    if (rc != SCFF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return sfail(rc, err);
+    }
+    // an executable graph of this topology: update it, else instantiate one
+    hipGraphExec_t exec = nullptr;
+    for (size_t i = 0; i < R.execs.size(); ++i)
+        if (R.execs[i].first == topo) {
+            exec = R.execs[i].second;
+            R.execs.erase(R.execs.begin() + (long)i);
+            break;
+        }
+    if (exec) {
+        hipGraphExecUpdateResult res;
+        hipGraphNode_t bad = nullptr;
+        if (hipGraphExecUpdate(exec, graph, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+        } else {
+            ++R.graphs_updated;
+        }
+    }
+    if (!exec) {
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return sfail(SCFF_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(e));
+        }
+        ++R.graphs_instantiated;
+    }
+    (void)hipGraphDestroy(graph);
+    R.execs.emplace_back(topo, exec);
+    if (R.execs.size() > kMaxExecs) {
+        (void)hipGraphExecDestroy(R.execs.front().second);
+        R.execs.erase(R.execs.begin());
+    }
+    e = hipGraphLaunch(exec, R.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(R.st);
+    if (e != hipSuccess) return sfail(SCFF_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+    return SCFF_OK;
+}
+
+void run_loop(scff_server* s) {
+    Runner R;
     if (!s->fake) {
         (void)hipSetDevice(s->device);
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+        if (hipStreamCreateWithFlags(&R.st, hipStreamNonBlocking) != hipSuccess) R.st = nullptr;
+        if (hipMalloc((void**)&R.d_cnt, kVariants * sizeof(int)) != hipSuccess) R.d_cnt = nullptr;
     }
     for (;;) {
-        Req* r;
+        std::vector<Member> ms;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_run.wait(lk, [&] { return s->stop || !s->run_q.empty(); });
             if (s->stop && s->run_q.empty()) break;
-            r = lookup(s, s->run_q.front());
-            s->run_q.pop_front();
-            if (!r) continue;
-            r->t_run0 = Clock::now();
-        }
-        int rc = SCFF_OK;
-        std::string err;
-        void* stage = nullptr;
-        if (!s->fake) {
-            // outputs into a pinned staging buffer (f, then |f|^2); when the
-            // call returns, the context's work and the copy are complete
-            const size_t np = out_points(r);
-            stage = take_stage(s, np * (sizeof(float) * 2 + sizeof(float)));
-            if (!stage) {
-                rc = SCFF_ENOMEM;
-                err = "pinned staging buffer allocation failed";
-            } else {
-                float* sf = r->f ? (float*)stage : nullptr;
-                float* sf2 = r->f2 ? (float*)stage + 2 * np : nullptr;
-                rc = scff_eval_grid(r->ctx, &r->grid, r->precision, sf, sf2, 0, st);
-                if (rc != SCFF_OK) err = scff_last_error();
+            const auto now = Clock::now();
+            while (!s->run_q.empty() && (int)ms.size() < s->max_inflight) {
+                Req* r = lookup(s, s->run_q.front());
+                s->run_q.pop_front();
+                if (!r) continue;
+                r->t_run0 = now;
+                Member m;
+                m.r = r;
+                ms.push_back(std::move(m));
             }
+            s->batches += ms.empty() ? 0 : 1;
+            s->batched_requests += (long long)ms.size();
+        }
+        if (!s->fake) {
+            for (Member& m : ms) {
+                Req* r = m.r;
+                if (!R.st || !R.d_cnt) {
+                    m.rc = SCFF_EDEVICE;
+                    m.err = "batch runner has no stream or queue counters";
+                    continue;
+                }
+                m.stage = take_stage(s, out_points(r) * (sizeof(float) * 2 + sizeof(float)));
+                if (!m.stage) {
+                    m.rc = SCFF_ENOMEM;
+                    m.err = "pinned staging buffer allocation failed";
+                    continue;
+                }
+                m.rc = scff::ctx_batch_reserve(r->ctx, &r->grid, r->precision, r->f != nullptr, r->f2 != nullptr, &m.be);
+                if (m.rc != SCFF_OK) m.err = scff_last_error();
+            }
+            const int brc = run_batch(s, R, ms);
+            if (brc != SCFF_OK) {
+                const std::string err = scff_last_error();
+                for (Member& m : ms)
+                    if (m.rc == SCFF_OK) {
+                        m.rc = brc;
+                        m.err = err;
+                    }
+            }
+            for (Member& m : ms) scff::ctx_batch_done(m.r->ctx);
         } else {
             std::this_thread::sleep_for(std::chrono::milliseconds(2));
         }
         std::unique_lock<std::mutex> lk(s->mu);
-        r->t_run1 = Clock::now();
-        give_ctx(s, r->ctx, r->ctx_mol);
-        r->ctx = nullptr;
-        s->admitted -= r->bytes;
-        --s->inflight;
-        if (rc == SCFF_OK && stage) {
-            // results are staged: the copy threads finish the request
-            ++s->copying;
-            s->copy_q.emplace_back(r->ticket, stage);
-            s->cv_copy.notify_one();
-        } else {
-            if (stage) s->stage_free.emplace(s->stage_size[stage], stage);
-            if (rc != SCFF_OK) scff::set_error(err);
-            finish(s, r, rc);
+        s->graphs_instantiated += R.graphs_instantiated;
+        s->graphs_updated += R.graphs_updated;
+        R.graphs_instantiated = R.graphs_updated = 0;
+        for (Member& m : ms) {
+            Req* r = m.r;
+            r->t_run1 = Clock::now();
+            give_ctx(s, r->ctx, r->ctx_mol);
+            r->ctx = nullptr;
+            s->admitted -= r->bytes;
+            s->cv_prep.notify_all();
+            --s->inflight;
+            if (m.rc == SCFF_OK && m.stage) {
+                // results are staged: the copy threads finish the request
+                ++s->copying;
+                s->copy_q.emplace_back(r->ticket, m.stage);
+                s->cv_copy.notify_one();
+            } else if (m.rc == SCFF_OK) {   // scheduler test mode
+                finish(s, r, SCFF_OK);
+            } else {
+                if (m.stage) s->stage_free.emplace(s->stage_size[m.stage], m.stage);
+                scff::set_error(m.err);
+                finish(s, r, m.rc);
+            }
         }
         s->cv_sched.notify_all();
         lk.unlock();
         drain_to_free(s);
     }
-    if (st) (void)hipStreamDestroy(st);
+    for (auto& x : R.execs) (void)hipGraphExecDestroy(x.second);
+    if (R.d_buf) (void)hipFree(R.d_buf);
+    if (R.d_cnt) (void)hipFree(R.d_cnt);
+    if (R.h_buf) (void)hipHostFree(R.h_buf);
+    if (R.st) (void)hipStreamDestroy(R.st);
 }
 
 void copy_loop(scff_server* s) {
@@ -514,7 +738,7 @@ int scff_server_create(int device, size_t hbm_budget_bytes, int max_inflight, sc
     s->pool_ctx_max = s->budget / (2 * s->pool_cap);
     for (int i = 0; i < n_prep; ++i) s->threads.emplace_back(prep_loop, s);
     s->threads.emplace_back(sched_loop, s);
-    for (int i = 0; i < max_inflight; ++i) s->threads.emplace_back(run_loop, s);
+    for (int i = 0; i < kRunners; ++i) s->threads.emplace_back(run_loop, s);
     for (int i = 0; i < 2; ++i) s->threads.emplace_back(copy_loop, s);
     *out = s;
     return SCFF_OK;
@@ -598,6 +822,10 @@ int scff_server_cancel(scff_server* s, unsigned long long ticket) {
     if (it == s->reqs.end()) return sfail(SCFF_EINVAL, "unknown ticket");
     Req* r = it->second.get();
     if (r->state == St::Running || r->state == St::Done) return sfail(SCFF_EBUSY, "request already running or finished");
+    if (r->state == St::Ready) {
+        s->staged -= r->bytes;
+        s->cv_prep.notify_all();
+    }
     r->state = St::Cancelled;
     r->t_done = Clock::now();
     give_ctx(s, r->ctx, r->ctx_mol);
@@ -623,6 +851,10 @@ int scff_server_stats_get(scff_server* s, scff_server_stats* o) {
     o->peak_inflight = s->peak_inflight;
     o->mol_cache_hits = s->n_mol_hits;
     for (int i = 0; i < 5; ++i) o->ns_stage[i] = s->ns_stage[i];
+    o->batches = s->batches;
+    o->batched_requests = s->batched_requests;
+    o->graphs_instantiated = s->graphs_instantiated;
+    o->graphs_updated = s->graphs_updated;
     return SCFF_OK;
 }
 

@@ -144,3 +144,64 @@ def test_failing_requests_fail_alone_on_the_device():
             ctx.set_options(1e-9, 1.0)
             f, f2 = ctx.eval_grid_host(gg, "fp32")
         assert np.array_equal(res[2], f) and np.array_equal(res[3], f2)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_graph_replays_match_eager(precision):
+    """Requests of one shape submitted one after another each run as a batch
+    of the same launch topology, so the runner replays one executable graph
+    with updated parameters; every replay (new transitions each time, eager
+    work of the caller's own in between) is bit-identical to a plain context
+    evaluation of the same request."""
+    import torch
+    from paper_2512_18010_amd import binding
+    (mol, T0, g), = requests(31, 1)
+    rng = np.random.Generator(np.random.PCG64(32))
+    Ts = [wl.make_transitions(rng, mol.nbf, wl.n_occupied(mol.Z), 5) for _ in range(5)]
+    results = []
+    with binding.Server(0, 0, max_inflight=2) as srv:
+        for T in Ts:
+            status, _, f, f2 = srv.wait(srv.submit(mol, T, g, precision=precision, screen_eps=1e-9))
+            assert status == binding.SCFF_OK
+            results.append((f.copy(), f2.copy()))
+            x = torch.ones(1 << 20, device="cuda")
+            torch.cuda.synchronize()
+            assert float(x.sum()) == float(1 << 20)   # eager device work between the replays
+        st = srv.stats()
+    log("stats", st)
+    assert st["graphs_updated"] >= 1, st
+    with binding.Context(0) as ctx:
+        ctx.load_molecule(mol)
+        ctx.set_options(1e-9, 1.0)
+        for T, (f, f2) in zip(Ts, results):
+            ctx.load_transitions(T)
+            fe, f2e = ctx.eval_grid_host(g, precision)
+            assert np.array_equal(f, fe) and np.array_equal(f2, f2e)
+
+
+def test_batches_share_launches_and_budget_caps_admission():
+    """Sixteen requests submitted at once under a budget that holds only a
+    few of them: they run in batches of several requests (fewer batch
+    launches than requests), the admitted bytes never exceed the budget, and
+    every result equals its run alone."""
+    import torch  # noqa: F401
+    from paper_2512_18010_amd import binding
+    reqs = requests(404, 16)
+    alone = []
+    with binding.Server(0, 0, max_inflight=8) as srv:
+        for (mol, T, g) in reqs:
+            status, _, f, f2 = srv.wait(srv.submit(mol, T, g, screen_eps=1e-9))
+            assert status == binding.SCFF_OK
+            alone.append((f.copy(), f2.copy()))
+        fp = srv.stats()["peak_admitted_bytes"]
+    budget = int(3 * fp)
+    with binding.Server(0, budget, max_inflight=8) as srv:
+        tickets = [srv.submit(mol, T, g, screen_eps=1e-9) for (mol, T, g) in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    log("stats", st)
+    assert st["peak_admitted_bytes"] <= budget
+    assert st["batches"] < st["batched_requests"] == 16, st
+    for k, ((fa, f2a), (status, _, fm, f2m)) in enumerate(zip(alone, mixed)):
+        assert status == binding.SCFF_OK
+        assert np.array_equal(fa, fm) and np.array_equal(f2a, f2m), f"request {k} differs alone vs batched"
