@@ -135,7 +135,7 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
             t, i = pending.pop(0)
             st, ns, _, _ = srv.wait(t)
             if st != 0:
-                raise RuntimeError(f"serving request failed with status {st}")
+                raise RuntimeError(f"serving request failed with status {st}: {srv.last_failure()}")
             lat.append(ns * 1e-6)
             out.append(i)
         dt = time.perf_counter() - t0
@@ -192,7 +192,7 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
             ready.acquire()
             st, ns, _, _ = srv.wait(tickets[j])
             if st != 0:
-                raise RuntimeError(f"serving request failed with status {st}")
+                raise RuntimeError(f"serving request failed with status {st}: {srv.last_failure()}")
             lat.append(ns * 1e-6)
         dt = time.perf_counter() - t0
         th.join()
@@ -208,7 +208,9 @@ def serving_benchmark(precision: str, n_pool: int, n_sat: int, n_per_rate: int, 
                 f"{r['throughput_req_per_s']:.2f} req/s")
     st = srv.stats()
     res["server_stats"] = {k: v for k, v in st.items()
-                           if k.startswith("peak") or k in ("completed", "failed", "mol_cache_hits")}
+                           if k.startswith("peak") or k in ("completed", "failed", "mol_cache_hits", "batches",
+                                                            "batched_requests", "graphs_instantiated",
+                                                            "graphs_updated", "eager_batches")}
     srv.close()
     return res
 

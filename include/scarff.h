@@ -347,6 +347,8 @@ typedef struct {
     /* batch launches, the requests they carried, and graph executables
      * instantiated / reused with updated parameters */
     long long batches, batched_requests, graphs_instantiated, graphs_updated;
+    /* batches run with eager launches because their graph capture failed */
+    long long eager_batches;
 } scff_server_stats;
 
 /* Create a server on `device`.  A request is prepared (basis, pair
@@ -401,6 +403,11 @@ int scff_server_cancel(scff_server* srv, unsigned long long ticket);
  * totals and summed stage times cover its whole life.  SCFF_EINVAL on a
  * NULL argument.  Thread-safe. */
 int scff_server_stats_get(scff_server* srv, scff_server_stats* out);
+
+/* Message of the most recently failed request ("ticket N: ..."; "" if
+ * none), copied into buf (at most len - 1 characters and a terminating NUL).
+ * SCFF_EINVAL on a NULL argument or len == 0.  Thread-safe. */
+int scff_server_last_failure(scff_server* srv, char* buf, size_t len);
 
 /* Destroy the server: requests not yet running are cancelled, running ones
  * (and their host copies) finish first; then every context, stream and

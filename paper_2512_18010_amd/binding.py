@@ -73,7 +73,8 @@ class scff_server_stats(ctypes.Structure):
                 ("peak_admitted_bytes", c_size_t), ("peak_inflight", c_longlong),
                 ("mol_cache_hits", c_longlong), ("ns_stage", c_longlong * 5),
                 ("batches", c_longlong), ("batched_requests", c_longlong),
-                ("graphs_instantiated", c_longlong), ("graphs_updated", c_longlong)]
+                ("graphs_instantiated", c_longlong), ("graphs_updated", c_longlong),
+                ("eager_batches", c_longlong)]
 
 
 def _fn(name, res, args):
@@ -116,6 +117,7 @@ scff_server_wait = _fn("scff_server_wait", c_int,
                        [c_void_p, c_ulonglong, c_longlong, P(c_int), P(c_longlong)])
 scff_server_cancel = _fn("scff_server_cancel", c_int, [c_void_p, c_ulonglong])
 scff_server_stats_get = _fn("scff_server_stats_get", c_int, [c_void_p, P(scff_server_stats)])
+scff_server_last_failure = _fn("scff_server_last_failure", c_int, [c_void_p, ctypes.c_char_p, c_size_t])
 scff_server_destroy = _fn("scff_server_destroy", None, [c_void_p])
 
 
@@ -423,6 +425,11 @@ class Server:
         d = {k: getattr(st, k) for k, _ in scff_server_stats._fields_}
         d["ns_stage"] = list(d["ns_stage"])
         return d
+
+    def last_failure(self) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        check(scff_server_last_failure(self._h, buf, 1024))
+        return buf.value.decode()
 
     def close(self):
         if getattr(self, "_h", None):

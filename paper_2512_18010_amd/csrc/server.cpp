@@ -134,6 +134,8 @@ struct scff_server {
     size_t staged = 0;                 // device bytes of prepared requests waiting for admission
     long long batches = 0, batched_requests = 0;             // batch launches and the requests in them
     long long graphs_instantiated = 0, graphs_updated = 0;   // graph executables created / reused
+    long long eager_batches = 0;       // batches run without a graph (capture failed)
+    std::string last_failure;          // message of the most recent failed request
 };
 
 namespace {
@@ -251,6 +253,7 @@ void finish(scff_server* s, Req* r, int status) {
         s->ns_stage[4] += ns(r->t_run1, r->t_done);
     } else {
         ++s->n_failed;
+        s->last_failure = "ticket " + std::to_string(r->ticket) + ": " + scff_last_error();
     }
     s->cv_done.notify_all();
 }
@@ -434,7 +437,7 @@ struct Runner {
     void* h_buf = nullptr;     // pinned staging of descriptors and items
     size_t h_cap = 0;
     std::vector<std::pair<std::string, hipGraphExec_t>> execs;   // by topology, most recent last
-    long long graphs_instantiated = 0, graphs_updated = 0;
+    long long graphs_instantiated = 0, graphs_updated = 0, eager_batches = 0;
 };
 
 constexpr size_t kMaxExecs = 32;
@@ -473,9 +476,53 @@ struct Member {
     std::string err;
 };
 
+// Enqueues the batch's device work on R.st (the same calls whether the stream
+// is being captured or not).
+int enqueue_batch(Runner& R, std::vector<Member*>& live, const int off[], size_t need, std::string& err) {
+    const auto* d_desc = (const scff::GridDesc*)R.d_buf;
+    const size_t dbytes = (live.size() * sizeof(scff::GridDesc) + 255) & ~(size_t)255;
+    const auto* d_items = (const int2*)((const char*)R.d_buf + dbytes);
+    hipError_t e = hipMemcpyAsync(R.d_buf, R.h_buf, need, hipMemcpyHostToDevice, R.st);
+    if (e == hipSuccess) e = scff::launch_zero_counters(R.d_cnt, kVariants, R.st);
+    if (e != hipSuccess) {
+        err = std::string("queue upload: ") + hipGetErrorString(e);
+        return SCFF_EDEVICE;
+    }
+    for (Member* m : live)
+        if (scff::ctx_batch_tables(m->r->ctx, &m->r->grid, R.st) != SCFF_OK) {
+            err = scff_last_error();
+            return SCFF_EDEVICE;
+        }
+    const int ncu = scff::ctx_n_cu(live[0]->r->ctx);
+    for (int v = 0; v < kVariants; ++v) {
+        const int n = off[v + 1] - off[v];
+        if (n == 0) continue;
+        const int wgs = std::min(n, ncu * scff::grid_wg_per_cu(v % 2 + 1, v / 2));
+        e = scff::launch_grid_batch(v, d_desc, d_items + off[v], n, R.d_cnt + v, wgs, R.st);
+        if (e != hipSuccess) {
+            err = std::string("batch grid kernel: ") + hipGetErrorString(e);
+            return SCFF_EDEVICE;
+        }
+    }
+    for (Member* m : live) {
+        const size_t np = m->be.nout;
+        float* sf = m->r->f ? (float*)m->stage : nullptr;
+        float* sf2 = m->r->f2 ? (float*)m->stage + 2 * np : nullptr;
+        if (scff::ctx_batch_finish(m->r->ctx, &m->r->grid, m->be, sf, sf2, R.st) != SCFF_OK) {
+            err = scff_last_error();
+            return SCFF_EDEVICE;
+        }
+    }
+    return SCFF_OK;
+}
+
 // Runs the batch's device work; returns SCFF_OK or the error of a launch (then
-// every member that had not failed alone fails with it).
+// every member that had not failed alone fails with it).  The launches are
+// captured into a graph and replayed; if the capture itself fails (another
+// thread's device-wide call can invalidate it), the same launches run
+// eagerly on the stream.
 int run_batch(scff_server* s, Runner& R, std::vector<Member>& ms) {
+    (void)s;
     std::vector<Member*> live;
     for (Member& m : ms)
         if (m.rc == SCFF_OK) live.push_back(&m);
@@ -497,95 +544,76 @@ int run_batch(scff_server* s, Runner& R, std::vector<Member>& ms) {
     for (size_t i = 0; i < live.size(); ++i)
         std::memcpy((char*)R.h_buf + i * sizeof(scff::GridDesc), &live[i]->be.desc, sizeof(scff::GridDesc));
     std::memcpy((char*)R.h_buf + dbytes, items.data(), items.size() * sizeof(int2));
-    const auto* d_desc = (const scff::GridDesc*)R.d_buf;
-    const auto* d_items = (const int2*)((const char*)R.d_buf + dbytes);
     // launch topology: per member its variant, split and outputs; per variant whether it runs
     std::string topo;
     for (Member* m : live)
         topo += std::to_string(m->be.cls) + (m->be.n_split > 1 ? "s" : "u") + (m->r->f ? "f" : "-") +
                 (m->r->f2 ? "g" : "-") + ";";
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return sfail(SCFF_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
-    rc = SCFF_OK;
+    for (int v = 0; v < kVariants; ++v)
+        if (off[v + 1] > off[v]) topo += "k" + std::to_string(v);
     std::string err;
-    auto hip_ok = [&](hipError_t x, const char* what) {
-        if (x != hipSuccess && rc == SCFF_OK) {
-            rc = SCFF_EDEVICE;
-            err = std::string(what) + ": " + hipGetErrorString(x);
-        }
-        return rc == SCFF_OK;
-    };
-    if (hip_ok(hipMemcpyAsync(R.d_buf, R.h_buf, need, hipMemcpyHostToDevice, R.st), "queue upload") &&
-        hip_ok(scff::launch_zero_counters(R.d_cnt, kVariants, R.st), "counter reset")) {
-        for (Member* m : live)
-            if (rc == SCFF_OK && scff::ctx_batch_tables(m->r->ctx, &m->r->grid, R.st) != SCFF_OK) {
-                rc = SCFF_EDEVICE;
-                err = scff_last_error();
-            }
-        const int ncu = scff::ctx_n_cu(live[0]->r->ctx);
-        for (int v = 0; v < kVariants && rc == SCFF_OK; ++v) {
-            const int n = off[v + 1] - off[v];
-            if (n == 0) continue;
-            topo += "k" + std::to_string(v);
-            const int wgs = std::min(n, ncu * scff::grid_wg_per_cu(v % 2 + 1, v / 2));
-            hip_ok(scff::launch_grid_batch(v, d_desc, d_items + off[v], n, R.d_cnt + v, wgs, R.st), "batch grid kernel");
-        }
-        for (Member* m : live) {
-            if (rc != SCFF_OK) break;
-            const size_t np = m->be.nout;
-            float* sf = m->r->f ? (float*)m->stage : nullptr;
-            float* sf2 = m->r->f2 ? (float*)m->stage + 2 * np : nullptr;
-            if (scff::ctx_batch_finish(m->r->ctx, &m->r->grid, m->be, sf, sf2, R.st) != SCFF_OK) {
-                rc = SCFF_EDEVICE;
-                err = scff_last_error();
-            }
-        }
-    }
-    e = hipStreamEndCapture(R.st, &graph);
-    if (rc == SCFF_OK && e != hipSuccess) {
-        rc = SCFF_EDEVICE;
-        err = std::string("stream capture: ") + hipGetErrorString(e);
-    }
-    if (rc != SCFF_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return sfail(rc, err);
-    }
-    // an executable graph of this topology: update it, else instantiate one
-    hipGraphExec_t exec = nullptr;
-    for (size_t i = 0; i < R.execs.size(); ++i)
-        if (R.execs[i].first == topo) {
-            exec = R.execs[i].second;
-            R.execs.erase(R.execs.begin() + (long)i);
-            break;
-        }
-    if (exec) {
-        hipGraphExecUpdateResult res;
-        hipGraphNode_t bad = nullptr;
-        if (hipGraphExecUpdate(exec, graph, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
-            (void)hipGraphExecDestroy(exec);
-            exec = nullptr;
-        } else {
-            ++R.graphs_updated;
-        }
-    }
-    if (!exec) {
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
+    hipGraph_t graph = nullptr;
+    bool captured = false;
+    if (hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        rc = enqueue_batch(R, live, off, need, err);
+        const hipError_t e = hipStreamEndCapture(R.st, &graph);
+        captured = rc == SCFF_OK && e == hipSuccess && graph;
+        if (!captured && graph) {
             (void)hipGraphDestroy(graph);
-            return sfail(SCFF_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(e));
+            graph = nullptr;
         }
-        ++R.graphs_instantiated;
+        (void)hipGetLastError();   // a failed capture leaves its error behind
     }
-    (void)hipGraphDestroy(graph);
-    R.execs.emplace_back(topo, exec);
-    if (R.execs.size() > kMaxExecs) {
-        (void)hipGraphExecDestroy(R.execs.front().second);
-        R.execs.erase(R.execs.begin());
+    hipGraphExec_t exec = nullptr;
+    if (captured) {
+        // an executable graph of this topology: update it, else instantiate one
+        for (size_t i = 0; i < R.execs.size(); ++i)
+            if (R.execs[i].first == topo) {
+                exec = R.execs[i].second;
+                R.execs.erase(R.execs.begin() + (long)i);
+                break;
+            }
+        if (exec) {
+            hipGraphExecUpdateResult res;
+            hipGraphNode_t bad = nullptr;
+            if (hipGraphExecUpdate(exec, graph, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(exec);
+                exec = nullptr;
+            } else {
+                ++R.graphs_updated;
+            }
+        }
+        if (!exec) {
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+                ++R.graphs_instantiated;
+            } else {
+                (void)hipGetLastError();
+                exec = nullptr;
+            }
+        }
+        (void)hipGraphDestroy(graph);
     }
-    e = hipGraphLaunch(exec, R.st);
+    hipError_t e;
+    if (exec) {
+        R.execs.emplace_back(topo, exec);
+        if (R.execs.size() > kMaxExecs) {
+            (void)hipGraphExecDestroy(R.execs.front().second);
+            R.execs.erase(R.execs.begin());
+        }
+        e = hipGraphLaunch(exec, R.st);
+    } else {
+        // no graph (capture or instantiation failed): the same launches, eagerly
+        ++R.eager_batches;
+        err.clear();
+        if ((rc = enqueue_batch(R, live, off, need, err)) != SCFF_OK) {
+            (void)hipStreamSynchronize(R.st);
+            return sfail(rc, err);
+        }
+        e = hipSuccess;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(R.st);
-    if (e != hipSuccess) return sfail(SCFF_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return sfail(SCFF_EDEVICE, std::string("batch: ") + hipGetErrorString(e));
     return SCFF_OK;
 }
 
@@ -648,7 +676,8 @@ void run_loop(scff_server* s) {
         std::unique_lock<std::mutex> lk(s->mu);
         s->graphs_instantiated += R.graphs_instantiated;
         s->graphs_updated += R.graphs_updated;
-        R.graphs_instantiated = R.graphs_updated = 0;
+        s->eager_batches += R.eager_batches;
+        R.graphs_instantiated = R.graphs_updated = R.eager_batches = 0;
         for (Member& m : ms) {
             Req* r = m.r;
             r->t_run1 = Clock::now();
@@ -855,6 +884,16 @@ int scff_server_stats_get(scff_server* s, scff_server_stats* o) {
     o->batched_requests = s->batched_requests;
     o->graphs_instantiated = s->graphs_instantiated;
     o->graphs_updated = s->graphs_updated;
+    o->eager_batches = s->eager_batches;
+    return SCFF_OK;
+}
+
+int scff_server_last_failure(scff_server* s, char* buf, size_t len) {
+    if (!s || !buf || len == 0) return sfail(SCFF_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const size_t n = std::min(len - 1, s->last_failure.size());
+    std::memcpy(buf, s->last_failure.data(), n);
+    buf[n] = '\0';
     return SCFF_OK;
 }
 
