@@ -356,10 +356,12 @@ typedef struct {
  * by one of 8 prep threads, admitted in FIFO order while the device bytes of
  * all admitted requests fit `hbm_budget_bytes` (0 = 64 GiB) and at most
  * `max_inflight` requests are admitted (1..64), and run by one of two batch
- * runners: every admitted request waiting for a runner joins its next batch,
- * whose launches (each request's 1D tables, one persistent grid kernel per
- * kernel variant consuming the (request, tile) items of all its requests
- * from a device queue, split reductions, result copies) are captured into a
+ * runners: the admitted requests waiting for a runner (up to half of
+ * max_inflight, rounded up) join its next batch, so two batches overlap on
+ * the device.  A batch's launches (each request's 1D tables, one persistent
+ * grid kernel per kernel variant consuming the (request, tile) items of all
+ * its requests from a device queue, split reductions, result copies) are
+ * captured into a
  * HIP graph; an executable graph is kept per launch topology (up to 32 per
  * runner) and replayed with the next batch's parameters.  A request's
  * results are identical alone and in any batch.  A request larger than the

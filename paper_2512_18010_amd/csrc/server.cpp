@@ -415,8 +415,8 @@ void sched_loop(scff_server* s) {
     }
 }
 
-// A batch runner: takes every admitted request waiting for it (up to
-// max_inflight), and runs them as one batch on its own stream:
+// A batch runner: takes the admitted requests waiting for it (up to half of
+// max_inflight, rounded up), and runs them as one batch on its own stream:
 //   reserve   each request's device buffers (tables, outputs, split sums)
 //             and its grid-kernel descriptor, nothing launched yet;
 //   capture   into a graph: upload of the descriptors and of the queue of
@@ -631,7 +631,12 @@ void run_loop(scff_server* s) {
             s->cv_run.wait(lk, [&] { return s->stop || !s->run_q.empty(); });
             if (s->stop && s->run_q.empty()) break;
             const auto now = Clock::now();
-            while (!s->run_q.empty() && (int)ms.size() < s->max_inflight) {
+            // at most half the in-flight cap per batch, so that the other
+            // runner always has requests to run beside it: one batch's tail
+            // (last tiles, reductions, result copies) overlaps the other's
+            // grid kernels
+            const int take = std::max(1, (s->max_inflight + kRunners - 1) / kRunners);
+            while (!s->run_q.empty() && (int)ms.size() < take) {
                 Req* r = lookup(s, s->run_q.front());
                 s->run_q.pop_front();
                 if (!r) continue;
