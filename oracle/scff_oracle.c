@@ -45,6 +45,14 @@
  *  5. Omega_{mu nu}(q) = c_mu c_nu sum_{k,l} d_k d_l n_k n_l I_x I_y I_z.
  *  6. f_s(q) = s_f sum_{mu,nu} T^s_{mu nu} Omega_{mu nu}(q); OpenMP over q.
  *
+ * FFT method (Sec. 3, eq. PhiTDM; Sec. 5.2): the transition density on
+ * points, written out from its definition in the AO basis,
+ *     Phi_s(r) = s_f sum_{mu,nu} T^s_{mu nu} phi_mu(r) phi_nu(r),
+ *     phi_mu(r) = c_mu sum_k d_k n_k (x-A_x)^a (y-A_y)^b (z-A_z)^c e^{-alpha_k |r-A|^2}
+ * (App. A primitives with the normalisations of steps 2-3), FP64, no
+ * thresholding; OpenMP over points.  The transform itself is done in the
+ * Python wrapper with a library FFT.
+ *
  * Pins (tests that tie this file to something other than itself) are listed
  * in the test suite: same-centre s/p/d closed forms, 1D and 3D real-space
  * quadrature, the paper's Hermite form, and the invariants f(-q) = f(q)*,
@@ -259,6 +267,79 @@ int scffo_pair_matrix(int n_atoms, const double* xyz, int n_shells, const int* s
             out[((size_t)m * nbf + n) * 2 + 0] = creal(om);
             out[((size_t)m * nbf + n) * 2 + 1] = cimag(om);
         }
+    free(comp);
+    return 0;
+}
+
+/* phi_mu(r) of every component at one point (App. A primitive sum) */
+static void ao_values(const comp_t* comp, int nbf, const double* xyz, const double* exps,
+                      const double* coefs, const double* r, double* phi) {
+    for (int m = 0; m < nbf; ++m) {
+        const double* A = xyz + 3 * comp[m].atom;
+        double d[3], r2 = 0.0, mono = 1.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            d[ax] = r[ax] - A[ax];
+            r2 += d[ax] * d[ax];
+            for (int e = 0; e < comp[m].pw[ax]; ++e) mono *= d[ax];
+        }
+        double rad = 0.0;
+        for (int k = 0; k < comp[m].nprim; ++k) {
+            double a = exps[comp[m].prim_off + k];
+            rad += coefs[comp[m].prim_off + k] * prim_norm(a, comp[m].pw) * exp(-a * r2);
+        }
+        phi[m] = comp[m].c * mono * rad;
+    }
+}
+
+/*
+ * Transition density (FFT method, eq. PhiTDM in the AO basis).  r is
+ * [n_pts][3] (bohr); phi_out is [n_states][n_pts];  T as in scffo_eval.
+ */
+int scffo_density(int n_atoms, const double* xyz, int n_shells, const int* shell_atom,
+                  const int* shell_l, const int* shell_nprim, const double* exps,
+                  const double* coefs, int normalise, int n_states, const double* T, int n_pts,
+                  const double* r, double spin_factor, double* phi_out, int n_threads) {
+    (void)n_atoms;
+    comp_t* comp = NULL;
+    int nbf = build_components(n_shells, shell_atom, shell_l, shell_nprim, exps, coefs,
+                               normalise, &comp);
+    if (nbf < 0) return nbf;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel
+    {
+        double* phi = (double*)malloc(sizeof(double) * (size_t)nbf);
+#pragma omp for schedule(static)
+        for (int ip = 0; ip < n_pts; ++ip) {
+            ao_values(comp, nbf, xyz, exps, coefs, r + 3 * (size_t)ip, phi);
+            for (int s = 0; s < n_states; ++s) {
+                const double* Ts = T + (size_t)s * nbf * nbf;
+                double acc = 0.0;
+                for (int m = 0; m < nbf; ++m)
+                    for (int n = 0; n < nbf; ++n) acc += Ts[(size_t)m * nbf + n] * phi[m] * phi[n];
+                phi_out[(size_t)s * n_pts + ip] = spin_factor * acc;
+            }
+        }
+        free(phi);
+    }
+    free(comp);
+    return 0;
+}
+
+/* phi_mu at each point: out is [n_pts][nbf]. */
+int scffo_ao_values(int n_atoms, const double* xyz, int n_shells, const int* shell_atom,
+                    const int* shell_l, const int* shell_nprim, const double* exps,
+                    const double* coefs, int normalise, int n_pts, const double* r, double* out) {
+    (void)n_atoms;
+    comp_t* comp = NULL;
+    int nbf = build_components(n_shells, shell_atom, shell_l, shell_nprim, exps, coefs,
+                               normalise, &comp);
+    if (nbf < 0) return nbf;
+    for (int ip = 0; ip < n_pts; ++ip)
+        ao_values(comp, nbf, xyz, exps, coefs, r + 3 * (size_t)ip, out + (size_t)ip * nbf);
     free(comp);
     return 0;
 }
