@@ -258,6 +258,46 @@ int scff_export_vtensors(scff_ctx* ctx, const scff_grid* grid, long long* n_term
                          float* vy, float* vz, float* tp);
 
 /*
+ * The FFT method (paper Sec. 3, eqs. PhiTDM, Falbega, continuFFT, fftABC,
+ * qabc; Sec. 5.2; the Parseval check of Sec. 7).  The transition density
+ *     Phi_s(r) = s_f sum_{mu nu} T^s_{mu nu} phi_mu(r) phi_nu(r)
+ * is tabulated on the periodic real-space grid
+ *     x_a = xmin[a] + i_a L[a] / n[a],  i_a = 0 .. n[a]-1,
+ * and Fourier transformed; the result approximates f_s at
+ *     q_a = 2 pi (j_a - n[a]/2) / L[a],  j_a = 0 .. n[a]-1
+ * (most negative frequency first) as
+ *     f_s(q) = V_pix sum_r Phi_s(r) e^{+i q.r},  V_pix = prod_a L[a] / n[a],
+ * which converges to the exact form factor as the box grows and the spacing
+ * shrinks (the method's discretisation is the caller's choice: the paper
+ * takes x_lim = pi / dq and dx = 2 pi / q_lim).
+ *   grid       n[a] powers of two in 1..1024; L[a] > 0 (bohr)
+ *   f          complex64 [n_states][n0][n1][n2] interleaved, or NULL
+ *   f2         |f|^2, float [n_states][n0][n1][n2], or NULL
+ *   phi        the transition density Phi_s, float [n_states][n0][n1][n2], or NULL
+ *   parseval   host double [n_states][2]: (sum_r |Phi_s|^2 V_pix,
+ *              sum_q |f_s|^2 dq^3 / (2 pi)^3), equal by Parseval's identity
+ *              up to rounding; or NULL
+ * f, f2 and phi are host buffers (out_on_device = 0, the call returns when
+ * they are written) or device buffers (out_on_device = 1, asynchronous on
+ * hip_stream unless parseval is requested, which waits for the stream).
+ * The density is FP32 (AO values built in FP64 and rounded once, weights
+ * contracted on the matrix cores with FP64 sums over each 16 functions),
+ * the transform FP32 radix-2, the corner phase FP64.  The context's
+ * screening threshold is not applied (primitives below the FP32 range are
+ * skipped); the spin factor is.  Basis size: up to about 1000 functions.
+ * SCFF_EINVAL for bad sizes, no output or a basis too large, SCFF_ESTATE
+ * before a molecule and transitions are loaded, SCFF_ENOMEM over the budget.
+ */
+typedef struct {
+    int n[3];
+    double xmin[3];   /* corner of the box, bohr */
+    double L[3];      /* box lengths, bohr */
+} scff_fft_grid;
+
+int scff_eval_fft(scff_ctx* ctx, const scff_fft_grid* grid, float* f, float* f2, float* phi, double* parseval,
+                  int out_on_device, void* hip_stream);
+
+/*
  * Separable integral (paper Sec. 5.3: integrals of the form
  * I = int d^3q f(q_x) g(q_y) h(q_z) f_S(q), evaluated from the 1D V-tensors
  * with a cost linear in the axis sizes instead of their product):

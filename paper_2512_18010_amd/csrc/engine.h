@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <functional>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -160,7 +161,45 @@ constexpr size_t kScratchBytes = (size_t)256 << 20;
 // Device address of this device's array (device current; resolved once).
 hipError_t scratch_address(int device, void** ptr);
 
+// ---- FFT method (fft.hip) ----
+// Molecule tables the transition-density kernel reads (device pointers).
+struct FftMol {
+    const PrepShell* shells;
+    const int* bf0;
+    const double* xyz;
+    const double* exps;
+    const double* coefs;
+    const double* n1d;
+    const double* cnorm;
+    int n_shells;
+};
+// LDS a density workgroup may hold: two workgroups per CU.
+constexpr size_t kFftLdsBytes = (size_t)78 << 10;
+// Grid points per density workgroup (64, 32 or 16) for nbf_pad basis rows
+// within lds_limit bytes of LDS; 0 if even 16 do not fit.
+int fft_points_per_tile(int nbf_pad, size_t lds_limit);
+hipError_t launch_fft_pack(const double* T, const double* cnorm, int nbf, int ns, int RB, int KS, double spin,
+                           float* Ap, hipStream_t st);
+hipError_t launch_fft_density(const FftMol& m, const float* Ap, int nbf_pad, int ns, int RB, int KS, const int n[3],
+                              const double x0[3], const double h[3], float* Z, float* phi, double* psum,
+                              size_t lds_limit, long long* n_part, hipStream_t st);
+hipError_t launch_fft_lines(float2* Z, int nb, const int n[3], hipStream_t st);
+hipError_t launch_fft_finish(const float2* Z, const int n[3], int ns, double vpix, const double u[3], float2* f,
+                             float* f2, double* psum, long long* n_part, hipStream_t st);
+hipError_t launch_fft_sum(const double* part, int ns, long long n, double scale, double* out, int stride,
+                          hipStream_t st);
+
 // ---- runtime.cpp ----
+// Gate between stream capture and device-wide runtime calls.  Allocation and
+// release of device or pinned memory, event and stream creation and
+// destruction, and device synchronisation take it shared; a thread that
+// captures a stream into a graph holds it exclusively from the start to the
+// end of the capture, so no such call (which the runtime may let touch or
+// synchronise every stream, the capturing one included) runs meanwhile.
+// Hold it only around the runtime call itself, never across another gated
+// call.
+std::shared_mutex& device_gate();
+using GateShared = std::shared_lock<std::shared_mutex>;
 // Thread-local message returned by scff_last_error().
 void set_error(const std::string& msg);
 // Pack and upload a context's problem for grid g on stream st and wait for

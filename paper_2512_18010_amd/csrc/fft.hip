@@ -1,0 +1,432 @@
+// The FFT method (paper Sec. 3 and Sec. 5.2) on the device:
+//
+//   1. fft_pack_kernel      transition weights as MFMA A operands:
+//                           s_f c_mu c_nu (T_{mu nu} + T_{nu mu}) per unordered
+//                           component pair (T_{mu mu} on the diagonal);
+//   2. fft_density_kernel   the transition density (eq. PhiTDM, AO form)
+//                             Phi_s(r) = sum_mu phi_mu(r) sum_{nu >= mu} Tp_s(mu,nu) phi_nu(r)
+//                           on a tile of real-space points: the AO values of
+//                           the tile are formed in LDS (FP64, rounded once),
+//                           Y_s(mu, r) = sum_nu Tp_s(mu,nu) phi_nu(r) runs on
+//                           the matrix cores (v_mfma_f32_16x16x4_f32; rows
+//                           mu of one state, k = nu, columns = points), and
+//                           sum_mu phi_mu Y_s(mu) is folded into FP64 per
+//                           16 rows.  Two states share one complex array
+//                           (Phi_2b + i Phi_2b+1), so each FFT carries two.
+//   3. fft_lines_kernel     radix-2 transforms of all lines of one axis of the
+//                           complex arrays, a line group staged in LDS (eq.
+//                           Falbega as three 1D passes);
+//   4. fft_finish_kernel    separates the two states of each array
+//                           (F_a = (Z_k + Z*_{-k})/2, F_b = (Z_k - Z*_{-k})/2i),
+//                           orders the frequencies most negative first and
+//                           applies the pixel volume and the corner phase:
+//                           f_s(q) = V_pix e^{+i q.x_min} conj(F_s) (eq.
+//                           fftABC for the conjugate array, eq. qabc);
+//   5. fft_sum_kernel       the two sides of Parseval's identity (Sec. 7) from
+//                           per-wave FP64 partial sums, in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "engine.h"
+
+namespace scff {
+
+typedef float fft_floatx4 __attribute__((ext_vector_type(4)));
+
+// Primitives whose exponent argument alpha r^2 exceeds this are skipped (the
+// paper's thresholding of negligible primitives): e^{-103} is below the
+// smallest FP32 subnormal, so the rounded AO value is unchanged.
+constexpr double kExpCut = 103.0;
+
+namespace {
+
+__global__ void fft_pack_kernel(const double* __restrict__ T, const double* __restrict__ cnorm, int nbf, int ns,
+                                int RB, int KS, double spin, float* __restrict__ Ap) {
+    const long long total = (long long)ns * RB * KS * 64;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int lane = (int)(i & 63);
+        long long r = i >> 6;
+        const int ks = (int)(r % KS);
+        r /= KS;
+        const int rb = (int)(r % RB);
+        const int s = (int)(r / RB);
+        const int mu = 16 * rb + (lane & 15), nu = 4 * ks + (lane >> 4);
+        double v = 0.0;
+        if (mu < nbf && nu < nbf && mu <= nu) {
+            const double* Ts = T + (size_t)s * nbf * nbf;
+            const double t = mu == nu ? Ts[(size_t)mu * nbf + mu] : Ts[(size_t)mu * nbf + nu] + Ts[(size_t)nu * nbf + mu];
+            v = spin * cnorm[mu] * cnorm[nu] * t;
+        }
+        Ap[i] = (float)v;
+    }
+}
+
+// AO values of one shell at one point, FP64, rounded to FP32 into
+// ph[(bf0 + c) * NP + p] for each Cartesian component c.
+__device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, double y, double z, float* ph, int NP,
+                                             int p) {
+    const PrepShell S = m.shells[sh];
+    const double* A = m.xyz + 3 * S.atom;
+    const double dx = x - A[0], dy = y - A[1], dz = z - A[2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    // radial sums: sum_k d_k (product of 1D norms for the power pattern) e^{-alpha_k r^2}
+    double ra = 0.0, rb = 0.0;   // l = 2: ra for xx-type, rb for xy-type; l < 2: ra only
+    for (int k = 0; k < S.nprim; ++k) {
+        const int o = S.off + k;
+        const double ar = m.exps[o] * r2;
+        if (ar > kExpCut) continue;
+        const double e = m.coefs[o] * exp(-ar);
+        const double n0 = m.n1d[3 * o], n1 = m.n1d[3 * o + 1], n2 = m.n1d[3 * o + 2];
+        if (S.l == 0) {
+            ra += e * n0 * n0 * n0;
+        } else if (S.l == 1) {
+            ra += e * n1 * n0 * n0;
+        } else {
+            ra += e * n2 * n0 * n0;
+            rb += e * n1 * n1 * n0;
+        }
+    }
+    const int b0 = m.bf0[sh];
+    const double* cn = m.cnorm + b0;
+    float* o = ph + (size_t)b0 * NP + p;
+    if (S.l == 0) {
+        o[0] = (float)(cn[0] * ra);
+    } else if (S.l == 1) {
+        o[0] = (float)(cn[0] * dx * ra);
+        o[NP] = (float)(cn[1] * dy * ra);
+        o[2 * NP] = (float)(cn[2] * dz * ra);
+    } else {
+        o[0] = (float)(cn[0] * dx * dx * ra);
+        o[NP] = (float)(cn[1] * dx * dy * rb);
+        o[2 * NP] = (float)(cn[2] * dx * dz * rb);
+        o[3 * NP] = (float)(cn[3] * dy * dy * ra);
+        o[4 * NP] = (float)(cn[4] * dy * dz * rb);
+        o[5 * NP] = (float)(cn[5] * dz * dz * ra);
+    }
+}
+
+// One workgroup (4 waves) per tile of NP = 16 NPB consecutive grid points
+// (flattened [ix][iy][iz], z fastest).  Wave w works on point block
+// pb = w % NPB and on the row blocks rb = w / NPB (mod 4 / NPB); the row
+// groups of a point block are summed through LDS at the end of each state.
+// LDS: phi[nbf_pad][NP] FP32, then 4 x 16 FP64 for that sum.
+template <int NPB>
+__global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const float* __restrict__ Ap, int nbf_pad, int ns,
+                                                          int RB, int KS, int3 n, double3 x0, double3 h,
+                                                          long long npts, float* __restrict__ Z,
+                                                          float* __restrict__ phi_out, double* __restrict__ psum) {
+    extern __shared__ __align__(16) float fft_lds[];
+    constexpr int NP = 16 * NPB;
+    constexpr int WR = 4 / NPB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long p0 = (long long)blockIdx.x * NP;
+    float* ph = fft_lds;
+    double* red = reinterpret_cast<double*>(fft_lds + (size_t)nbf_pad * NP);
+
+    for (int i = tid; i < nbf_pad * NP; i += 256) ph[i] = 0.f;
+    __syncthreads();
+    for (int item = tid; item < m.n_shells * NP; item += 256) {
+        const int sh = item / NP, p = item - sh * NP;
+        const long long g = p0 + p;
+        if (g >= npts) continue;
+        const int iz = (int)(g % n.z);
+        const long long r1 = g / n.z;
+        const int iy = (int)(r1 % n.y), ix = (int)(r1 / n.y);
+        shell_values(m, sh, x0.x + ix * h.x, x0.y + iy * h.y, x0.z + iz * h.z, ph, NP, p);
+    }
+    __syncthreads();
+
+    const int pb = wave % NPB, rg = wave / NPB;
+    const int kk = lane >> 4, col = lane & 15;
+    const float* phc = ph + pb * 16 + col;   // phi[row][pb*16 + col] = phc[row * NP]
+    const long long g = p0 + pb * 16 + col;
+    const bool valid = g < npts;
+    for (int s = 0; s < ns; ++s) {
+        double acc = 0.0;
+        for (int rb = rg; rb < RB; rb += WR) {
+            fft_floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+            const float* ap = Ap + (size_t)(s * RB + rb) * KS * 64 + lane;
+            int ks = 4 * rb;
+            for (; ks + 1 < KS; ks += 2) {
+                const float a0 = ap[(size_t)ks * 64], a1 = ap[(size_t)(ks + 1) * 64];
+                const float b0 = phc[(4 * ks + kk) * NP], b1 = phc[(4 * ks + 4 + kk) * NP];
+                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, c1, 0, 0, 0);
+            }
+            if (ks < KS) {
+                const float a0 = ap[(size_t)ks * 64];
+                const float b0 = phc[(4 * ks + kk) * NP];
+                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c0, 0, 0, 0);
+            }
+            // lane (kk, col) holds rows 4 kk + i of column col
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                acc += (double)phc[(16 * rb + 4 * kk + i) * NP] * ((double)c0[i] + (double)c1[i]);
+        }
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        if constexpr (WR > 1) {
+            if (lane < 16) red[wave * 16 + lane] = acc;
+            __syncthreads();
+            if (rg == 0)
+                for (int w = 1; w < WR; ++w) acc += red[(pb + w * NPB) * 16 + col];
+            __syncthreads();
+        }
+        if (rg == 0) {
+            if (valid && lane < 16) {
+                const float v = (float)acc;
+                float* zp = Z + ((size_t)(s >> 1) * npts + g) * 2;
+                zp[s & 1] = v;
+                if ((ns & 1) && s == ns - 1) zp[1] = 0.f;
+                if (phi_out) phi_out[(size_t)s * npts + g] = v;
+            }
+            double q = valid ? acc * acc : 0.0;
+            q += __shfl_xor(q, 1);
+            q += __shfl_xor(q, 2);
+            q += __shfl_xor(q, 4);
+            q += __shfl_xor(q, 8);
+            if (psum && lane == 0) psum[(size_t)s * gridDim.x * NPB + (size_t)blockIdx.x * NPB + pb] = q;
+        }
+    }
+}
+
+// Lines of one axis of the complex arrays Z[nb][nx][ny][nz]: a workgroup
+// transforms M lines of length N in LDS (radix-2, decimation in time on
+// bit-reversed input), with twiddles e^{-2 pi i k / N} built in FP64 and
+// rounded.  Along z the M lines are consecutive rows; along y and x they are
+// M consecutive z, so every load and store touches contiguous runs.
+__global__ __launch_bounds__(256) void fft_lines_kernel(float2* __restrict__ Z, int axis, int3 n, int nb, int M,
+                                                        long long lines) {
+    extern __shared__ __align__(16) float fft_lds[];
+    const int N = axis == 0 ? n.x : axis == 1 ? n.y : n.z;
+    const int logN = 31 - __clz(N);
+    float2* buf = reinterpret_cast<float2*>(fft_lds);
+    float2* tw = buf + (size_t)M * N;
+    for (int k = threadIdx.x; k < N / 2; k += blockDim.x) {
+        double sn, cs;
+        sincospi(-2.0 * k / N, &sn, &cs);
+        tw[k] = make_float2((float)cs, (float)sn);
+    }
+    const long long plane = (long long)n.y * n.z, vol = (long long)n.x * plane;
+    const long long gidx = blockIdx.x;
+    long long base, es, ls;
+    int mcount = M;
+    if (axis == 2) {
+        base = gidx * M * N;
+        es = 1;
+        ls = N;
+        const long long left = lines - gidx * M;
+        if (left < M) mcount = (int)left;
+    } else {
+        const int zb = n.z / M;
+        const int z0 = (int)(gidx % zb) * M;
+        const long long r = gidx / zb;
+        if (axis == 1) {
+            const int x = (int)(r % n.x);
+            const long long b = r / n.x;
+            base = b * vol + (long long)x * plane + z0;
+            es = n.z;
+        } else {
+            const int y = (int)(r % n.y);
+            const long long b = r / n.y;
+            base = b * vol + (long long)y * n.z + z0;
+            es = plane;
+        }
+        ls = 1;
+    }
+    (void)nb;
+    const int tot = mcount * N;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        int mm, k;
+        if (axis == 2) {
+            mm = i / N;
+            k = i - mm * N;
+        } else {
+            k = i / mcount;
+            mm = i - k * mcount;
+        }
+        const float2 v = Z[base + mm * ls + k * es];
+        buf[mm * N + (int)(__brev((unsigned)k) >> (32 - logN))] = v;
+    }
+    __syncthreads();
+    const int hN = N / 2;
+    for (int len = 2; len <= N; len <<= 1) {
+        const int half = len >> 1, tstep = N / len;
+        for (int j = threadIdx.x; j < mcount * hN; j += blockDim.x) {
+            const int mm = j / hN, r = j - mm * hN;
+            const int grp = r / half, pos = r - grp * half;
+            const int i0 = mm * N + grp * len + pos, i1 = i0 + half;
+            const float2 w = tw[pos * tstep];
+            const float2 a = buf[i0], b = buf[i1];
+            const float tr = w.x * b.x - w.y * b.y, ti = w.x * b.y + w.y * b.x;
+            buf[i0] = make_float2(a.x + tr, a.y + ti);
+            buf[i1] = make_float2(a.x - tr, a.y - ti);
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        int mm, k;
+        if (axis == 2) {
+            mm = i / N;
+            k = i - mm * N;
+        } else {
+            k = i / mcount;
+            mm = i - k * mcount;
+        }
+        Z[base + mm * ls + k * es] = buf[mm * N + k];
+    }
+}
+
+// One thread per output point (i, j, k) of every state: q_a = 2 pi (i_a - n_a/2) / L_a.
+__global__ __launch_bounds__(256) void fft_finish_kernel(const float2* __restrict__ Z, int3 n, int ns, double vpix,
+                                                         double3 u, long long npts, float2* __restrict__ f,
+                                                         float* __restrict__ f2, double* __restrict__ psum) {
+    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool valid = idx < npts;
+    const int lane = threadIdx.x & 63;
+    const long long wv = idx >> 6;   // global wave index
+    const long long nwv = (npts + 63) >> 6;
+    long long src = 0, mir = 0;
+    double cs = 1.0, sn = 0.0;
+    if (valid) {
+        const int k = (int)(idx % n.z);
+        const long long r1 = idx / n.z;
+        const int j = (int)(r1 % n.y), i = (int)(r1 / n.y);
+        const int ai = i - n.x / 2, aj = j - n.y / 2, ak = k - n.z / 2;
+        const int si = (i + n.x / 2) & (n.x - 1), sj = (j + n.y / 2) & (n.y - 1), sk = (k + n.z / 2) & (n.z - 1);
+        const int mi = (n.x - si) & (n.x - 1), mj = (n.y - sj) & (n.y - 1), mk = (n.z - sk) & (n.z - 1);
+        src = ((long long)si * n.y + sj) * n.z + sk;
+        mir = ((long long)mi * n.y + mj) * n.z + mk;
+        // q.x_min / (2 pi) in turns, reduced to [-1/2, 1/2], in FP64
+        double t = ai * u.x + aj * u.y + ak * u.z;
+        t -= rint(t);
+        sincospi(2.0 * t, &sn, &cs);
+    }
+    for (int s = 0; s < ns; ++s) {
+        double a2 = 0.0;
+        if (valid) {
+            const float2 zs = Z[(size_t)(s >> 1) * npts + src];
+            const float2 zm = Z[(size_t)(s >> 1) * npts + mir];
+            double fr, fi;   // F_s
+            if ((s & 1) == 0) {
+                fr = 0.5 * ((double)zs.x + (double)zm.x);
+                fi = 0.5 * ((double)zs.y - (double)zm.y);
+            } else {
+                fr = 0.5 * ((double)zs.y + (double)zm.y);
+                fi = -0.5 * ((double)zs.x - (double)zm.x);
+            }
+            // f = V_pix e^{i theta} conj(F)
+            const double vr = vpix * (cs * fr + sn * fi), vi = vpix * (sn * fr - cs * fi);
+            a2 = vr * vr + vi * vi;
+            const size_t o = (size_t)s * npts + idx;
+            if (f) f[o] = make_float2((float)vr, (float)vi);
+            if (f2) f2[o] = (float)a2;
+        }
+        if (psum) {
+            for (int d = 1; d < 64; d <<= 1) a2 += __shfl_xor(a2, d);
+            if (lane == 0 && wv < nwv) psum[(size_t)s * nwv + wv] = a2;
+        }
+    }
+}
+
+// out[s * stride] = sum of part[s][0..n) in a fixed order (one workgroup per state).
+__global__ __launch_bounds__(256) void fft_sum_kernel(const double* __restrict__ part, long long n, double scale,
+                                                      double* __restrict__ out, int stride) {
+    __shared__ double sm[256];
+    const int s = blockIdx.x;
+    double a = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256) a += part[(size_t)s * n + i];
+    sm[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(size_t)s * stride] = scale * sm[0];
+}
+
+}  // namespace
+
+int fft_points_per_tile(int nbf_pad, size_t lds_limit) {
+    const size_t extra = 4 * 16 * sizeof(double);
+    for (int np = 64; np >= 16; np /= 2)
+        if ((size_t)nbf_pad * np * sizeof(float) + extra <= lds_limit) return np;
+    return 0;
+}
+
+hipError_t launch_fft_pack(const double* T, const double* cnorm, int nbf, int ns, int RB, int KS, double spin,
+                           float* Ap, hipStream_t st) {
+    const long long total = (long long)ns * RB * KS * 64;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(fft_pack_kernel, dim3(blocks), dim3(256), 0, st, T, cnorm, nbf, ns, RB, KS, spin, Ap);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_density(const FftMol& m, const float* Ap, int nbf_pad, int ns, int RB, int KS, const int n[3],
+                              const double x0[3], const double h[3], float* Z, float* phi, double* psum,
+                              size_t lds_limit, long long* n_part, hipStream_t st) {
+    const long long npts = (long long)n[0] * n[1] * n[2];
+    const int NP = fft_points_per_tile(nbf_pad, lds_limit);
+    if (NP == 0) return hipErrorInvalidValue;
+    const long long tiles = (npts + NP - 1) / NP;
+    if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = (size_t)nbf_pad * NP * sizeof(float) + 4 * 16 * sizeof(double);
+    const int3 nn = make_int3(n[0], n[1], n[2]);
+    const double3 xx = make_double3(x0[0], x0[1], x0[2]), hh = make_double3(h[0], h[1], h[2]);
+    *n_part = tiles * (NP / 16);
+    if (NP == 64)
+        hipLaunchKernelGGL(fft_density_kernel<4>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB,
+                           KS, nn, xx, hh, npts, Z, phi, psum);
+    else if (NP == 32)
+        hipLaunchKernelGGL(fft_density_kernel<2>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB,
+                           KS, nn, xx, hh, npts, Z, phi, psum);
+    else
+        hipLaunchKernelGGL(fft_density_kernel<1>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB,
+                           KS, nn, xx, hh, npts, Z, phi, psum);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_lines(float2* Z, int nb, const int n[3], hipStream_t st) {
+    const int3 nn = make_int3(n[0], n[1], n[2]);
+    for (int axis = 2; axis >= 0; --axis) {
+        const int N = n[axis];
+        if (N < 2) continue;
+        long long lines;
+        int M;
+        long long groups;
+        if (axis == 2) {
+            lines = (long long)nb * n[0] * n[1];
+            M = std::max(1, 4096 / N);
+            groups = (lines + M - 1) / M;
+        } else {
+            M = std::min(std::min(16, n[2]), std::max(1, 4096 / N));
+            lines = (long long)nb * n[0] * n[1] * n[2] / N;
+            groups = lines / M;
+        }
+        if (groups > 0x7fffffffLL) return hipErrorInvalidValue;
+        const size_t lds = ((size_t)M * N + N / 2) * sizeof(float2);
+        hipLaunchKernelGGL(fft_lines_kernel, dim3((unsigned)groups), dim3(256), lds, st, Z, axis, nn, nb, M, lines);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fft_finish(const float2* Z, const int n[3], int ns, double vpix, const double u[3], float2* f,
+                             float* f2, double* psum, long long* n_part, hipStream_t st) {
+    const long long npts = (long long)n[0] * n[1] * n[2];
+    const long long blocks = (npts + 255) / 256;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    *n_part = (npts + 63) / 64;
+    hipLaunchKernelGGL(fft_finish_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Z, make_int3(n[0], n[1], n[2]),
+                       ns, vpix, make_double3(u[0], u[1], u[2]), npts, f, f2, psum);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_sum(const double* part, int ns, long long n, double scale, double* out, int stride,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(fft_sum_kernel, dim3(ns), dim3(256), 0, st, part, n, scale, out, stride);
+    return hipGetLastError();
+}
+
+}  // namespace scff

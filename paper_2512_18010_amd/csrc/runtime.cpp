@@ -54,6 +54,11 @@ thread_local std::string g_err;
 
 void scff::set_error(const std::string& msg) { g_err = msg; }
 
+std::shared_mutex& scff::device_gate() {
+    static std::shared_mutex m;
+    return m;
+}
+
 // Timing events: precompute start/end, 1D tables start, grid kernel start/end.
 enum { EV_PREP0, EV_PREP1, EV_VT0, EV_GRID0, EV_GRID1, EV_N };
 
@@ -100,6 +105,10 @@ struct scff_ctx {
     // FP64 low-momentum and separable work: weights / points, per-row and
     // per-pair values, per-state results
     DeviceBuffer d_lq_in, d_lq_S, d_lq_G, d_lq_out;
+    // FFT method: packed weights, complex arrays of state pairs, partial
+    // sums, Parseval sums, device copy of the density for host output
+    DeviceBuffer d_fft_A, d_fft_Z, d_fft_part, d_fft_out, d_phi;
+    size_t lds_block = 65536;   // LDS bytes one workgroup may use
     void* scratch = nullptr;   // this device's static scratch array (scff_eval_grid_noalloc)
 };
 
@@ -117,7 +126,10 @@ int ok() {
 
 void dev_free(scff_ctx* c, DeviceBuffer& b) {
     if (b.p) {
-        (void)hipFree(b.p);
+        {
+            GateShared g(device_gate());
+            (void)hipFree(b.p);
+        }
         c->used -= b.bytes;
     }
     b.p = nullptr;
@@ -132,7 +144,11 @@ hipError_t dev_reserve_raw(scff_ctx* c, DeviceBuffer& b, size_t bytes) {
     if (c->budget && c->used - old + bytes > c->budget) return hipErrorOutOfMemory;
     dev_free(c, b);
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e;
+    {
+        GateShared g(device_gate());
+        e = hipMalloc(&p, bytes);
+    }
     if (e != hipSuccess) return e;
     b.p = p;
     b.bytes = bytes;
@@ -158,7 +174,10 @@ int hip_check(hipError_t e, const char* what) {
 int upload_sync(scff_ctx* c, DeviceBuffer& b, const void* src, size_t bytes) {
     int rc = dev_reserve(c, b, bytes);
     if (rc) return rc;
-    if (bytes) return hip_check(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice), "upload");
+    if (bytes) {
+        GateShared g(device_gate());
+        return hip_check(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice), "upload");
+    }
     return SCFF_OK;
 }
 
@@ -175,9 +194,11 @@ int order_after(scff_ctx* c, hipStream_t st) {
 }
 int order_mark(scff_ctx* c, hipStream_t st) {
     int rc;
-    if (!c->order_ev &&
-        (rc = hip_check(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming), "event create")))
-        return rc;
+    if (!c->order_ev) {
+        GateShared g(device_gate());
+        if ((rc = hip_check(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming), "event create")))
+            return rc;
+    }
     if ((rc = hip_check(hipEventRecord(c->order_ev, st), "event record"))) return rc;
     c->order_st = st;
     c->order_pending = true;
@@ -405,7 +426,8 @@ int check_precision(int precision) {
 
 void free_all(scff_ctx* c) {
     for (DeviceBuffer* b : {&c->d_mol, &c->d_T, &c->d_vtab, &c->d_part, &c->d_f, &c->d_f2, &c->d_q,
-                            &c->d_lq_in, &c->d_lq_S, &c->d_lq_G, &c->d_lq_out})
+                            &c->d_lq_in, &c->d_lq_S, &c->d_lq_G, &c->d_lq_out, &c->d_fft_A, &c->d_fft_Z,
+                            &c->d_fft_part, &c->d_fft_out, &c->d_phi})
         dev_free(c, *b);
     PrepWork& w = c->prep;
     for (DeviceBuffer* b : {&w.rows_all, &w.rowsum, &w.trow, &w.tbound, &w.wt, &w.cpmn, &w.tp64, &w.bsum,
@@ -540,8 +562,12 @@ int scff_create(int device, size_t hbm_budget_bytes, scff_ctx** out) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->n_cu = ncu;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->lds_block = (size_t)lds;
     // pinned staging of small readbacks and uploads; without it (allocation
     // refused) the same copies go through pageable memory
+    GateShared g(device_gate());
     if (hipHostMalloc(&c->prep.pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) c->prep.pinned = nullptr;
     c->budget = hbm_budget_bytes;
     const char* v = std::getenv("SCFF_VALIDATE");
@@ -559,12 +585,18 @@ void scff_destroy(scff_ctx* c) {
     (void)hipSetDevice(c->device);
     // wait for this context's own device work only (other contexts keep
     // running); after a call that failed half-way, for the whole device
-    if (c->async_open || order_drain(c) != SCFF_OK) (void)hipDeviceSynchronize();
+    if (c->async_open || order_drain(c) != SCFF_OK) {
+        GateShared g(device_gate());
+        (void)hipDeviceSynchronize();
+    }
     free_all(c);
-    for (hipEvent_t& e : c->ev)
-        if (e) (void)hipEventDestroy(e);
-    if (c->order_ev) (void)hipEventDestroy(c->order_ev);
-    if (c->prep.pinned) (void)hipHostFree(c->prep.pinned);
+    {
+        GateShared g(device_gate());
+        for (hipEvent_t& e : c->ev)
+            if (e) (void)hipEventDestroy(e);
+        if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+        if (c->prep.pinned) (void)hipHostFree(c->prep.pinned);
+    }
     delete c;
 }
 
@@ -803,9 +835,11 @@ int scff_set_timing(scff_ctx* c, int enable) {
     if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
     int rc;
     if ((rc = set_device(c))) return rc;
-    if (enable && !c->ev[0])
+    if (enable && !c->ev[0]) {
+        GateShared g(device_gate());
         for (hipEvent_t& e : c->ev)
             if ((rc = hip_check(hipEventCreate(&e), "hipEventCreate"))) return rc;
+    }
     c->timing = enable != 0;
     c->ev_recorded = false;
     return ok();
@@ -972,6 +1006,112 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 }
 
 }  // namespace
+
+int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, float* phi, double* parseval,
+                  int out_on_device, void* hip_stream) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (!g) return fail(SCFF_EINVAL, "grid is NULL");
+    for (int a = 0; a < 3; ++a) {
+        const int na = g->n[a];
+        if (na < 1 || na > 1024 || (na & (na - 1)))
+            return fail(SCFF_EINVAL, "FFT grid sizes must be powers of two in 1..1024");
+        if (!std::isfinite(g->xmin[a]) || !std::isfinite(g->L[a]) || !(g->L[a] > 0.0))
+            return fail(SCFF_EINVAL, "FFT box corner must be finite and its lengths positive");
+    }
+    if (!f && !f2 && !phi && !parseval) return fail(SCFF_EINVAL, "no output requested");
+    if (!c->have_mol) return fail(SCFF_ESTATE, "no molecule loaded");
+    if (!c->have_T) return fail(SCFF_ESTATE, "no transitions loaded");
+    const int nbf = c->basis.nbf, ns = c->n_states;
+    const int nbf_pad = (nbf + 15) & ~15;
+    const size_t lds_limit = std::min(c->lds_block, kFftLdsBytes);
+    if (fft_points_per_tile(nbf_pad, lds_limit) == 0)
+        return fail(SCFF_EINVAL, "basis too large for the FFT method's density tile (" + std::to_string(nbf) +
+                                     " functions)");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((rc = order_after(c, st))) return rc;
+    const int RB = nbf_pad / 16, KS = nbf_pad / 4, nb = (ns + 1) / 2;
+    const long long npts = (long long)g->n[0] * g->n[1] * g->n[2];
+    const size_t nout = (size_t)npts * ns;
+    const int NP = fft_points_per_tile(nbf_pad, lds_limit);
+    const long long part_d = (npts + NP - 1) / NP * (NP / 16), part_f = (npts + 63) / 64;
+    if ((rc = dev_reserve(c, c->d_fft_A, (size_t)ns * RB * KS * 64 * sizeof(float))) ||
+        (rc = dev_reserve(c, c->d_fft_Z, (size_t)nb * npts * sizeof(float2))))
+        return rc;
+    if (parseval &&
+        ((rc = dev_reserve(c, c->d_fft_part, (size_t)ns * (size_t)std::max(part_d, part_f) * sizeof(double))) ||
+         (rc = dev_reserve(c, c->d_fft_out, (size_t)ns * 2 * sizeof(double)))))
+        return rc;
+    float2* df = (float2*)f;
+    float* df2 = f2;
+    float* dphi = phi;
+    if (!out_on_device) {
+        if (f && (rc = dev_reserve(c, c->d_f, nout * sizeof(float2)))) return rc;
+        if (f2 && (rc = dev_reserve(c, c->d_f2, nout * sizeof(float)))) return rc;
+        if (phi && (rc = dev_reserve(c, c->d_phi, nout * sizeof(float)))) return rc;
+        df = f ? (float2*)c->d_f.p : nullptr;
+        df2 = f2 ? (float*)c->d_f2.p : nullptr;
+        dphi = phi ? (float*)c->d_phi.p : nullptr;
+    }
+    const unsigned char* mb = (const unsigned char*)c->d_mol.p;
+    FftMol m;
+    m.shells = (const PrepShell*)(mb + c->mol_off[0]);
+    m.bf0 = (const int*)(mb + c->mol_off[3]);
+    m.xyz = (const double*)(mb + c->mol_off[6]);
+    m.exps = (const double*)(mb + c->mol_off[7]);
+    m.coefs = (const double*)(mb + c->mol_off[8]);
+    m.n1d = (const double*)(mb + c->mol_off[9]);
+    m.cnorm = (const double*)(mb + c->mol_off[10]);
+    m.n_shells = c->basis.n_shells;
+    double h[3], u[3], vpix = 1.0, dq3 = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        h[a] = g->L[a] / g->n[a];
+        u[a] = g->xmin[a] / g->L[a];
+        vpix *= h[a];
+        dq3 *= 2.0 * M_PI / g->L[a];
+    }
+    double* part = parseval ? (double*)c->d_fft_part.p : nullptr;
+    double* pout = parseval ? (double*)c->d_fft_out.p : nullptr;
+    long long np_d = 0, np_f = 0;
+    if ((rc = hip_check(launch_fft_pack((const double*)c->d_T.p, m.cnorm, nbf, ns, RB, KS, c->spin,
+                                       (float*)c->d_fft_A.p, st),
+                        "FFT weight packing")) ||
+        (rc = hip_check(launch_fft_density(m, (const float*)c->d_fft_A.p, nbf_pad, ns, RB, KS, g->n, g->xmin, h,
+                                           (float*)c->d_fft_Z.p, dphi, part, lds_limit, &np_d, st),
+                        "transition density kernel")))
+        return rc;
+    if (parseval && (rc = hip_check(launch_fft_sum(part, ns, np_d, vpix, pout, 2, st), "Parseval sum")))
+        return rc;
+    if (f || f2 || parseval) {
+        if ((rc = hip_check(launch_fft_lines((float2*)c->d_fft_Z.p, nb, g->n, st), "FFT line kernels")) ||
+            (rc = hip_check(launch_fft_finish((const float2*)c->d_fft_Z.p, g->n, ns, vpix, u, df, df2, part, &np_f,
+                                              st),
+                            "FFT finish kernel")))
+            return rc;
+        if (parseval &&
+            (rc = hip_check(launch_fft_sum(part, ns, np_f, dq3 / (8.0 * M_PI * M_PI * M_PI), pout + 1, 2, st),
+                            "Parseval sum")))
+            return rc;
+    }
+    if (!out_on_device) {
+        if ((rc = copy_out(df, f, df2, f2, nout, st))) return rc;
+        if (phi && (rc = hip_check(hipMemcpyAsync(phi, dphi, nout * sizeof(float), hipMemcpyDeviceToHost, st),
+                                   "D2H phi")))
+            return rc;
+    }
+    if (parseval &&
+        (rc = hip_check(hipMemcpyAsync(parseval, pout, (size_t)ns * 2 * sizeof(double), hipMemcpyDeviceToHost, st),
+                        "D2H Parseval sums")))
+        return rc;
+    if (!out_on_device || parseval) {
+        if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
+        order_done(c);
+    } else if ((rc = order_mark(c, st))) {
+        return rc;
+    }
+    return ok();
+}
 
 int scff_eval_separable(scff_ctx* c, const scff_grid* g, const double* wx, const double* wy, const double* wz,
                         double* out) {

@@ -217,9 +217,12 @@ void* take_stage(scff_server* s, size_t bytes) {
             s->stage_all.erase(std::find(s->stage_all.begin(), s->stage_all.end(), drop));
         }
     }
-    if (drop) (void)hipHostFree(drop);   // idle: no copy uses it
     void* p = nullptr;
-    if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+    {
+        scff::GateShared g(scff::device_gate());
+        if (drop) (void)hipHostFree(drop);   // idle: no copy uses it
+        if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     s->stage_all.push_back(p);
     s->stage_size[p] = cls;
@@ -265,6 +268,7 @@ void prep_loop(scff_server* s) {
     hipStream_t pst = nullptr;
     if (!s->fake) {
         (void)hipSetDevice(s->device);
+        scff::GateShared g(scff::device_gate());
         if (hipStreamCreateWithFlags(&pst, hipStreamNonBlocking) != hipSuccess) pst = nullptr;
     }
     for (;;) {
@@ -278,7 +282,10 @@ void prep_loop(scff_server* s) {
                 return s->stop || (!s->prep_q.empty() && (s->admitted + s->staged < s->budget || s->staged == 0));
             });
             if (s->stop) {
-                if (pst) (void)hipStreamDestroy(pst);
+                if (pst) {
+                    scff::GateShared g(scff::device_gate());
+                    (void)hipStreamDestroy(pst);
+                }
                 return;
             }
             t = s->prep_q.front();
@@ -448,6 +455,7 @@ int grow_device(void** p, size_t* cap, size_t need) {
     if (*cap >= need) return SCFF_OK;
     size_t c = std::max<size_t>(need, 2 * *cap);
     c = std::max<size_t>(c, 4096);
+    scff::GateShared g(scff::device_gate());
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
@@ -460,6 +468,7 @@ int grow_pinned(void** p, size_t* cap, size_t need) {
     if (*cap >= need) return SCFF_OK;
     size_t c = std::max<size_t>(need, 2 * *cap);
     c = std::max<size_t>(c, 4096);
+    scff::GateShared g(scff::device_gate());
     if (*p) (void)hipHostFree(*p);
     *p = nullptr;
     *cap = 0;
@@ -553,16 +562,33 @@ int run_batch(scff_server* s, Runner& R, std::vector<Member>& ms) {
         if (off[v + 1] > off[v]) topo += "k" + std::to_string(v);
     std::string err;
     hipGraph_t graph = nullptr;
-    bool captured = false;
-    if (hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        rc = enqueue_batch(R, live, off, need, err);
-        const hipError_t e = hipStreamEndCapture(R.st, &graph);
-        captured = rc == SCFF_OK && e == hipSuccess && graph;
-        if (!captured && graph) {
-            (void)hipGraphDestroy(graph);
-            graph = nullptr;
+    bool captured = false, began = false;
+    {
+        // no allocation, release or device synchronisation in any thread of
+        // the process while the stream is captured
+        std::unique_lock<std::shared_mutex> gate(scff::device_gate());
+        if (hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            began = true;
+            rc = enqueue_batch(R, live, off, need, err);
+            const hipError_t e = hipStreamEndCapture(R.st, &graph);
+            captured = rc == SCFF_OK && e == hipSuccess && graph;
+            if (!captured && graph) {
+                (void)hipGraphDestroy(graph);
+                graph = nullptr;
+            }
         }
         (void)hipGetLastError();   // a failed capture leaves its error behind
+    }
+    if (!captured && began) {
+        // the stream of a failed capture may keep its error: run the eager
+        // launches on a fresh one
+        scff::GateShared g(scff::device_gate());
+        hipStream_t fresh = nullptr;
+        if (hipStreamCreateWithFlags(&fresh, hipStreamNonBlocking) == hipSuccess) {
+            (void)hipStreamDestroy(R.st);
+            R.st = fresh;
+        }
+        (void)hipGetLastError();
     }
     hipGraphExec_t exec = nullptr;
     if (captured) {
@@ -578,6 +604,7 @@ int run_batch(scff_server* s, Runner& R, std::vector<Member>& ms) {
             hipGraphNode_t bad = nullptr;
             if (hipGraphExecUpdate(exec, graph, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
                 (void)hipGetLastError();
+                scff::GateShared g(scff::device_gate());
                 (void)hipGraphExecDestroy(exec);
                 exec = nullptr;
             } else {
@@ -585,6 +612,7 @@ int run_batch(scff_server* s, Runner& R, std::vector<Member>& ms) {
             }
         }
         if (!exec) {
+            scff::GateShared g(scff::device_gate());
             if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
                 ++R.graphs_instantiated;
             } else {
@@ -598,6 +626,7 @@ int run_batch(scff_server* s, Runner& R, std::vector<Member>& ms) {
     if (exec) {
         R.execs.emplace_back(topo, exec);
         if (R.execs.size() > kMaxExecs) {
+            scff::GateShared g(scff::device_gate());
             (void)hipGraphExecDestroy(R.execs.front().second);
             R.execs.erase(R.execs.begin());
         }
@@ -621,6 +650,7 @@ void run_loop(scff_server* s) {
     Runner R;
     if (!s->fake) {
         (void)hipSetDevice(s->device);
+        scff::GateShared g(scff::device_gate());
         if (hipStreamCreateWithFlags(&R.st, hipStreamNonBlocking) != hipSuccess) R.st = nullptr;
         if (hipMalloc((void**)&R.d_cnt, kVariants * sizeof(int)) != hipSuccess) R.d_cnt = nullptr;
     }
@@ -708,6 +738,7 @@ void run_loop(scff_server* s) {
         lk.unlock();
         drain_to_free(s);
     }
+    scff::GateShared g(scff::device_gate());
     for (auto& x : R.execs) (void)hipGraphExecDestroy(x.second);
     if (R.d_buf) (void)hipFree(R.d_buf);
     if (R.d_cnt) (void)hipFree(R.d_cnt);
@@ -924,7 +955,10 @@ void scff_server_destroy(scff_server* s) {
         if (kv.second->ctx) scff_destroy(kv.second->ctx);
     for (Idle& e : s->ctx_pool) scff_destroy(e.c);
     for (scff_ctx* c : s->to_free) scff_destroy(c);
-    for (void* p : s->stage_all) (void)hipHostFree(p);
+    {
+        scff::GateShared g(scff::device_gate());
+        for (void* p : s->stage_all) (void)hipHostFree(p);
+    }
     delete s;
 }
 
