@@ -49,6 +49,10 @@ class scff_grid(ctypes.Structure):
     _fields_ = [("n", c_int * 3), ("qmin", c_double * 3), ("qmax", c_double * 3)]
 
 
+class scff_fft_grid(ctypes.Structure):
+    _fields_ = [("n", c_int * 3), ("xmin", c_double * 3), ("L", c_double * 3)]
+
+
 class scff_info(ctypes.Structure):
     _fields_ = [("nbf", c_int), ("n_shells", c_int), ("n_states", c_int),
                 ("shell_pairs_total", c_longlong), ("pairs_total", c_longlong),
@@ -109,6 +113,8 @@ scff_export_vtensors = _fn("scff_export_vtensors", c_int,
                             c_void_p])
 scff_eval_separable = _fn("scff_eval_separable", c_int,
                           [c_void_p, P(scff_grid), P(c_double), P(c_double), P(c_double), P(c_double)])
+scff_eval_fft = _fn("scff_eval_fft", c_int,
+                    [c_void_p, P(scff_fft_grid), c_void_p, c_void_p, c_void_p, P(c_double), c_int, c_void_p])
 scff_dipole = _fn("scff_dipole", c_int, [c_void_p, P(c_double), P(c_double), P(c_double)])
 scff_dipole_fit = _fn("scff_dipole_fit", c_int, [c_void_p, c_double, P(c_double), P(c_double), P(c_double)])
 scff_server_create = _fn("scff_server_create", c_int, [c_int, c_size_t, c_int, P(c_void_p)])
@@ -189,6 +195,15 @@ def make_grid(n, qmin, qmax) -> scff_grid:
         g.n[a] = int(n[a])
         g.qmin[a] = float(qmin[a])
         g.qmax[a] = float(qmax[a])
+    return g
+
+
+def make_fft_grid(n, xmin, L) -> scff_fft_grid:
+    g = scff_fft_grid()
+    for a in range(3):
+        g.n[a] = int(n[a])
+        g.xmin[a] = float(xmin[a])
+        g.L[a] = float(L[a])
     return g
 
 
@@ -302,6 +317,38 @@ class Context:
                              f.data_ptr() if f is not None else None,
                              f2.data_ptr() if f2 is not None else None, 1, _stream_ptr(stream)))
         return f, f2
+
+    def eval_fft_host(self, n, xmin, L, want_f=True, want_f2=True, want_phi=False, parseval=True):
+        """FFT method on the box [xmin, xmin + L) sampled at n points per axis (host outputs):
+        (f complex64 [s,n0,n1,n2] or None, f2 or None, phi float32 [s,n0,n1,n2] or None,
+        parseval float64 [s, 2] or None)."""
+        g = make_fft_grid(n, xmin, L)
+        shape = (self.n_states,) + tuple(int(x) for x in n)
+        f = np.empty(shape + (2,), np.float32) if want_f else None
+        f2 = np.empty(shape, np.float32) if want_f2 else None
+        phi = np.empty(shape, np.float32) if want_phi else None
+        ps = np.empty((self.n_states, 2), np.float64) if parseval else None
+        check(scff_eval_fft(self._h, ctypes.byref(g), f.ctypes.data if f is not None else None,
+                            f2.ctypes.data if f2 is not None else None,
+                            phi.ctypes.data if phi is not None else None,
+                            _d(ps) if ps is not None else None, 0, None))
+        return (f.view(np.complex64)[..., 0] if f is not None else None), f2, phi, ps
+
+    def eval_fft_device(self, n, xmin, L, f=None, f2=None, phi=None, stream=None):
+        """FFT method into torch tensors f ([s,n0,n1,n2,2] float32), f2 / phi ([s,n0,n1,n2] float32)."""
+        import torch
+        g = make_fft_grid(n, xmin, L)
+        shape = (self.n_states,) + tuple(int(x) for x in n)
+        if f is not None:
+            _check_device_tensor(f, "f", torch.float32, shape + (2,), self.device)
+        if f2 is not None:
+            _check_device_tensor(f2, "f2", torch.float32, shape, self.device)
+        if phi is not None:
+            _check_device_tensor(phi, "phi", torch.float32, shape, self.device)
+        check(scff_eval_fft(self._h, ctypes.byref(g), f.data_ptr() if f is not None else None,
+                            f2.data_ptr() if f2 is not None else None,
+                            phi.data_ptr() if phi is not None else None, None, 1, _stream_ptr(stream)))
+        return f, f2, phi
 
     def eval_points(self, q, precision="fp32"):
         q = np.ascontiguousarray(np.atleast_2d(q), np.float64)

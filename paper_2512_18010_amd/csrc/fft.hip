@@ -61,7 +61,8 @@ __global__ void fft_pack_kernel(const double* __restrict__ T, const double* __re
     }
 }
 
-// AO values of one shell at one point, FP64, rounded to FP32 into
+// AO values of one shell at one point before the contracted normalisation
+// (c_mu is folded into the packed weights), FP64, rounded to FP32 into
 // ph[(bf0 + c) * NP + p] for each Cartesian component c.
 __device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, double y, double z, float* ph, int NP,
                                              int p) {
@@ -87,21 +88,20 @@ __device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, 
         }
     }
     const int b0 = m.bf0[sh];
-    const double* cn = m.cnorm + b0;
     float* o = ph + (size_t)b0 * NP + p;
     if (S.l == 0) {
-        o[0] = (float)(cn[0] * ra);
+        o[0] = (float)ra;
     } else if (S.l == 1) {
-        o[0] = (float)(cn[0] * dx * ra);
-        o[NP] = (float)(cn[1] * dy * ra);
-        o[2 * NP] = (float)(cn[2] * dz * ra);
+        o[0] = (float)(dx * ra);
+        o[NP] = (float)(dy * ra);
+        o[2 * NP] = (float)(dz * ra);
     } else {
-        o[0] = (float)(cn[0] * dx * dx * ra);
-        o[NP] = (float)(cn[1] * dx * dy * rb);
-        o[2 * NP] = (float)(cn[2] * dx * dz * rb);
-        o[3 * NP] = (float)(cn[3] * dy * dy * ra);
-        o[4 * NP] = (float)(cn[4] * dy * dz * rb);
-        o[5 * NP] = (float)(cn[5] * dz * dz * ra);
+        o[0] = (float)(dx * dx * ra);
+        o[NP] = (float)(dx * dy * rb);
+        o[2 * NP] = (float)(dx * dz * rb);
+        o[3 * NP] = (float)(dy * dy * ra);
+        o[4 * NP] = (float)(dy * dz * rb);
+        o[5 * NP] = (float)(dz * dz * ra);
     }
 }
 
@@ -374,6 +374,13 @@ hipError_t launch_fft_density(const FftMol& m, const float* Ap, int nbf_pad, int
     const int3 nn = make_int3(n[0], n[1], n[2]);
     const double3 xx = make_double3(x0[0], x0[1], x0[2]), hh = make_double3(h[0], h[1], h[2]);
     *n_part = tiles * (NP / 16);
+    if (lds > 65536) {
+        // dynamic LDS beyond 64 KiB per workgroup must be allowed explicitly
+        const void* fn = NP == 64 ? (const void*)fft_density_kernel<4>
+                                  : NP == 32 ? (const void*)fft_density_kernel<2> : (const void*)fft_density_kernel<1>;
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     if (NP == 64)
         hipLaunchKernelGGL(fft_density_kernel<4>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB,
                            KS, nn, xx, hh, npts, Z, phi, psum);

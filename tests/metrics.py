@@ -9,6 +9,9 @@ relative error where |f_ref|^2 >= 1e-3 peak are reported beside it.
 import numpy as np
 
 TOL_F2 = {"fp32": 1e-6, "bf16x3": 1e-4}
+# FFT method against the oracle's FFT method on the same grid (FP32 density
+# and FP32 radix-2 transforms)
+TOL_FFT = 1e-6
 
 # Error lines recorded by the GPU tests, printed in the terminal summary of
 # the run (so the error of every transition is visible without -s).

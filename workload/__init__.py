@@ -299,3 +299,18 @@ def sample_grid_indices(grid: Grid, n: int, seed: int) -> np.ndarray:
             for iz in (0, nz - 1):
                 idx.add((ix * ny + iy) * nz + iz)
     return np.array(sorted(idx), dtype=np.int64)
+
+
+# ------------------------------------------------------------- FFT method boxes
+
+def fft_box(mol: Molecule, n, margin_bohr: float = 5.0, scale: float = 2.0):
+    """Real-space box of the FFT method (paper Sec. 3, Fig. of the box scale):
+    the atoms' bounding box with `margin_bohr` on every side, enlarged
+    `scale` times about its centre, sampled at n points per axis.
+    Returns (n, xmin, L) as tuples."""
+    lo = mol.xyz.min(axis=0) - margin_bohr
+    hi = mol.xyz.max(axis=0) + margin_bohr
+    centre = 0.5 * (lo + hi)
+    L = scale * (hi - lo)
+    xmin = centre - 0.5 * L
+    return tuple(int(x) for x in n), tuple(float(x) for x in xmin), tuple(float(x) for x in L)
