@@ -257,6 +257,80 @@ def grid_roofline(K, R, ns, nq, precision, grid_ms):
                             "mfma_achieved_tflops": con_issued / grid_s / 1e12}}
 
 
+def fft_benchmark(ctx, stream, n_axis, steps, warmup, log):
+    """FFT method on the config-1 molecule and its 12 transitions in the
+    paper's doubled box (bounding box + 5 bohr, times 2) sampled at n_axis^3
+    points: one step = molecule load + T from HBM + weight packing + density +
+    transforms + finishing, f and |f|^2 left in HBM."""
+    import torch
+    import workload as wl
+    W = wl.make_config(1)
+    n, xmin, L = wl.fft_box(W.mol, (n_axis,) * 3)
+    ns, nbf = W.T.shape[0], W.mol.nbf
+    npts = n[0] * n[1] * n[2]
+    T_dev = torch.from_numpy(np.ascontiguousarray(W.T)).cuda()
+    f = torch.empty((ns,) + n + (2,), dtype=torch.float32, device="cuda")
+    f2 = torch.empty((ns,) + n, dtype=torch.float32, device="cuda")
+
+    def step():
+        ctx.load_molecule(W.mol)
+        ctx.load_transitions_device(T_dev, stream)
+        ctx.set_options(0.0, 1.0)
+        ctx.eval_fft_device(n, xmin, L, f, f2, None, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    st = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        st.append(ctx.last_fft_timing())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    st = np.array(st)
+    pack_ms, dens_ms, tr_ms = (float(np.mean(st[:, i])) for i in range(3))
+    # checks: the density on seeded points against the oracle, Parseval's identity
+    import oracle
+    _, _, phi, ps = ctx.eval_fft_host(n, xmin, L, want_f=False, want_f2=False, want_phi=True, parseval=True)
+    rng = np.random.Generator(np.random.PCG64(99))
+    idx = np.concatenate([rng.integers(0, npts, 200), np.abs(phi.reshape(ns, -1)).argmax(axis=1)])
+    ax = oracle.real_space_axes(n, xmin, L)
+    ii = np.unravel_index(idx, n)
+    pts = np.stack([ax[0][ii[0]], ax[1][ii[1]], ax[2][ii[2]]], axis=1)
+    ref = oracle.density(W.mol, W.T, pts, n_threads=min(16, os.cpu_count() or 1))
+    e_phi = np.abs(phi.reshape(ns, -1)[:, idx] - ref).max(axis=1) / np.abs(phi.reshape(ns, -1)).max(axis=1)
+    e_par = np.abs(ps[:, 0] / ps[:, 1] - 1.0)
+    del T_dev, f, f2
+    pairs = nbf * (nbf + 1) // 2
+    flops = 2.0 * pairs * ns * npts
+    nb = (ns + 1) // 2
+    passes = sum(1 for a in range(3) if n[a] > 1)
+    tr_bytes = passes * 2 * nb * npts * 8 + 2 * nb * npts * 8 + ns * npts * 12
+    log(f"fft method {n}: {ms:.2f} ms/step, density {dens_ms:.2f} ms ({flops / dens_ms / 1e9:.1f} TFLOP/s), "
+        f"transforms {tr_ms:.2f} ms, density error {e_phi.max():.2e}, Parseval {e_par.max():.2e}")
+    return {
+        "workload": f"{W.name}; FFT box {n[0]}x{n[1]}x{n[2]} = bounding box + 5 bohr, doubled",
+        "box": {"n": list(n), "xmin": list(xmin), "L": list(L)},
+        "steps": steps, "ms_per_step": ms,
+        "value": ns * npts / (ms * 1e-3), "unit": "q-points*transitions/s",
+        "stages_ms": {"pack": pack_ms, "density": dens_ms, "transforms": tr_ms},
+        "roofline": {"bound": "mfma", "kernel": "fft_density_kernel",
+                     "achieved": flops / (dens_ms * 1e-3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / (dens_ms * 1e-3) / PEAK_FP32_MFMA,
+                     "per_unit": "2 flops per (unordered AO pair, real-space point, transition) on the matrix cores",
+                     "units": {"pairs": pairs, "points": npts, "n_states": ns}},
+        "transforms_roofline": {"bound": "hbm", "achieved": tr_bytes / (tr_ms * 1e-3) / 1e9,
+                                "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                "frac": tr_bytes / (tr_ms * 1e-3) / PEAK_HBM,
+                                "per_unit": "per pass 16 B per complex point of each state pair; finishing "
+                                            "16 B read per pair and 12 B written per state per point"},
+        "errors_vs_oracle": {"density_sampled_max": float(e_phi.max()),
+                             "density_per_transition": [float(x) for x in e_phi],
+                             "parseval_max": float(e_par.max())},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +349,9 @@ def main():
     ap.add_argument("--no-config2", action="store_true",
                     help="skip the 128^3 leg (190 bf, 12 transitions: split-BF16 vs FP32, error per transition)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--no-fft", action="store_true",
+                    help="skip the FFT-method leg (190 bf, 12 transitions, 128^3 real-space box)")
+    ap.add_argument("--fft-n", type=int, default=128, help="real-space points per axis of the FFT-method leg")
     ap.add_argument("--no-symmetric", action="store_true",
                     help="skip the symmetric-grid measurement (f(-q) = f(q)*, half the planes evaluated)")
     ap.add_argument("--serve-pool", type=int, default=24, help="distinct requests in the serving pool")
@@ -430,6 +507,11 @@ def main():
         c2.release()
         config2 = {"workload": c2.W.name, "grid": list(c2.n), "n_states": c2.ns, "legs": legs2}
 
+    # ---- FFT method (Sec. 3, Sec. 5.2): config-1 molecule and transitions
+    fft_leg = None
+    if not args.no_fft:
+        fft_leg = fft_benchmark(ctx, stream, args.fft_n, max(5, args.steps // 2), 2, log)
+
     serving = None
     if not args.no_serving:
         serving = []
@@ -482,6 +564,7 @@ def main():
         "config2": config2,
         "symmetric_grid": symmetric,
         "serving": serving,
+        "fft_method": fft_leg,
     }
     print(json.dumps(out))
 

@@ -284,7 +284,7 @@ int scff_export_vtensors(scff_ctx* ctx, const scff_grid* grid, long long* n_term
  * contracted on the matrix cores with FP64 sums over each 16 functions),
  * the transform FP32 radix-2, the corner phase FP64.  The context's
  * screening threshold is not applied (primitives below the FP32 range are
- * skipped); the spin factor is.  Basis size: up to about 1000 functions.
+ * skipped); the spin factor is.  Basis size: up to 1232 functions.
  * SCFF_EINVAL for bad sizes, no output or a basis too large, SCFF_ESTATE
  * before a molecule and transitions are loaded, SCFF_ENOMEM over the budget.
  */
@@ -296,6 +296,12 @@ typedef struct {
 
 int scff_eval_fft(scff_ctx* ctx, const scff_fft_grid* grid, float* f, float* f2, float* phi, double* parseval,
                   int out_on_device, void* hip_stream);
+
+/* With scff_set_timing(ctx, 1): HIP-event durations (ms) of the last
+ * scff_eval_fft's weight packing, transition-density kernel, and transforms
+ * with the finishing kernel (and the Parseval sums); waits for them.
+ * SCFF_ESTATE if no timed FFT evaluation was recorded. */
+int scff_last_fft_timing(scff_ctx* ctx, float* pack_ms, float* density_ms, float* transform_ms);
 
 /*
  * Separable integral (paper Sec. 5.3: integrals of the form

@@ -115,6 +115,7 @@ scff_eval_separable = _fn("scff_eval_separable", c_int,
                           [c_void_p, P(scff_grid), P(c_double), P(c_double), P(c_double), P(c_double)])
 scff_eval_fft = _fn("scff_eval_fft", c_int,
                     [c_void_p, P(scff_fft_grid), c_void_p, c_void_p, c_void_p, P(c_double), c_int, c_void_p])
+scff_last_fft_timing = _fn("scff_last_fft_timing", c_int, [c_void_p, P(c_float), P(c_float), P(c_float)])
 scff_dipole = _fn("scff_dipole", c_int, [c_void_p, P(c_double), P(c_double), P(c_double)])
 scff_dipole_fit = _fn("scff_dipole_fit", c_int, [c_void_p, c_double, P(c_double), P(c_double), P(c_double)])
 scff_server_create = _fn("scff_server_create", c_int, [c_int, c_size_t, c_int, P(c_void_p)])
@@ -349,6 +350,12 @@ class Context:
                             f2.data_ptr() if f2 is not None else None,
                             phi.data_ptr() if phi is not None else None, None, 1, _stream_ptr(stream)))
         return f, f2, phi
+
+    def last_fft_timing(self):
+        """(pack_ms, density_ms, transform_ms) of the last timed FFT evaluation."""
+        a, b, t = c_float(), c_float(), c_float()
+        check(scff_last_fft_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)))
+        return a.value, b.value, t.value
 
     def eval_points(self, q, precision="fp32"):
         q = np.ascontiguousarray(np.atleast_2d(q), np.float64)

@@ -173,11 +173,11 @@ struct FftMol {
     const double* cnorm;
     int n_shells;
 };
-// LDS a density workgroup may hold: two workgroups per CU.
+// LDS a density workgroup may hold (its AO block grows with the basis: up to
+// 1232 functions).
 constexpr size_t kFftLdsBytes = (size_t)78 << 10;
-// Grid points per density workgroup (64, 32 or 16) for nbf_pad basis rows
-// within lds_limit bytes of LDS; 0 if even 16 do not fit.
-int fft_points_per_tile(int nbf_pad, size_t lds_limit);
+// LDS bytes of one density workgroup for nbf_pad basis rows.
+size_t fft_density_lds(int nbf_pad);
 hipError_t launch_fft_pack(const double* T, const double* cnorm, int nbf, int ns, int RB, int KS, double spin,
                            float* Ap, hipStream_t st);
 hipError_t launch_fft_density(const FftMol& m, const float* Ap, int nbf_pad, int ns, int RB, int KS, const int n[3],

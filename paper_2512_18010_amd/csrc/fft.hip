@@ -37,6 +37,9 @@ typedef float fft_floatx4 __attribute__((ext_vector_type(4)));
 // smallest FP32 subnormal, so the rounded AO value is unchanged.
 constexpr double kExpCut = 103.0;
 
+// Grid points per density workgroup: one MFMA column block.
+constexpr int kFftTile = 16;
+
 namespace {
 
 __global__ void fft_pack_kernel(const double* __restrict__ T, const double* __restrict__ cnorm, int nbf, int ns,
@@ -63,8 +66,8 @@ __global__ void fft_pack_kernel(const double* __restrict__ T, const double* __re
 
 // AO values of one shell at one point before the contracted normalisation
 // (c_mu is folded into the packed weights), FP64, rounded to FP32 into
-// ph[(bf0 + c) * NP + p] for each Cartesian component c.
-__device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, double y, double z, float* ph, int NP,
+// ph[(bf0 + c) * RS + p] for each Cartesian component c (RS: LDS row stride).
+__device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, double y, double z, float* ph, int RS,
                                              int p) {
     const PrepShell S = m.shells[sh];
     const double* A = m.xyz + 3 * S.atom;
@@ -88,75 +91,103 @@ __device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, 
         }
     }
     const int b0 = m.bf0[sh];
-    float* o = ph + (size_t)b0 * NP + p;
+    float* o = ph + (size_t)b0 * RS + p;
     if (S.l == 0) {
         o[0] = (float)ra;
     } else if (S.l == 1) {
         o[0] = (float)(dx * ra);
-        o[NP] = (float)(dy * ra);
-        o[2 * NP] = (float)(dz * ra);
+        o[RS] = (float)(dy * ra);
+        o[2 * RS] = (float)(dz * ra);
     } else {
         o[0] = (float)(dx * dx * ra);
-        o[NP] = (float)(dx * dy * rb);
-        o[2 * NP] = (float)(dx * dz * rb);
-        o[3 * NP] = (float)(dy * dy * ra);
-        o[4 * NP] = (float)(dy * dz * rb);
-        o[5 * NP] = (float)(dz * dz * ra);
+        o[RS] = (float)(dx * dy * rb);
+        o[2 * RS] = (float)(dx * dz * rb);
+        o[3 * RS] = (float)(dy * dy * ra);
+        o[4 * RS] = (float)(dy * dz * rb);
+        o[5 * RS] = (float)(dz * dz * ra);
     }
 }
 
-// One workgroup (4 waves) per tile of NP = 16 NPB consecutive grid points
-// (flattened [ix][iy][iz], z fastest).  Wave w works on point block
-// pb = w % NPB and on the row blocks rb = w / NPB (mod 4 / NPB); the row
-// groups of a point block are summed through LDS at the end of each state.
-// LDS: phi[nbf_pad][NP] FP32, then 4 x 16 FP64 for that sum.
-template <int NPB>
+// One workgroup (4 waves) per tile of 16 consecutive grid points (flattened
+// [ix][iy][iz], z fastest).  Wave w takes the row blocks rb = w (mod 4) of
+// every state; the four partial densities of a point are summed through LDS
+// at the end of each state.  LDS: phi[nbf_pad][16] FP32 (a wave reads rows
+// 4 ks + kk, kk = 0..3, at the 16 points per MFMA operand: 64 distinct
+// banks), then 4 x 16 FP64 for the sum.  Small tiles keep the LDS per
+// workgroup small, so up to 8 waves per SIMD hide the operand latencies; the
+// four waves read the same A operands at nearly the same time, mostly from
+// the vector L1.
 __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const float* __restrict__ Ap, int nbf_pad, int ns,
                                                           int RB, int KS, int3 n, double3 x0, double3 h,
                                                           long long npts, float* __restrict__ Z,
                                                           float* __restrict__ phi_out, double* __restrict__ psum) {
     extern __shared__ __align__(16) float fft_lds[];
-    constexpr int NP = 16 * NPB;
-    constexpr int WR = 4 / NPB;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NP = kFftTile;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wave-uniform: the row-block loop and the A-operand addresses stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const long long p0 = (long long)blockIdx.x * NP;
     float* ph = fft_lds;
     double* red = reinterpret_cast<double*>(fft_lds + (size_t)nbf_pad * NP);
 
     for (int i = tid; i < nbf_pad * NP; i += 256) ph[i] = 0.f;
     __syncthreads();
-    for (int item = tid; item < m.n_shells * NP; item += 256) {
-        const int sh = item / NP, p = item - sh * NP;
+    {
+        // one lane per (shell, point): a wave takes 4 shells at a time
+        const int p = lane % NP;
         const long long g = p0 + p;
-        if (g >= npts) continue;
         const int iz = (int)(g % n.z);
         const long long r1 = g / n.z;
         const int iy = (int)(r1 % n.y), ix = (int)(r1 / n.y);
-        shell_values(m, sh, x0.x + ix * h.x, x0.y + iy * h.y, x0.z + iz * h.z, ph, NP, p);
+        const double x = x0.x + ix * h.x, y = x0.y + iy * h.y, z = x0.z + iz * h.z;
+        for (int sh0 = wave * 4; sh0 < m.n_shells; sh0 += 16) {
+            const int sh = sh0 + lane / NP;
+            if (sh < m.n_shells && g < npts) shell_values(m, sh, x, y, z, ph, NP, p);
+        }
     }
     __syncthreads();
 
-    const int pb = wave % NPB, rg = wave / NPB;
     const int kk = lane >> 4, col = lane & 15;
-    const float* phc = ph + pb * 16 + col;   // phi[row][pb*16 + col] = phc[row * NP]
-    const long long g = p0 + pb * 16 + col;
+    const float* phc = ph + col;   // phi[row][col] = phc[row * NP]
+    const long long g = p0 + col;
     const bool valid = g < npts;
     for (int s = 0; s < ns; ++s) {
         double acc = 0.0;
-        for (int rb = rg; rb < RB; rb += WR) {
+        for (int rb = wave; rb < RB; rb += 4) {
             fft_floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
             const float* ap = Ap + (size_t)(s * RB + rb) * KS * 64 + lane;
-            int ks = 4 * rb;
-            for (; ks + 1 < KS; ks += 2) {
-                const float a0 = ap[(size_t)ks * 64], a1 = ap[(size_t)(ks + 1) * 64];
-                const float b0 = phc[(4 * ks + kk) * NP], b1 = phc[(4 * ks + 4 + kk) * NP];
-                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, c1, 0, 0, 0);
-            }
-            if (ks < KS) {
-                const float a0 = ap[(size_t)ks * 64];
-                const float b0 = phc[(4 * ks + kk) * NP];
-                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c0, 0, 0, 0);
+            // k-steps k0 .. KS-1 (a multiple of 4 of them).  The A operands of
+            // the next 8 k-steps are loaded while the current 8 run (two
+            // register sets); loads past the row block read the next block or
+            // the array's slack and are not used
+            const int k0 = 4 * rb, nk = KS - k0;
+            float A0[8], A1[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) A0[j] = ap[(size_t)(k0 + j) * 64];
+            for (int t = 0; t < nk; t += 16) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) A1[j] = ap[(size_t)(k0 + t + 8 + j) * 64];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (j < 4 || t + 4 < nk) {
+                        const float b = phc[(4 * (k0 + t + j) + kk) * NP];
+                        if (j & 1)
+                            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A0[j], b, c1, 0, 0, 0);
+                        else
+                            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A0[j], b, c0, 0, 0, 0);
+                    }
+                if (t + 8 >= nk) break;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) A0[j] = ap[(size_t)(k0 + t + 16 + j) * 64];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (j < 4 || t + 12 < nk) {
+                        const float b = phc[(4 * (k0 + t + 8 + j) + kk) * NP];
+                        if (j & 1)
+                            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A1[j], b, c1, 0, 0, 0);
+                        else
+                            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A1[j], b, c0, 0, 0, 0);
+                    }
             }
             // lane (kk, col) holds rows 4 kk + i of column col
 #pragma unroll
@@ -165,14 +196,10 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const float*
         }
         acc += __shfl_xor(acc, 16);
         acc += __shfl_xor(acc, 32);
-        if constexpr (WR > 1) {
-            if (lane < 16) red[wave * 16 + lane] = acc;
-            __syncthreads();
-            if (rg == 0)
-                for (int w = 1; w < WR; ++w) acc += red[(pb + w * NPB) * 16 + col];
-            __syncthreads();
-        }
-        if (rg == 0) {
+        if (lane < 16) red[wave * 16 + lane] = acc;
+        __syncthreads();
+        if (wave == 0) {
+            acc += red[16 + col] + red[32 + col] + red[48 + col];
             if (valid && lane < 16) {
                 const float v = (float)acc;
                 float* zp = Z + ((size_t)(s >> 1) * npts + g) * 2;
@@ -185,8 +212,9 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const float*
             q += __shfl_xor(q, 2);
             q += __shfl_xor(q, 4);
             q += __shfl_xor(q, 8);
-            if (psum && lane == 0) psum[(size_t)s * gridDim.x * NPB + (size_t)blockIdx.x * NPB + pb] = q;
+            if (psum && lane == 0) psum[(size_t)s * gridDim.x + blockIdx.x] = q;
         }
+        __syncthreads();
     }
 }
 
@@ -347,12 +375,7 @@ __global__ __launch_bounds__(256) void fft_sum_kernel(const double* __restrict__
 
 }  // namespace
 
-int fft_points_per_tile(int nbf_pad, size_t lds_limit) {
-    const size_t extra = 4 * 16 * sizeof(double);
-    for (int np = 64; np >= 16; np /= 2)
-        if ((size_t)nbf_pad * np * sizeof(float) + extra <= lds_limit) return np;
-    return 0;
-}
+size_t fft_density_lds(int nbf_pad) { return (size_t)nbf_pad * kFftTile * sizeof(float) + 4 * 16 * sizeof(double); }
 
 hipError_t launch_fft_pack(const double* T, const double* cnorm, int nbf, int ns, int RB, int KS, double spin,
                            float* Ap, hipStream_t st) {
@@ -366,30 +389,20 @@ hipError_t launch_fft_density(const FftMol& m, const float* Ap, int nbf_pad, int
                               const double x0[3], const double h[3], float* Z, float* phi, double* psum,
                               size_t lds_limit, long long* n_part, hipStream_t st) {
     const long long npts = (long long)n[0] * n[1] * n[2];
-    const int NP = fft_points_per_tile(nbf_pad, lds_limit);
-    if (NP == 0) return hipErrorInvalidValue;
-    const long long tiles = (npts + NP - 1) / NP;
+    const size_t lds = fft_density_lds(nbf_pad);
+    if (lds > lds_limit) return hipErrorInvalidValue;
+    const long long tiles = (npts + kFftTile - 1) / kFftTile;
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    const size_t lds = (size_t)nbf_pad * NP * sizeof(float) + 4 * 16 * sizeof(double);
-    const int3 nn = make_int3(n[0], n[1], n[2]);
-    const double3 xx = make_double3(x0[0], x0[1], x0[2]), hh = make_double3(h[0], h[1], h[2]);
-    *n_part = tiles * (NP / 16);
+    *n_part = tiles;
     if (lds > 65536) {
         // dynamic LDS beyond 64 KiB per workgroup must be allowed explicitly
-        const void* fn = NP == 64 ? (const void*)fft_density_kernel<4>
-                                  : NP == 32 ? (const void*)fft_density_kernel<2> : (const void*)fft_density_kernel<1>;
-        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t e =
+            hipFuncSetAttribute((const void*)fft_density_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    if (NP == 64)
-        hipLaunchKernelGGL(fft_density_kernel<4>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB,
-                           KS, nn, xx, hh, npts, Z, phi, psum);
-    else if (NP == 32)
-        hipLaunchKernelGGL(fft_density_kernel<2>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB,
-                           KS, nn, xx, hh, npts, Z, phi, psum);
-    else
-        hipLaunchKernelGGL(fft_density_kernel<1>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB,
-                           KS, nn, xx, hh, npts, Z, phi, psum);
+    hipLaunchKernelGGL(fft_density_kernel, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB, KS,
+                       make_int3(n[0], n[1], n[2]), make_double3(x0[0], x0[1], x0[2]),
+                       make_double3(h[0], h[1], h[2]), npts, Z, phi, psum);
     return hipGetLastError();
 }
 

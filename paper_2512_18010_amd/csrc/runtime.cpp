@@ -60,7 +60,8 @@ std::shared_mutex& scff::device_gate() {
 }
 
 // Timing events: precompute start/end, 1D tables start, grid kernel start/end.
-enum { EV_PREP0, EV_PREP1, EV_VT0, EV_GRID0, EV_GRID1, EV_N };
+// FFT method: packing start, density start, density end, transforms end.
+enum { EV_PREP0, EV_PREP1, EV_VT0, EV_GRID0, EV_GRID1, EV_FFT0, EV_FFT1, EV_FFT2, EV_FFT3, EV_N };
 
 struct scff_ctx {
     int device = 0;
@@ -88,7 +89,7 @@ struct scff_ctx {
     // timing
     bool timing = false;
     hipEvent_t ev[EV_N] = {};
-    bool ev_recorded = false, ev_prep = false;
+    bool ev_recorded = false, ev_prep = false, fft_recorded = false;
     // stream ordering: the end of the last asynchronous work on the context
     hipEvent_t order_ev = nullptr;
     hipStream_t order_st = nullptr;
@@ -842,6 +843,7 @@ int scff_set_timing(scff_ctx* c, int enable) {
     }
     c->timing = enable != 0;
     c->ev_recorded = false;
+    c->fft_recorded = false;
     return ok();
 }
 
@@ -858,6 +860,22 @@ int scff_last_timing(scff_ctx* c, float* prep_ms, float* vtable_ms, float* grid_
     if (prep_ms) *prep_ms = c->ev_prep ? p : 0.0f;
     if (vtable_ms) *vtable_ms = a;
     if (grid_ms) *grid_ms = b;
+    return ok();
+}
+
+int scff_last_fft_timing(scff_ctx* c, float* pack_ms, float* density_ms, float* transform_ms) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (!c->timing || !c->fft_recorded) return fail(SCFF_ESTATE, "no timed FFT evaluation recorded");
+    int rc;
+    if ((rc = hip_check(hipEventSynchronize(c->ev[EV_FFT3]), "event sync"))) return rc;
+    float a = 0.f, b = 0.f, t = 0.f;
+    if ((rc = hip_check(hipEventElapsedTime(&a, c->ev[EV_FFT0], c->ev[EV_FFT1]), "elapsed")) ||
+        (rc = hip_check(hipEventElapsedTime(&b, c->ev[EV_FFT1], c->ev[EV_FFT2]), "elapsed")) ||
+        (rc = hip_check(hipEventElapsedTime(&t, c->ev[EV_FFT2], c->ev[EV_FFT3]), "elapsed")))
+        return rc;
+    if (pack_ms) *pack_ms = a;
+    if (density_ms) *density_ms = b;
+    if (transform_ms) *transform_ms = t;
     return ok();
 }
 
@@ -1024,7 +1042,7 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, floa
     const int nbf = c->basis.nbf, ns = c->n_states;
     const int nbf_pad = (nbf + 15) & ~15;
     const size_t lds_limit = std::min(c->lds_block, kFftLdsBytes);
-    if (fft_points_per_tile(nbf_pad, lds_limit) == 0)
+    if (fft_density_lds(nbf_pad) > lds_limit)
         return fail(SCFF_EINVAL, "basis too large for the FFT method's density tile (" + std::to_string(nbf) +
                                      " functions)");
     int rc;
@@ -1034,9 +1052,9 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, floa
     const int RB = nbf_pad / 16, KS = nbf_pad / 4, nb = (ns + 1) / 2;
     const long long npts = (long long)g->n[0] * g->n[1] * g->n[2];
     const size_t nout = (size_t)npts * ns;
-    const int NP = fft_points_per_tile(nbf_pad, lds_limit);
-    const long long part_d = (npts + NP - 1) / NP * (NP / 16), part_f = (npts + 63) / 64;
-    if ((rc = dev_reserve(c, c->d_fft_A, (size_t)ns * RB * KS * 64 * sizeof(float))) ||
+    const long long part_d = (npts + 15) / 16, part_f = (npts + 63) / 64;
+    // the density kernel loads A operands up to 24 k-steps past a row block (unused): slack of 32
+    if ((rc = dev_reserve(c, c->d_fft_A, ((size_t)ns * RB * KS + 32) * 64 * sizeof(float))) ||
         (rc = dev_reserve(c, c->d_fft_Z, (size_t)nb * npts * sizeof(float2))))
         return rc;
     if (parseval &&
@@ -1074,12 +1092,16 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, floa
     double* part = parseval ? (double*)c->d_fft_part.p : nullptr;
     double* pout = parseval ? (double*)c->d_fft_out.p : nullptr;
     long long np_d = 0, np_f = 0;
+    c->fft_recorded = false;
+    if ((rc = record(c, EV_FFT0, st))) return rc;
     if ((rc = hip_check(launch_fft_pack((const double*)c->d_T.p, m.cnorm, nbf, ns, RB, KS, c->spin,
                                        (float*)c->d_fft_A.p, st),
                         "FFT weight packing")) ||
+        (rc = record(c, EV_FFT1, st)) ||
         (rc = hip_check(launch_fft_density(m, (const float*)c->d_fft_A.p, nbf_pad, ns, RB, KS, g->n, g->xmin, h,
                                            (float*)c->d_fft_Z.p, dphi, part, lds_limit, &np_d, st),
-                        "transition density kernel")))
+                        "transition density kernel")) ||
+        (rc = record(c, EV_FFT2, st)))
         return rc;
     if (parseval && (rc = hip_check(launch_fft_sum(part, ns, np_d, vpix, pout, 2, st), "Parseval sum")))
         return rc;
@@ -1094,6 +1116,8 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, floa
                             "Parseval sum")))
             return rc;
     }
+    if ((rc = record(c, EV_FFT3, st))) return rc;
+    c->fft_recorded = c->timing;
     if (!out_on_device) {
         if ((rc = copy_out(df, f, df2, f2, nout, st))) return rc;
         if (phi && (rc = hip_check(hipMemcpyAsync(phi, dphi, nout * sizeof(float), hipMemcpyDeviceToHost, st),

@@ -88,8 +88,8 @@ def test_fft_odd_state_count_and_spin(eng, oracle_mod):
 
 @pytest.mark.parametrize("n_heavy,n_states", [(30, 3), (36, 2)])
 def test_fft_large_basis_tiles(eng, oracle_mod, n_heavy, n_states):
-    """Bases of 570 and ~660 functions, which take the tiles of 32 and 16
-    points (the AO block of a tile fills the workgroup's LDS)."""
+    """Bases of 570 and 685 functions (36 and 43 row blocks of 16, so each
+    of the four waves of a tile takes a different number of them)."""
     rng = np.random.Generator(np.random.PCG64(950 + n_heavy))
     mol = wl.make_molecule(rng, n_heavy, int(round(0.8 * n_heavy)), layout="box",
                            box_A=12.0 * (n_heavy / 30.0) ** (1 / 3))
