@@ -34,13 +34,19 @@ PEAK_HBM = 8.0e12
 
 
 def kernel_source_hash() -> str:
-    """Hash of the kernel source with comments and blank lines dropped (a
-    comment edit does not invalidate measured counters; a code edit does)."""
+    """Hash of the grid kernel's source: kernels.hip and the part of engine.h
+    that defines its layout constants and descriptor (from the namespace to
+    the first runtime declaration), with comments and blank lines dropped (a
+    comment edit or a change elsewhere does not invalidate measured counters;
+    a change of the kernel's code does)."""
     import re
     h = hashlib.sha256()
     for name in ("kernels.hip", "engine.h"):
         with open(os.path.join(ROOT, "paper_2512_18010_amd", "csrc", name)) as fh:
-            text = re.sub(r"//[^\n]*", "", fh.read())
+            text = fh.read()
+        if name == "engine.h":
+            text = text[text.index("namespace scff {"):text.index("struct DeviceBuffer")]
+        text = re.sub(r"//[^\n]*", "", text)
         h.update("\n".join(l.rstrip() for l in text.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
