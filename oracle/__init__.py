@@ -11,7 +11,13 @@ follows.  This wrapper only builds that file with gcc and marshals arrays.
 
 The FFT method (Sec. 3, Sec. 5.2) is here too: the transition density on a
 real-space grid (C, FP64) and its transform by the paper's steps, with
-numpy's FFT as the library step (``fft_form_factor``).
+numpy's FFT as the library step (``fft_form_factor``).  And the spherical
+method's result (Sec. 4 eqs. SphericalMethod, RTensor; Sec. 5.4) from its
+plain definition: R_lm(q) is the projection of f on the sphere of radius q
+onto the complex spherical harmonic Y_lm, computed with a product quadrature
+(Gauss-Legendre in cos theta, uniform in phi) of the Cartesian f above, and
+the spherical grid is the truncated sum over l <= lmax (``spherical_R``,
+``spherical_grid``).
 
 Parity unpinned: nothing.  Every function here is pinned by tests against
 closed forms, real-space quadrature, the paper's Hermite form, a direct DFT
@@ -224,3 +230,91 @@ def parseval_sums(phi, f, n, L):
     a = (np.abs(phi.reshape(ns, -1)) ** 2).sum(axis=1) * vpix
     b = (np.abs(f.reshape(ns, -1)) ** 2).sum(axis=1) * dq3 / (2.0 * np.pi) ** 3
     return a, b
+
+
+# ------------------------------------------------------------ spherical method
+
+
+def ylm_index(l, m):
+    return l * l + l + m
+
+
+def sph_harm_table(lmax, theta, phi):
+    """Complex spherical harmonics Y_l^m(theta, phi), orthonormal on the unit
+    sphere, with the Condon-Shortley phase, for l <= lmax -> complex128
+    [(lmax+1)^2, n] (index l^2 + l + m).  Associated Legendre functions by the
+    standard upward recurrences in l from P_m^m; Y_l^{-m} = (-1)^m conj(Y_l^m)."""
+    theta = np.asarray(theta, np.float64).reshape(-1)
+    phi = np.asarray(phi, np.float64).reshape(-1)
+    x, sx = np.cos(theta), np.sin(theta)
+    out = np.zeros(((lmax + 1) ** 2, theta.size), np.complex128)
+    # normalised P~_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) P_l^m, P_l^m with Condon-Shortley phase
+    pmm = np.full(theta.size, np.sqrt(1.0 / (4.0 * np.pi)))
+    for m in range(lmax + 1):
+        if m > 0:
+            pmm = -np.sqrt((2.0 * m + 1.0) / (2.0 * m)) * sx * pmm
+        plm2, plm1 = None, pmm
+        e = np.exp(1j * m * phi)
+        for l in range(m, lmax + 1):
+            if l == m:
+                cur = pmm
+            elif l == m + 1:
+                cur = np.sqrt(2.0 * m + 3.0) * x * pmm
+            else:
+                a = np.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+                b = np.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+                cur = a * (x * plm1 - b * plm2)
+            if l > m:
+                plm2, plm1 = plm1, cur
+            y = cur * e
+            out[ylm_index(l, m)] = y
+            if m > 0:
+                out[ylm_index(l, -m)] = (-1) ** m * np.conj(y)
+    return out
+
+
+def sphere_rule(n_theta, n_phi=None):
+    """Product rule on the unit sphere: Gauss-Legendre nodes in cos(theta),
+    n_phi = 2 n_theta equally spaced azimuths.  Exact for Y_l^m products of
+    total degree < 2 n_theta (and |m| < n_phi).  Returns (theta, phi, w)."""
+    if n_phi is None:
+        n_phi = 2 * n_theta
+    xg, wg = np.polynomial.legendre.leggauss(n_theta)
+    ph = 2.0 * np.pi * np.arange(n_phi) / n_phi
+    T, P = np.meshgrid(np.arccos(xg), ph, indexing="ij")
+    W = np.repeat(wg[:, None], n_phi, axis=1) * (2.0 * np.pi / n_phi)
+    return T.ravel(), P.ravel(), W.ravel()
+
+
+def spherical_R(mol, T, qs, lmax, n_theta, normalise=True, spin_factor=1.0, n_threads=None):
+    """R_lm(q) = int dOmega Y_l^m*(q^) f(q q^) for each radius in qs (a.u.):
+    the coefficients of eq. SphericalMethod, from the Cartesian f of this
+    oracle on a product quadrature with n_theta Gauss-Legendre nodes (choose
+    n_theta above lmax plus the band limit of f on the sphere, about
+    q * max|r| + 30).  Returns complex128 [n_states, n_q, (lmax+1)^2]."""
+    th, ph, w = sphere_rule(n_theta)
+    Y = sph_harm_table(lmax, th, ph)
+    dirs = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    qs = np.asarray(qs, np.float64).reshape(-1)
+    T = np.asarray(T, np.float64)
+    if T.ndim == 2:
+        T = T[None]
+    out = np.zeros((T.shape[0], qs.size, (lmax + 1) ** 2), np.complex128)
+    for k, q in enumerate(qs):
+        f = eval_points(mol, T, q * dirs, normalise, spin_factor, n_threads)   # [s, n_pts]
+        out[:, k, :] = (f * w[None, :]) @ np.conj(Y).T
+    return out
+
+
+def spherical_grid(R, lmax, theta, phi):
+    """f_s(q, theta_i, phi_j) = sum_{l <= lmax, m} R_lm(q) Y_l^m(theta_i, phi_j)
+    -> complex128 [n_states, n_q, n_theta, n_phi]."""
+    th, ph = np.meshgrid(np.asarray(theta, float), np.asarray(phi, float), indexing="ij")
+    Y = sph_harm_table(lmax, th.ravel(), ph.ravel())
+    f = R[..., : (lmax + 1) ** 2] @ Y
+    return f.reshape(R.shape[0], R.shape[1], th.shape[0], th.shape[1])
+
+
+def angular_average_from_R(R):
+    """<|f|^2>_Omega(q) = sum_lm |R_lm(q)|^2 / (4 pi) (Sec. 4) -> [n_states, n_q]."""
+    return (np.abs(R) ** 2).sum(axis=-1) / (4.0 * np.pi)
