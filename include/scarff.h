@@ -304,6 +304,37 @@ int scff_eval_fft(scff_ctx* ctx, const scff_fft_grid* grid, float* f, float* f2,
 int scff_last_fft_timing(scff_ctx* ctx, float* pack_ms, float* density_ms, float* transform_ms);
 
 /*
+ * The spherical method (paper Sec. 4 eqs. DTensor, WTensor, YYY,
+ * SphericalMethod, RTensor; Sec. 5.4; App. B): the form factor on spheres of
+ * radius q (a.u.) expanded in complex spherical harmonics (Condon-Shortley
+ * phase, orthonormal),
+ *     f_s(q, theta, phi) = sum_{l <= lmax} sum_{m} R^s_lm(q) Y_l^m(theta, phi),
+ * where R^s_lm(q) = int dOmega Y_l^m* f_s is computed exactly (up to rounding,
+ * in FP64) from the pair precompute: per Gaussian centre of a primitive pair
+ * the monomial coefficients are turned into harmonics, the plane wave
+ * e^{i q.P} is expanded in spherical Bessel functions and harmonics, and the
+ * two are coupled with Gaunt coefficients.  The truncation at lmax is the
+ * method's only approximation (it converges quickly, see the paper's figure
+ * of the angular average); the screening threshold is not applied.
+ *   lmax       0..48
+ *   q          n_q radii (host array, >= 0), n_q in 1..4096
+ *   n_theta, n_phi
+ *              the angular grid theta_i = pi i / (n_theta - 1),
+ *              phi_j = 2 pi j / n_phi (n_theta >= 2 when f or f2 is requested)
+ *   R          complex128 [n_states][n_q][(lmax+1)^2][2], index l^2 + l + m, or NULL
+ *   f, f2      complex64 [n_states][n_q][n_theta][n_phi][2] and float
+ *              [n_states][n_q][n_theta][n_phi], or NULL
+ *   avg        <|f_s|^2>_Omega(q) = sum_lm |R^s_lm(q)|^2 / (4 pi), double
+ *              [n_states][n_q], or NULL
+ * Outputs are host (out_on_device = 0) or device buffers (1); the call
+ * returns when they are written.  SCFF_EINVAL for bad sizes or no output,
+ * SCFF_ESTATE before a molecule and transitions are loaded, SCFF_ENOMEM over
+ * the budget.
+ */
+int scff_eval_spherical(scff_ctx* ctx, int lmax, int n_q, const double* q, int n_theta, int n_phi, double* R,
+                        float* f, float* f2, double* avg, int out_on_device, void* hip_stream);
+
+/*
  * Separable integral (paper Sec. 5.3: integrals of the form
  * I = int d^3q f(q_x) g(q_y) h(q_z) f_S(q), evaluated from the 1D V-tensors
  * with a cost linear in the axis sizes instead of their product):

@@ -2,6 +2,7 @@
 // kernels, runtime).  Not part of the public ABI; see include/scarff.h.
 #pragma once
 
+#include <array>
 #include <cstddef>
 #include <cstdint>
 #include <functional>
@@ -188,6 +189,38 @@ hipError_t launch_fft_finish(const float2* Z, const int n[3], int ns, double vpi
                              float* f2, double* psum, long long* n_part, hipStream_t st);
 hipError_t launch_fft_sum(const double* part, int ns, long long n, double scale, double* out, int stride,
                           hipStream_t st);
+
+// ---- spherical method (sph_tables.cpp, sph.hip) ----
+// Polynomial degree of one geometry's D tensor (l_A + l_B <= 4 for d shells).
+constexpr int kSphMaxN = 4;
+// Gaunt entries per (lam mu, l m): L = |l - lam| + 2 j, j < 5.
+constexpr int kSphGauntJ = 5;
+constexpr int kSphMaxL = 48;   // largest lmax accepted
+struct SphIndex {
+    std::vector<std::array<int, 3>> nlm;   // (n, lam, mu) of the W tensor, n <= 4, lam = n, n-2, ...
+    std::vector<std::array<int, 3>> uvw;   // monomial powers with u + v + w <= 4
+};
+SphIndex sph_index();
+// Theta[uvw][nlm] complex (re, im), zero unless u + v + w = n.
+std::vector<double> sph_theta_table(const SphIndex& ix);
+// Gaunt[(lam mu)][(l m)][j], (lmax + 1)^2 harmonics l m, real.
+std::vector<double> sph_gaunt_table(int lmax);
+// One geometry (shell pair, primitive pair) of the spherical method.
+struct SphGeom {
+    int isp, pp;      // shell pair, primitive pair within it
+    int ncp, npp;     // component pairs and primitive pairs of the shell pair
+    int term0;        // first term of the shell pair
+};
+hipError_t launch_sph_geom(const SphGeom* geo, int n_geo, const VRowDev* rows, const int4* trow, const double* tp64,
+                           int ns, const double2* theta, const int* uvw_idx, const int* nfirst, int n_nlm, int Lmax,
+                           double4* gdat, double2* Yc, double2* W, hipStream_t st);
+hipError_t launch_sph_q(const double4* gdat, const double2* Yc, const double2* W, int n_geo, int ns, int Lmax,
+                        const int* nlm_of, int n_nlm, const double* qs, int n_q, double2* Q, hipStream_t st);
+hipError_t launch_sph_couple(const double2* Q, const double* gaunt, int ns, int lmax, int Lmax, int n_q, double2* R,
+                             hipStream_t st);
+hipError_t launch_sph_grid(const double2* R, int ns, int lmax, int n_q, int n_theta, int n_phi, double2* F,
+                           float2* f, float* f2, hipStream_t st);
+hipError_t launch_sph_avg(const double2* R, int ns, int lmax, int n_q, double* avg, hipStream_t st);
 
 // ---- runtime.cpp ----
 // Gate between stream capture and device-wide runtime calls.  Allocation and

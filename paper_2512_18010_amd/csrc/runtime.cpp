@@ -109,6 +109,12 @@ struct scff_ctx {
     // FFT method: packed weights, complex arrays of state pairs, partial
     // sums, Parseval sums, device copy of the density for host output
     DeviceBuffer d_fft_A, d_fft_Z, d_fft_part, d_fft_out, d_phi;
+    // spherical method: constant tables (for sph_lmax), geometries, per-geometry
+    // data, harmonics and W tensor, radii, contraction, R tensor, Legendre stage,
+    // angular average
+    DeviceBuffer d_sph_tab, d_sph_geo, d_sph_gdat, d_sph_Yc, d_sph_W, d_sph_q, d_sph_Q, d_sph_R, d_sph_F, d_sph_avg;
+    int sph_lmax = -1;
+    size_t sph_off[5] = {};   // theta, uvw index, nfirst, nlm_of, gaunt
     size_t lds_block = 65536;   // LDS bytes one workgroup may use
     void* scratch = nullptr;   // this device's static scratch array (scff_eval_grid_noalloc)
 };
@@ -428,7 +434,9 @@ int check_precision(int precision) {
 void free_all(scff_ctx* c) {
     for (DeviceBuffer* b : {&c->d_mol, &c->d_T, &c->d_vtab, &c->d_part, &c->d_f, &c->d_f2, &c->d_q,
                             &c->d_lq_in, &c->d_lq_S, &c->d_lq_G, &c->d_lq_out, &c->d_fft_A, &c->d_fft_Z,
-                            &c->d_fft_part, &c->d_fft_out, &c->d_phi})
+                            &c->d_fft_part, &c->d_fft_out, &c->d_phi, &c->d_sph_tab, &c->d_sph_geo,
+                            &c->d_sph_gdat, &c->d_sph_Yc, &c->d_sph_W, &c->d_sph_q, &c->d_sph_Q, &c->d_sph_R,
+                            &c->d_sph_F, &c->d_sph_avg})
         dev_free(c, *b);
     PrepWork& w = c->prep;
     for (DeviceBuffer* b : {&w.rows_all, &w.rowsum, &w.trow, &w.tbound, &w.wt, &w.cpmn, &w.tp64, &w.bsum,
@@ -1133,6 +1141,133 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, floa
         order_done(c);
     } else if ((rc = order_mark(c, st))) {
         return rc;
+    }
+    return ok();
+}
+
+int scff_eval_spherical(scff_ctx* c, int lmax, int n_q, const double* q, int n_theta, int n_phi, double* R,
+                        float* f, float* f2, double* avg, int out_on_device, void* hip_stream) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (lmax < 0 || lmax > kSphMaxL) return fail(SCFF_EINVAL, "lmax must be in 0..48");
+    if (n_q < 1 || n_q > 4096 || !q) return fail(SCFF_EINVAL, "n_q must be in 1..4096 and q non-NULL");
+    for (int i = 0; i < n_q; ++i)
+        if (!std::isfinite(q[i]) || q[i] < 0.0) return fail(SCFF_EINVAL, "radii must be finite and >= 0");
+    if ((f || f2) && (n_theta < 2 || n_theta > 4096 || n_phi < 1 || n_phi > 8192))
+        return fail(SCFF_EINVAL, "the angular grid needs 2..4096 polar and 1..8192 azimuthal points");
+    if (!R && !f && !f2 && !avg) return fail(SCFF_EINVAL, "no output requested");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((rc = order_after(c, st))) return rc;
+    if ((rc = ensure_prepared(c, st))) return rc;
+    const int ns = c->n_states, Lmax = lmax + kSphMaxN;
+    const int nl = (lmax + 1) * (lmax + 1), nL = (Lmax + 1) * (Lmax + 1);
+    // constant tables for this lmax
+    const SphIndex ix = sph_index();
+    const int n_nlm = (int)ix.nlm.size();
+    if (c->sph_lmax != lmax) {
+        const std::vector<double> th = sph_theta_table(ix);
+        const std::vector<double> ga = sph_gaunt_table(lmax);
+        std::vector<int> uvw_idx(125, -1), nfirst(kSphMaxN + 2, 0), nlm_of((kSphMaxN + 1) * 25, -1);
+        for (size_t a = 0; a < ix.uvw.size(); ++a)
+            uvw_idx[(ix.uvw[a][0] * (kSphMaxN + 1) + ix.uvw[a][1]) * (kSphMaxN + 1) + ix.uvw[a][2]] = (int)a;
+        for (int b = 0; b < n_nlm; ++b) {
+            const auto& e = ix.nlm[b];
+            nlm_of[e[0] * 25 + e[1] * e[1] + e[1] + e[2]] = b;
+            nfirst[e[0] + 1] = b + 1;
+        }
+        const size_t sz[5] = {th.size() * sizeof(double), uvw_idx.size() * sizeof(int), nfirst.size() * sizeof(int),
+                              nlm_of.size() * sizeof(int), ga.size() * sizeof(double)};
+        const void* src[5] = {th.data(), uvw_idx.data(), nfirst.data(), nlm_of.data(), ga.data()};
+        size_t total = 0;
+        for (int i = 0; i < 5; ++i) {
+            c->sph_off[i] = total;
+            total += (sz[i] + 255) & ~(size_t)255;
+        }
+        std::vector<unsigned char> stage(total, 0);
+        for (int i = 0; i < 5; ++i) std::memcpy(stage.data() + c->sph_off[i], src[i], sz[i]);
+        c->sph_lmax = -1;
+        if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
+        if ((rc = upload_sync(c, c->d_sph_tab, stage.data(), total))) return rc;
+        c->sph_lmax = lmax;
+    }
+    // geometries: every primitive pair of every shell pair
+    const Basis& b = c->basis;
+    std::vector<SphGeom> geo;
+    for (int isp = 0; isp < b.n_sp; ++isp) {
+        const int sA = b.sp[4 * isp], sB = b.sp[4 * isp + 1], term0 = b.sp[4 * isp + 3];
+        const int lA = b.sh_l[sA], lB = b.sh_l[sB];
+        const int ncA = (lA + 1) * (lA + 2) / 2, ncB = (lB + 1) * (lB + 2) / 2;
+        const int ncp = sA == sB ? ncA * (ncA + 1) / 2 : ncA * ncB;
+        const int npp = b.sh_nprim[sA] * b.sh_nprim[sB];
+        for (int pp = 0; pp < npp; ++pp) geo.push_back(SphGeom{isp, pp, ncp, npp, term0});
+    }
+    const int n_geo = (int)geo.size();
+    const size_t nrows = (size_t)ns * 25;
+    if ((rc = dev_reserve(c, c->d_sph_geo, geo.size() * sizeof(SphGeom))) ||
+        (rc = dev_reserve(c, c->d_sph_gdat, geo.size() * sizeof(double4))) ||
+        (rc = dev_reserve(c, c->d_sph_Yc, (size_t)n_geo * nL * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_sph_W, (size_t)n_geo * n_nlm * ns * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_sph_q, (size_t)n_q * sizeof(double))) ||
+        (rc = dev_reserve(c, c->d_sph_Q, (size_t)n_q * nrows * nL * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_sph_R, (size_t)ns * n_q * nl * sizeof(double2))))
+        return rc;
+    if ((f || f2) && (rc = dev_reserve(c, c->d_sph_F, (size_t)ns * n_q * n_theta * (2 * lmax + 1) * sizeof(double2))))
+        return rc;
+    if (avg && !out_on_device && (rc = dev_reserve(c, c->d_sph_avg, (size_t)ns * n_q * sizeof(double)))) return rc;
+    const size_t nout = (size_t)ns * n_q * (size_t)(f || f2 ? n_theta : 0) * (size_t)(f || f2 ? n_phi : 0);
+    float2* df = (float2*)f;
+    float* df2 = f2;
+    double2* dR = (double2*)c->d_sph_R.p;
+    double* davg = avg;
+    if (!out_on_device) {
+        if (f && (rc = dev_reserve(c, c->d_f, nout * sizeof(float2)))) return rc;
+        if (f2 && (rc = dev_reserve(c, c->d_f2, nout * sizeof(float)))) return rc;
+        df = f ? (float2*)c->d_f.p : nullptr;
+        df2 = f2 ? (float*)c->d_f2.p : nullptr;
+        davg = avg ? (double*)c->d_sph_avg.p : nullptr;
+    } else if (R) {
+        dR = (double2*)R;
+    }
+    const unsigned char* tb = (const unsigned char*)c->d_sph_tab.p;
+    if ((rc = hip_check(hipMemcpyAsync(c->d_sph_geo.p, geo.data(), geo.size() * sizeof(SphGeom),
+                                       hipMemcpyHostToDevice, st), "upload geometries")) ||
+        (rc = hip_check(hipMemcpyAsync(c->d_sph_q.p, q, (size_t)n_q * sizeof(double), hipMemcpyHostToDevice, st),
+                        "upload radii")))
+        return rc;
+    if ((rc = hip_check(launch_sph_geom((const SphGeom*)c->d_sph_geo.p, n_geo, (const VRowDev*)c->prep.rows_all.p,
+                                        (const int4*)c->prep.trow.p, (const double*)c->prep.tp64.p, ns,
+                                        (const double2*)(tb + c->sph_off[0]), (const int*)(tb + c->sph_off[1]),
+                                        (const int*)(tb + c->sph_off[2]), n_nlm, Lmax, (double4*)c->d_sph_gdat.p,
+                                        (double2*)c->d_sph_Yc.p, (double2*)c->d_sph_W.p, st),
+                        "spherical geometry kernel")) ||
+        (rc = hip_check(launch_sph_q((const double4*)c->d_sph_gdat.p, (const double2*)c->d_sph_Yc.p,
+                                     (const double2*)c->d_sph_W.p, n_geo, ns, Lmax, (const int*)(tb + c->sph_off[3]),
+                                     n_nlm, (const double*)c->d_sph_q.p, n_q, (double2*)c->d_sph_Q.p, st),
+                        "spherical contraction kernel")) ||
+        (rc = hip_check(launch_sph_couple((const double2*)c->d_sph_Q.p, (const double*)(tb + c->sph_off[4]), ns, lmax,
+                                          Lmax, n_q, dR, st),
+                        "spherical coupling kernel")))
+        return rc;
+    if (davg && (rc = hip_check(launch_sph_avg(dR, ns, lmax, n_q, davg, st), "angular average kernel"))) return rc;
+    if ((f || f2) && (rc = hip_check(launch_sph_grid(dR, ns, lmax, n_q, n_theta, n_phi, (double2*)c->d_sph_F.p, df,
+                                                     df2, st),
+                                     "spherical grid kernels")))
+        return rc;
+    if (!out_on_device) {
+        if ((rc = copy_out(df, f, df2, f2, nout, st))) return rc;
+        if (R && (rc = hip_check(hipMemcpyAsync(R, dR, (size_t)ns * n_q * nl * sizeof(double2), hipMemcpyDeviceToHost,
+                                                st), "D2H R")))
+            return rc;
+        if (avg && (rc = hip_check(hipMemcpyAsync(avg, davg, (size_t)ns * n_q * sizeof(double), hipMemcpyDeviceToHost,
+                                                  st), "D2H average")))
+            return rc;
+        if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
+        order_done(c);
+    } else {
+        // host arrays (geometries, radii) were read by asynchronous copies: wait
+        if ((rc = hip_check(hipStreamSynchronize(st), "stream sync"))) return rc;
+        order_done(c);
     }
     return ok();
 }

@@ -1,0 +1,422 @@
+// The spherical method (paper Sec. 4 eqs. DTensor, WTensor, YYY,
+// SphericalMethod, RTensor; Sec. 5.4; App. B) on the device, FP64:
+//
+//   sph_geom_kernel    per geometry g (a primitive pair of a shell pair, so
+//                      one Gaussian centre P_g and exponent p_g): the
+//                      W tensor summed over the geometry's component pairs
+//                      with their packed transition weights,
+//                        W^s_g[n lam mu] = sum_c Tp_s(c) sum_{u+v+w=n} D_c^{uvw} Theta^{uvw}_{lam mu},
+//                      D_c^{uvw} = i^n e^x_u e^y_v e^z_w from the 1D rows of the
+//                      pair precompute; and Y_L^M*(P^_g) for L <= lmax + 4;
+//   sph_q_kernel       for each radius q, the contraction over geometries
+//                        Q^s[lam mu][L M](q) = sum_g b^s_g[lam mu](q) a_g[L M](q),
+//                        b = e^{-q^2/4p} sum_n q^n W^s_g[n lam mu],
+//                        a = 4 pi i^L j_L(q |P_g|) Y_L^M*(P^_g),
+//                      a complex GEMM (rows: state x (lam mu), columns:
+//                      (L M), k: geometries) tiled in LDS, with the spherical
+//                      Bessel functions by Miller's downward recurrence;
+//   sph_couple_kernel  R^s_lm(q) = sum_{lam mu, L} G^{mu, m-mu}_{lam L l} Q^s[lam mu][L, m-mu]
+//                      (eq. RTensor with the Gaunt coefficients of eq. YYY);
+//   sph_legendre_kernel / sph_phi_kernel
+//                      the angular grid f^s(q, theta_i, phi_j) = sum_lm R_lm Y_l^m
+//                      (eq. SphericalMethod) as a Legendre stage per theta and a
+//                      Fourier stage per phi; sph_avg_kernel <|f|^2>_Omega.
+#include <hip/hip_runtime.h>
+
+#include "engine.h"
+
+namespace scff {
+
+namespace {
+
+constexpr int kLam = (kSphMaxN + 1) * (kSphMaxN + 1);   // 25 harmonics lam <= 4
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// i^n
+__device__ __forceinline__ double2 ipow(int n) {
+    switch (n & 3) {
+        case 0: return make_double2(1.0, 0.0);
+        case 1: return make_double2(0.0, 1.0);
+        case 2: return make_double2(-1.0, 0.0);
+        default: return make_double2(0.0, -1.0);
+    }
+}
+
+// Y_L^M*(theta, phi) for L <= Lmax into out[L^2 + L + M] (Condon-Shortley,
+// orthonormal; associated Legendre functions by upward recurrence in L).
+__device__ void ylm_conj_row(int Lmax, double theta, double phi, double2* out) {
+    double sn, cs;
+    sincos(theta, &sn, &cs);
+    double pmm = sqrt(1.0 / (4.0 * M_PI));
+    for (int m = 0; m <= Lmax; ++m) {
+        if (m > 0) pmm *= -sqrt((2.0 * m + 1.0) / (2.0 * m)) * sn;
+        double es, ec;
+        sincos(m * phi, &es, &ec);
+        double p2 = 0.0, p1 = pmm;
+        for (int l = m; l <= Lmax; ++l) {
+            double cur;
+            if (l == m) {
+                cur = pmm;
+            } else if (l == m + 1) {
+                cur = sqrt(2.0 * m + 3.0) * cs * pmm;
+            } else {
+                const double a = sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+                const double b = sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+                cur = a * (cs * p1 - b * p2);
+            }
+            if (l > m) {
+                p2 = p1;
+                p1 = cur;
+            }
+            // conj(Y_l^m) = cur e^{-i m phi};  conj(Y_l^{-m}) = (-1)^m cur e^{+i m phi}
+            out[l * l + l + m] = make_double2(cur * ec, -cur * es);
+            if (m > 0) {
+                const double sg = (m & 1) ? -1.0 : 1.0;
+                out[l * l + l - m] = make_double2(sg * cur * ec, sg * cur * es);
+            }
+        }
+    }
+}
+
+// Spherical Bessel functions j_L(x) for L in [L0, L1] into out[L - L0],
+// FP64: Miller's downward recurrence j_{L-1} = (2L+1)/x j_L - j_{L+1} from
+// far above max(L1, x), normalised with j_0 = sin x / x or j_1 (whichever is
+// larger); the two-term power series below x = 1e-4.
+__device__ void bessel_range(double x, int L0, int L1, double* out) {
+    if (x < 1e-4) {
+        double df = 1.0;   // (2L+1)!!
+        double xl = 1.0;   // x^L
+        for (int L = 0; L <= L1; ++L) {
+            if (L > 0) {
+                df *= 2.0 * L + 1.0;
+                xl *= x;
+            }
+            if (L >= L0) out[L - L0] = xl / df * (1.0 - x * x / (2.0 * (2.0 * L + 3.0)));
+        }
+        return;
+    }
+    const int N = max(L1, (int)x) + 32;
+    double fp = 0.0, f = 1e-280, f0 = 0.0, f1 = 0.0;
+    for (int L = N; L >= 1; --L) {
+        const double fm = (2.0 * L + 1.0) / x * f - fp;   // f_{L-1}
+        fp = f;
+        f = fm;
+        if (L - 1 >= L0 && L - 1 <= L1) out[L - 1 - L0] = f;
+        if (L - 1 == 1) f1 = f;
+        if (fabs(f) > 1e250) {   // rescale everything kept so far
+            f *= 1e-250;
+            fp *= 1e-250;
+            f1 *= 1e-250;
+            for (int k = max(L - 1, L0); k <= L1; ++k) out[k - L0] *= 1e-250;
+        }
+    }
+    f0 = f;
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    const double j0 = sn / x, j1 = sn / (x * x) - cs / x;
+    const double scale = fabs(j0) >= fabs(j1) ? j0 / f0 : j1 / f1;
+    for (int L = L0; L <= L1; ++L) out[L - L0] *= scale;
+}
+
+__global__ __launch_bounds__(128) void sph_geom_kernel(const SphGeom* __restrict__ geo, int n_geo,
+                                                       const VRowDev* __restrict__ rows,
+                                                       const int4* __restrict__ trow,
+                                                       const double* __restrict__ tp64, int ns,
+                                                       const double2* __restrict__ theta, const int* __restrict__ uvw_idx,
+                                                       const int* __restrict__ nfirst, int n_nlm, int Lmax,
+                                                       double4* __restrict__ gdat, double2* __restrict__ Yc,
+                                                       double2* __restrict__ W) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_geo) return;
+    const SphGeom G = geo[g];
+    double2* Wg = W + (size_t)g * n_nlm * ns;
+    for (int i = 0; i < n_nlm * ns; ++i) Wg[i] = make_double2(0.0, 0.0);
+    const int4 t0 = trow[G.term0 + G.pp];
+    const double Px = rows[t0.x].P, Py = rows[t0.y].P, Pz = rows[t0.z].P;
+    const double d = sqrt(Px * Px + Py * Py + Pz * Pz);
+    const double th = d > 0.0 ? acos(fmin(1.0, fmax(-1.0, Pz / d))) : 0.0;
+    const double ph = d > 0.0 ? atan2(Py, Px) : 0.0;
+    gdat[g] = make_double4(d, th, ph, rows[t0.x].inv4p);
+    ylm_conj_row(Lmax, th, ph, Yc + (size_t)g * (Lmax + 1) * (Lmax + 1));
+    for (int c = 0; c < G.ncp; ++c) {
+        const int4 tr = trow[G.term0 + c * G.npp + G.pp];
+        const VRowDev& rx = rows[tr.x];
+        const VRowDev& ry = rows[tr.y];
+        const VRowDev& rz = rows[tr.z];
+        const double* tp = tp64 + (size_t)tr.w * ns;
+        for (int u = 0; u <= rx.deg; ++u)
+            for (int v = 0; v <= ry.deg; ++v)
+                for (int w = 0; w <= rz.deg; ++w) {
+                    const double e = rx.e[u] * ry.e[v] * rz.e[w];
+                    if (e == 0.0) continue;
+                    const int n = u + v + w;
+                    const int a = uvw_idx[(u * (kSphMaxN + 1) + v) * (kSphMaxN + 1) + w];
+                    const double2 coef = cscale(ipow(n), e);
+                    for (int b = nfirst[n]; b < nfirst[n + 1]; ++b) {
+                        const double2 th_ab = theta[(size_t)a * n_nlm + b];
+                        if (th_ab.x == 0.0 && th_ab.y == 0.0) continue;
+                        const double2 x = cmul(coef, th_ab);
+                        for (int s = 0; s < ns; ++s) {
+                            double2& o = Wg[(size_t)b * ns + s];
+                            o.x += tp[s] * x.x;
+                            o.y += tp[s] * x.y;
+                        }
+                    }
+                }
+    }
+}
+
+// Tile: 32 rows (state, lam mu) x 64 columns (L M) per workgroup, all
+// geometries in chunks of 32; thread (ty, tx) holds rows 2 ty + {0, 1} and
+// columns 4 tx + {0..3}.
+constexpr int kQRows = 32, kQCols = 64, kQK = 32, kQLspan = 10;
+
+__global__ __launch_bounds__(256) void sph_q_kernel(const double4* __restrict__ gdat, const double2* __restrict__ Yc,
+                                                    const double2* __restrict__ W, int n_geo, int ns, int Lmax,
+                                                    const int* __restrict__ nlm_of, int n_nlm,
+                                                    const double* __restrict__ qs, double2* __restrict__ Q) {
+    __shared__ double2 Bs[kQRows][kQK + 1];
+    __shared__ double2 As[kQK][kQCols + 1];
+    __shared__ double jt[kQK][kQLspan];
+    __shared__ double4 gd[kQK];
+    const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+    const int nrows = ns * kLam, ncols = (Lmax + 1) * (Lmax + 1);
+    const int r0 = blockIdx.y * kQRows, c0 = blockIdx.x * kQCols;
+    const int iq = blockIdx.z;
+    const double q = qs[iq];
+    const int cl = min(c0 + kQCols, ncols) - 1;
+    const int Lmin = (int)sqrt((double)c0 + 0.5), Lhi = (int)sqrt((double)cl + 0.5);
+    double2 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    for (int g0 = 0; g0 < n_geo; g0 += kQK) {
+        if (tid < kQK) {
+            const int g = g0 + tid;
+            if (g < n_geo) {
+                const double4 gg = gdat[g];
+                gd[tid] = gg;
+                bessel_range(q * gg.x, Lmin, Lhi, jt[tid]);
+            }
+        }
+        __syncthreads();
+        // B: rows (state, lam mu) x geometries
+        for (int e = tid; e < kQRows * kQK; e += 256) {
+            const int row = e / kQK, gg = e - row * kQK;
+            const int r = r0 + row, g = g0 + gg;
+            double2 b = make_double2(0.0, 0.0);
+            if (r < nrows && g < n_geo) {
+                const int s = r / kLam, lm = r - s * kLam;
+                const int lam = (int)sqrt((double)lm + 0.5);
+                const double2* Wg = W + (size_t)g * n_nlm * ns;
+                double qn = 1.0;
+                for (int n = 0; n <= kSphMaxN; ++n) {
+                    if (n >= lam && ((n - lam) & 1) == 0) {
+                        const int b_i = nlm_of[n * kLam + lm];
+                        const double2 w = Wg[(size_t)b_i * ns + s];
+                        b.x += qn * w.x;
+                        b.y += qn * w.y;
+                    }
+                    qn *= q;
+                }
+                b = cscale(b, exp(-q * q * gd[gg].w));
+            }
+            Bs[row][gg] = b;
+        }
+        // A: geometries x (L M)
+        for (int e = tid; e < kQK * kQCols; e += 256) {
+            const int gg = e / kQCols, cc = e - gg * kQCols;
+            const int col = c0 + cc, g = g0 + gg;
+            double2 a = make_double2(0.0, 0.0);
+            if (col < ncols && g < n_geo) {
+                const int L = (int)sqrt((double)col + 0.5);
+                const double jl = jt[gg][L - Lmin] * 4.0 * M_PI;
+                a = cmul(cscale(ipow(L), jl), Yc[(size_t)g * ncols + col]);
+            }
+            As[gg][cc] = a;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < kQK; ++k) {
+            const double2 b0 = Bs[2 * ty][k], b1 = Bs[2 * ty + 1][k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double2 a = As[k][4 * tx + j];
+                acc[0][j].x += b0.x * a.x - b0.y * a.y;
+                acc[0][j].y += b0.x * a.y + b0.y * a.x;
+                acc[1][j].x += b1.x * a.x - b1.y * a.y;
+                acc[1][j].y += b1.x * a.y + b1.y * a.x;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + 2 * ty + i, col = c0 + 4 * tx + j;
+            if (r < nrows && col < ncols) Q[((size_t)iq * nrows + r) * ncols + col] = acc[i][j];
+        }
+}
+
+__global__ void sph_couple_kernel(const double2* __restrict__ Q, const double* __restrict__ gaunt, int ns, int lmax,
+                                  int Lmax, int n_q, double2* __restrict__ R) {
+    const int nl = (lmax + 1) * (lmax + 1), ncols = (Lmax + 1) * (Lmax + 1), nrows = ns * kLam;
+    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx >= (long long)ns * n_q * nl) return;
+    const int lm = (int)(idx % nl);
+    const long long r1 = idx / nl;
+    const int iq = (int)(r1 % n_q), s = (int)(r1 / n_q);
+    const int l = (int)sqrt((double)lm + 0.5), m = lm - l * l - l;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int lam = 0; lam <= kSphMaxN; ++lam)
+        for (int mu = -lam; mu <= lam; ++mu) {
+            const int li = lam * lam + lam + mu;
+            const double2* Qr = Q + ((size_t)iq * nrows + s * kLam + li) * ncols;
+            const double* gr = gaunt + ((size_t)li * nl + lm) * kSphGauntJ;
+            const int M = m - mu;
+            for (int j = 0; j < kSphGauntJ; ++j) {
+                const int L = abs(l - lam) + 2 * j;
+                if (L > l + lam || abs(M) > L) continue;
+                const double gv = gr[j];
+                const double2 qv = Qr[L * L + L + M];
+                acc.x += gv * qv.x;
+                acc.y += gv * qv.y;
+            }
+        }
+    R[((size_t)s * n_q + iq) * nl + lm] = acc;
+}
+
+// F^s(q, theta_i, m) = sum_{l >= |m|} R^s_lm(q) P~_l^m(cos theta_i), with
+// Y_l^m = P~_l^m(cos theta) e^{i m phi} (P~ the normalised associated Legendre
+// function with the Condon-Shortley phase; P~_l^{-m} = (-1)^m P~_l^m).
+__global__ void sph_legendre_kernel(const double2* __restrict__ R, int ns, int lmax, int n_q, int n_theta,
+                                    double2* __restrict__ F) {
+    const int nm = 2 * lmax + 1, nl = (lmax + 1) * (lmax + 1);
+    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx >= (long long)n_q * n_theta * nm) return;
+    const int mi = (int)(idx % nm);
+    const long long r1 = idx / nm;
+    const int it = (int)(r1 % n_theta), iq = (int)(r1 / n_theta);
+    const int m = mi - lmax, am = abs(m);
+    const double theta = n_theta > 1 ? M_PI * it / (n_theta - 1) : 0.0;
+    double sn, cs;
+    sincos(theta, &sn, &cs);
+    double pmm = sqrt(1.0 / (4.0 * M_PI));
+    for (int k = 1; k <= am; ++k) pmm *= -sqrt((2.0 * k + 1.0) / (2.0 * k)) * sn;
+    const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
+    for (int s = 0; s < ns; ++s) {
+        const double2* Rs = R + ((size_t)s * n_q + iq) * nl;
+        double2 acc = make_double2(0.0, 0.0);
+        double p2 = 0.0, p1 = pmm;
+        for (int l = am; l <= lmax; ++l) {
+            double cur;
+            if (l == am) {
+                cur = pmm;
+            } else if (l == am + 1) {
+                cur = sqrt(2.0 * am + 3.0) * cs * pmm;
+            } else {
+                const double a = sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)am * am));
+                const double b = sqrt(((l - 1.0) * (l - 1.0) - (double)am * am) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+                cur = a * (cs * p1 - b * p2);
+            }
+            if (l > am) {
+                p2 = p1;
+                p1 = cur;
+            }
+            const double2 r = Rs[l * l + l + m];
+            acc.x += sg * cur * r.x;
+            acc.y += sg * cur * r.y;
+        }
+        F[(((size_t)s * n_q + iq) * n_theta + it) * nm + mi] = acc;
+    }
+}
+
+// f^s(q, theta_i, phi_j) = sum_m F^s(q, theta_i, m) e^{i m phi_j}, phi_j = 2 pi j / n_phi.
+__global__ void sph_phi_kernel(const double2* __restrict__ F, int ns, int lmax, int n_q, int n_theta, int n_phi,
+                               float2* __restrict__ f, float* __restrict__ f2) {
+    const int nm = 2 * lmax + 1;
+    const long long npts = (long long)n_q * n_theta * n_phi;
+    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx >= npts) return;
+    const int jp = (int)(idx % n_phi);
+    const long long r1 = idx / n_phi;   // q, theta
+    const double phi = 2.0 * M_PI * jp / n_phi;
+    for (int s = 0; s < ns; ++s) {
+        const double2* Fs = F + ((size_t)s * n_q * n_theta + r1) * nm;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int mi = 0; mi < nm; ++mi) {
+            double es, ec;
+            sincos((mi - lmax) * phi, &es, &ec);
+            const double2 v = Fs[mi];
+            acc.x += v.x * ec - v.y * es;
+            acc.y += v.x * es + v.y * ec;
+        }
+        const size_t o = (size_t)s * npts + idx;
+        if (f) f[o] = make_float2((float)acc.x, (float)acc.y);
+        if (f2) f2[o] = (float)(acc.x * acc.x + acc.y * acc.y);
+    }
+}
+
+__global__ void sph_avg_kernel(const double2* __restrict__ R, int ns, int lmax, int n_q, double* __restrict__ avg) {
+    const int nl = (lmax + 1) * (lmax + 1);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ns * n_q) return;
+    const double2* Rs = R + (size_t)idx * nl;
+    double a = 0.0;
+    for (int i = 0; i < nl; ++i) a += Rs[i].x * Rs[i].x + Rs[i].y * Rs[i].y;
+    avg[idx] = a / (4.0 * M_PI);
+}
+
+}  // namespace
+
+hipError_t launch_sph_geom(const SphGeom* geo, int n_geo, const VRowDev* rows, const int4* trow, const double* tp64,
+                           int ns, const double2* theta, const int* uvw_idx, const int* nfirst, int n_nlm, int Lmax,
+                           double4* gdat, double2* Yc, double2* W, hipStream_t st) {
+    if (n_geo <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sph_geom_kernel, dim3((n_geo + 127) / 128), dim3(128), 0, st, geo, n_geo, rows, trow, tp64, ns,
+                       theta, uvw_idx, nfirst, n_nlm, Lmax, gdat, Yc, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_q(const double4* gdat, const double2* Yc, const double2* W, int n_geo, int ns, int Lmax,
+                        const int* nlm_of, int n_nlm, const double* qs, int n_q, double2* Q, hipStream_t st) {
+    const int nrows = ns * kLam, ncols = (Lmax + 1) * (Lmax + 1);
+    // the Bessel span of one column block: 64 consecutive (L M) cover at most 8 values of L
+    dim3 grid((ncols + kQCols - 1) / kQCols, (nrows + kQRows - 1) / kQRows, n_q);
+    hipLaunchKernelGGL(sph_q_kernel, grid, dim3(256), 0, st, gdat, Yc, W, n_geo, ns, Lmax, nlm_of, n_nlm, qs, Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_couple(const double2* Q, const double* gaunt, int ns, int lmax, int Lmax, int n_q, double2* R,
+                             hipStream_t st) {
+    const long long n = (long long)ns * n_q * (lmax + 1) * (lmax + 1);
+    hipLaunchKernelGGL(sph_couple_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Q, gaunt, ns, lmax, Lmax,
+                       n_q, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_grid(const double2* R, int ns, int lmax, int n_q, int n_theta, int n_phi, double2* F, float2* f,
+                           float* f2, hipStream_t st) {
+    const long long n1 = (long long)n_q * n_theta * (2 * lmax + 1);
+    hipLaunchKernelGGL(sph_legendre_kernel, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, R, ns, lmax, n_q,
+                       n_theta, F);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long n2 = (long long)n_q * n_theta * n_phi;
+    hipLaunchKernelGGL(sph_phi_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, F, ns, lmax, n_q, n_theta,
+                       n_phi, f, f2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_avg(const double2* R, int ns, int lmax, int n_q, double* avg, hipStream_t st) {
+    const int n = ns * n_q;
+    hipLaunchKernelGGL(sph_avg_kernel, dim3((n + 255) / 256), dim3(256), 0, st, R, ns, lmax, n_q, avg);
+    return hipGetLastError();
+}
+
+}  // namespace scff
