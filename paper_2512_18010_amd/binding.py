@@ -115,6 +115,9 @@ scff_eval_separable = _fn("scff_eval_separable", c_int,
                           [c_void_p, P(scff_grid), P(c_double), P(c_double), P(c_double), P(c_double)])
 scff_eval_fft = _fn("scff_eval_fft", c_int,
                     [c_void_p, P(scff_fft_grid), c_void_p, c_void_p, c_void_p, P(c_double), c_int, c_void_p])
+scff_eval_spherical = _fn("scff_eval_spherical", c_int,
+                          [c_void_p, c_int, c_int, P(c_double), c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                           c_int, c_void_p])
 scff_last_fft_timing = _fn("scff_last_fft_timing", c_int, [c_void_p, P(c_float), P(c_float), P(c_float)])
 scff_dipole = _fn("scff_dipole", c_int, [c_void_p, P(c_double), P(c_double), P(c_double)])
 scff_dipole_fit = _fn("scff_dipole_fit", c_int, [c_void_p, c_double, P(c_double), P(c_double), P(c_double)])
@@ -350,6 +353,45 @@ class Context:
                             f2.data_ptr() if f2 is not None else None,
                             phi.data_ptr() if phi is not None else None, None, 1, _stream_ptr(stream)))
         return f, f2, phi
+
+    def eval_spherical_host(self, lmax, qs, n_theta=0, n_phi=0, want_R=True, want_f=False, want_f2=False,
+                            want_avg=True):
+        """Spherical method (host outputs): (R complex128 [s, n_q, (lmax+1)^2] or None,
+        f complex64 [s, n_q, n_theta, n_phi] or None, f2 or None, avg float64 [s, n_q] or None)."""
+        qs = np.ascontiguousarray(np.asarray(qs, np.float64).reshape(-1))
+        ns, nq, nl = self.n_states, qs.shape[0], (int(lmax) + 1) ** 2
+        R = np.empty((ns, nq, nl, 2), np.float64) if want_R else None
+        f = np.empty((ns, nq, n_theta, n_phi, 2), np.float32) if want_f else None
+        f2 = np.empty((ns, nq, n_theta, n_phi), np.float32) if want_f2 else None
+        avg = np.empty((ns, nq), np.float64) if want_avg else None
+        check(scff_eval_spherical(self._h, int(lmax), nq, _d(qs), int(n_theta), int(n_phi),
+                                  R.ctypes.data if R is not None else None,
+                                  f.ctypes.data if f is not None else None,
+                                  f2.ctypes.data if f2 is not None else None,
+                                  avg.ctypes.data if avg is not None else None, 0, None))
+        return ((R[..., 0] + 1j * R[..., 1]) if R is not None else None,
+                (f.view(np.complex64)[..., 0] if f is not None else None), f2, avg)
+
+    def eval_spherical_device(self, lmax, qs, n_theta, n_phi, f=None, f2=None, R=None, avg=None, stream=None):
+        """Spherical method into torch tensors: f [s,n_q,n_theta,n_phi,2] / f2 [s,n_q,n_theta,n_phi] float32,
+        R [s,n_q,(lmax+1)^2,2] / avg [s,n_q] float64."""
+        import torch
+        qs = np.ascontiguousarray(np.asarray(qs, np.float64).reshape(-1))
+        ns, nq, nl = self.n_states, qs.shape[0], (int(lmax) + 1) ** 2
+        if f is not None:
+            _check_device_tensor(f, "f", torch.float32, (ns, nq, n_theta, n_phi, 2), self.device)
+        if f2 is not None:
+            _check_device_tensor(f2, "f2", torch.float32, (ns, nq, n_theta, n_phi), self.device)
+        if R is not None:
+            _check_device_tensor(R, "R", torch.float64, (ns, nq, nl, 2), self.device)
+        if avg is not None:
+            _check_device_tensor(avg, "avg", torch.float64, (ns, nq), self.device)
+        check(scff_eval_spherical(self._h, int(lmax), nq, _d(qs), int(n_theta), int(n_phi),
+                                  R.data_ptr() if R is not None else None,
+                                  f.data_ptr() if f is not None else None,
+                                  f2.data_ptr() if f2 is not None else None,
+                                  avg.data_ptr() if avg is not None else None, 1, _stream_ptr(stream)))
+        return f, f2, R, avg
 
     def last_fft_timing(self):
         """(pack_ms, density_ms, transform_ms) of the last timed FFT evaluation."""
