@@ -337,6 +337,73 @@ def fft_benchmark(ctx, stream, n_axis, steps, warmup, log):
     }
 
 
+def sph_benchmark(ctx, stream, lmax, n, steps, warmup, log):
+    """Spherical method on the config-1 molecule and its 12 transitions: R_lm
+    up to lmax on n radii in (0, 6] a.u. and f on n x n angles per radius
+    (n^3 q-points).  One step = molecule load + T from HBM + pair precompute +
+    geometry kernel + contraction + coupling + angular grid, outputs in HBM."""
+    import torch
+    import workload as wl
+    W = wl.make_config(1)
+    ns = W.T.shape[0]
+    qs = 6.0 * np.arange(1, n + 1) / n
+    nl = (lmax + 1) ** 2
+    T_dev = torch.from_numpy(np.ascontiguousarray(W.T)).cuda()
+    f = torch.empty((ns, n, n, n, 2), dtype=torch.float32, device="cuda")
+    f2 = torch.empty((ns, n, n, n), dtype=torch.float32, device="cuda")
+    R = torch.empty((ns, n, nl, 2), dtype=torch.float64, device="cuda")
+    avg = torch.empty((ns, n), dtype=torch.float64, device="cuda")
+
+    def step():
+        ctx.load_molecule(W.mol)
+        ctx.load_transitions_device(T_dev, stream)
+        ctx.set_options(0.0, 1.0)
+        ctx.eval_spherical_device(lmax, qs, n, n, f, f2, R, avg, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    st = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        st.append(ctx.last_sph_timing())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    st = np.array(st)
+    geom_ms, con_ms, rest_ms = (float(np.mean(st[:, i])) for i in range(3))
+    # check: R on one radius against the oracle's projection (the GPU tests cover the rest)
+    import oracle
+    k = max(0, n // 8 - 1)
+    rmax = float(np.linalg.norm(W.mol.xyz, axis=1).max()) + 3.0
+    nt = int((lmax + np.e * qs[k] * rmax / 2 + 24) / 2) + 2
+    Rref = oracle.spherical_R(W.mol, W.T, [qs[k]], lmax, nt, n_threads=min(16, os.cpu_count() or 1))[:, 0, :]
+    Rg = R[:, k].cpu().numpy()
+    Rg = Rg[..., 0] + 1j * Rg[..., 1]
+    e_R = np.abs(Rg - Rref).max(axis=1) / np.abs(Rref).max(axis=1)
+    n_geo = int(sum(int(W.mol.shell_nprim[a]) * int(W.mol.shell_nprim[b])
+                    for a in range(W.mol.n_shells) for b in range(a, W.mol.n_shells)))
+    ncols = (lmax + 5) ** 2
+    flops = 8.0 * ns * 25 * ncols * n_geo * n
+    del T_dev, f, f2, R, avg
+    log(f"spherical method lmax {lmax}, {n}^3: {ms:.2f} ms/step, contraction {con_ms:.2f} ms "
+        f"({flops / con_ms / 1e9:.1f} TFLOP/s FP64), geometry {geom_ms:.2f} ms, rest {rest_ms:.2f} ms, "
+        f"R error {e_R.max():.1e}")
+    return {
+        "workload": f"{W.name}; lmax {lmax}, {n} radii in (0, 6] x {n} polar x {n} azimuthal angles",
+        "lmax": lmax, "n_radii": n, "n_theta": n, "n_phi": n, "geometries": n_geo,
+        "steps": steps, "ms_per_step": ms,
+        "value": ns * n ** 3 / (ms * 1e-3), "unit": "q-points*transitions/s",
+        "stages_ms": {"geometry": geom_ms, "contraction": con_ms, "coupling_and_grid": rest_ms},
+        "roofline": {"bound": "fp64", "kernel": "sph_q_kernel", "achieved": flops / (con_ms * 1e-3) / 1e12,
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": flops / (con_ms * 1e-3) / 78.6e12,
+                     "per_unit": "8 flops per (transition, harmonic lam mu <= 4, harmonic L M <= lmax + 4, "
+                                 "geometry, radius): one complex multiply-add of the contraction over geometries"},
+        "errors_vs_oracle": {"R_relative_max": float(e_R.max()), "R_per_transition": [float(x) for x in e_R],
+                             "radius": float(qs[k])},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +425,10 @@ def main():
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the FFT-method leg (190 bf, 12 transitions, 128^3 real-space box)")
     ap.add_argument("--fft-n", type=int, default=128, help="real-space points per axis of the FFT-method leg")
+    ap.add_argument("--no-sph", action="store_true",
+                    help="skip the spherical-method leg (190 bf, 12 transitions, lmax 24, 64 radii x 64 x 64 angles)")
+    ap.add_argument("--sph-lmax", type=int, default=24)
+    ap.add_argument("--sph-n", type=int, default=64, help="radii, polar and azimuthal points of the spherical leg")
     ap.add_argument("--no-symmetric", action="store_true",
                     help="skip the symmetric-grid measurement (f(-q) = f(q)*, half the planes evaluated)")
     ap.add_argument("--serve-pool", type=int, default=24, help="distinct requests in the serving pool")
@@ -518,6 +589,11 @@ def main():
     if not args.no_fft:
         fft_leg = fft_benchmark(ctx, stream, args.fft_n, max(5, args.steps // 2), 2, log)
 
+    # ---- spherical method (Sec. 4, Sec. 5.4): config-1 molecule and transitions
+    sph_leg = None
+    if not args.no_sph:
+        sph_leg = sph_benchmark(ctx, stream, args.sph_lmax, args.sph_n, max(3, args.steps // 4), 1, log)
+
     serving = None
     if not args.no_serving:
         serving = []
@@ -571,6 +647,7 @@ def main():
         "symmetric_grid": symmetric,
         "serving": serving,
         "fft_method": fft_leg,
+        "spherical_method": sph_leg,
     }
     print(json.dumps(out))
 

@@ -334,6 +334,13 @@ int scff_last_fft_timing(scff_ctx* ctx, float* pack_ms, float* density_ms, float
 int scff_eval_spherical(scff_ctx* ctx, int lmax, int n_q, const double* q, int n_theta, int n_phi, double* R,
                         float* f, float* f2, double* avg, int out_on_device, void* hip_stream);
 
+/* With scff_set_timing(ctx, 1): HIP-event durations (ms) of the last
+ * scff_eval_spherical's geometry kernel (W tensor and harmonics of the
+ * centres), contraction over geometries, and the rest (Gaunt coupling,
+ * angular average, angular grid); waits for them.  SCFF_ESTATE if no timed
+ * spherical evaluation was recorded. */
+int scff_last_sph_timing(scff_ctx* ctx, float* geom_ms, float* contraction_ms, float* rest_ms);
+
 /*
  * Separable integral (paper Sec. 5.3: integrals of the form
  * I = int d^3q f(q_x) g(q_y) h(q_z) f_S(q), evaluated from the 1D V-tensors

@@ -118,6 +118,7 @@ scff_eval_fft = _fn("scff_eval_fft", c_int,
 scff_eval_spherical = _fn("scff_eval_spherical", c_int,
                           [c_void_p, c_int, c_int, P(c_double), c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                            c_int, c_void_p])
+scff_last_sph_timing = _fn("scff_last_sph_timing", c_int, [c_void_p, P(c_float), P(c_float), P(c_float)])
 scff_last_fft_timing = _fn("scff_last_fft_timing", c_int, [c_void_p, P(c_float), P(c_float), P(c_float)])
 scff_dipole = _fn("scff_dipole", c_int, [c_void_p, P(c_double), P(c_double), P(c_double)])
 scff_dipole_fit = _fn("scff_dipole_fit", c_int, [c_void_p, c_double, P(c_double), P(c_double), P(c_double)])
@@ -392,6 +393,12 @@ class Context:
                                   f2.data_ptr() if f2 is not None else None,
                                   avg.data_ptr() if avg is not None else None, 1, _stream_ptr(stream)))
         return f, f2, R, avg
+
+    def last_sph_timing(self):
+        """(geom_ms, contraction_ms, rest_ms) of the last timed spherical evaluation."""
+        a, b, t = c_float(), c_float(), c_float()
+        check(scff_last_sph_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)))
+        return a.value, b.value, t.value
 
     def last_fft_timing(self):
         """(pack_ms, density_ms, transform_ms) of the last timed FFT evaluation."""

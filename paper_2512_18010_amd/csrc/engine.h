@@ -215,7 +215,8 @@ hipError_t launch_sph_geom(const SphGeom* geo, int n_geo, const VRowDev* rows, c
                            int ns, const double2* theta, const int* uvw_idx, const int* nfirst, int n_nlm, int Lmax,
                            double4* gdat, double2* Yc, double2* W, hipStream_t st);
 hipError_t launch_sph_q(const double4* gdat, const double2* Yc, const double2* W, int n_geo, int ns, int Lmax,
-                        const int* nlm_of, int n_nlm, const double* qs, int n_q, double2* Q, hipStream_t st);
+                        const int* nlm_of, int n_nlm, const double* qs, int n_q, double* J, double2* Q,
+                        hipStream_t st);
 hipError_t launch_sph_couple(const double2* Q, const double* gaunt, int ns, int lmax, int Lmax, int n_q, double2* R,
                              hipStream_t st);
 hipError_t launch_sph_grid(const double2* R, int ns, int lmax, int n_q, int n_theta, int n_phi, double2* F,

@@ -61,7 +61,8 @@ std::shared_mutex& scff::device_gate() {
 
 // Timing events: precompute start/end, 1D tables start, grid kernel start/end.
 // FFT method: packing start, density start, density end, transforms end.
-enum { EV_PREP0, EV_PREP1, EV_VT0, EV_GRID0, EV_GRID1, EV_FFT0, EV_FFT1, EV_FFT2, EV_FFT3, EV_N };
+// Spherical method: geometry kernel start, contraction start, contraction end, end.
+enum { EV_PREP0, EV_PREP1, EV_VT0, EV_GRID0, EV_GRID1, EV_FFT0, EV_FFT1, EV_FFT2, EV_FFT3, EV_SPH0, EV_SPH1, EV_SPH2, EV_SPH3, EV_N };
 
 struct scff_ctx {
     int device = 0;
@@ -89,7 +90,7 @@ struct scff_ctx {
     // timing
     bool timing = false;
     hipEvent_t ev[EV_N] = {};
-    bool ev_recorded = false, ev_prep = false, fft_recorded = false;
+    bool ev_recorded = false, ev_prep = false, fft_recorded = false, sph_recorded = false;
     // stream ordering: the end of the last asynchronous work on the context
     hipEvent_t order_ev = nullptr;
     hipStream_t order_st = nullptr;
@@ -112,7 +113,8 @@ struct scff_ctx {
     // spherical method: constant tables (for sph_lmax), geometries, per-geometry
     // data, harmonics and W tensor, radii, contraction, R tensor, Legendre stage,
     // angular average
-    DeviceBuffer d_sph_tab, d_sph_geo, d_sph_gdat, d_sph_Yc, d_sph_W, d_sph_q, d_sph_Q, d_sph_R, d_sph_F, d_sph_avg;
+    DeviceBuffer d_sph_tab, d_sph_geo, d_sph_gdat, d_sph_Yc, d_sph_W, d_sph_q, d_sph_Q, d_sph_R, d_sph_F, d_sph_avg,
+        d_sph_J;
     int sph_lmax = -1;
     size_t sph_off[5] = {};   // theta, uvw index, nfirst, nlm_of, gaunt
     size_t lds_block = 65536;   // LDS bytes one workgroup may use
@@ -436,7 +438,7 @@ void free_all(scff_ctx* c) {
                             &c->d_lq_in, &c->d_lq_S, &c->d_lq_G, &c->d_lq_out, &c->d_fft_A, &c->d_fft_Z,
                             &c->d_fft_part, &c->d_fft_out, &c->d_phi, &c->d_sph_tab, &c->d_sph_geo,
                             &c->d_sph_gdat, &c->d_sph_Yc, &c->d_sph_W, &c->d_sph_q, &c->d_sph_Q, &c->d_sph_R,
-                            &c->d_sph_F, &c->d_sph_avg})
+                            &c->d_sph_F, &c->d_sph_avg, &c->d_sph_J})
         dev_free(c, *b);
     PrepWork& w = c->prep;
     for (DeviceBuffer* b : {&w.rows_all, &w.rowsum, &w.trow, &w.tbound, &w.wt, &w.cpmn, &w.tp64, &w.bsum,
@@ -852,6 +854,7 @@ int scff_set_timing(scff_ctx* c, int enable) {
     c->timing = enable != 0;
     c->ev_recorded = false;
     c->fft_recorded = false;
+    c->sph_recorded = false;
     return ok();
 }
 
@@ -868,6 +871,22 @@ int scff_last_timing(scff_ctx* c, float* prep_ms, float* vtable_ms, float* grid_
     if (prep_ms) *prep_ms = c->ev_prep ? p : 0.0f;
     if (vtable_ms) *vtable_ms = a;
     if (grid_ms) *grid_ms = b;
+    return ok();
+}
+
+int scff_last_sph_timing(scff_ctx* c, float* geom_ms, float* contraction_ms, float* rest_ms) {
+    if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
+    if (!c->timing || !c->sph_recorded) return fail(SCFF_ESTATE, "no timed spherical evaluation recorded");
+    int rc;
+    if ((rc = hip_check(hipEventSynchronize(c->ev[EV_SPH3]), "event sync"))) return rc;
+    float a = 0.f, b = 0.f, t = 0.f;
+    if ((rc = hip_check(hipEventElapsedTime(&a, c->ev[EV_SPH0], c->ev[EV_SPH1]), "elapsed")) ||
+        (rc = hip_check(hipEventElapsedTime(&b, c->ev[EV_SPH1], c->ev[EV_SPH2]), "elapsed")) ||
+        (rc = hip_check(hipEventElapsedTime(&t, c->ev[EV_SPH2], c->ev[EV_SPH3]), "elapsed")))
+        return rc;
+    if (geom_ms) *geom_ms = a;
+    if (contraction_ms) *contraction_ms = b;
+    if (rest_ms) *rest_ms = t;
     return ok();
 }
 
@@ -1210,6 +1229,7 @@ int scff_eval_spherical(scff_ctx* c, int lmax, int n_q, const double* q, int n_t
         (rc = dev_reserve(c, c->d_sph_W, (size_t)n_geo * n_nlm * ns * sizeof(double2))) ||
         (rc = dev_reserve(c, c->d_sph_q, (size_t)n_q * sizeof(double))) ||
         (rc = dev_reserve(c, c->d_sph_Q, (size_t)n_q * nrows * nL * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_sph_J, (size_t)n_q * (Lmax + 2) * n_geo * sizeof(double))) ||
         (rc = dev_reserve(c, c->d_sph_R, (size_t)ns * n_q * nl * sizeof(double2))))
         return rc;
     if ((f || f2) && (rc = dev_reserve(c, c->d_sph_F, (size_t)ns * n_q * n_theta * (2 * lmax + 1) * sizeof(double2))))
@@ -1230,21 +1250,26 @@ int scff_eval_spherical(scff_ctx* c, int lmax, int n_q, const double* q, int n_t
         dR = (double2*)R;
     }
     const unsigned char* tb = (const unsigned char*)c->d_sph_tab.p;
+    c->sph_recorded = false;
     if ((rc = hip_check(hipMemcpyAsync(c->d_sph_geo.p, geo.data(), geo.size() * sizeof(SphGeom),
                                        hipMemcpyHostToDevice, st), "upload geometries")) ||
         (rc = hip_check(hipMemcpyAsync(c->d_sph_q.p, q, (size_t)n_q * sizeof(double), hipMemcpyHostToDevice, st),
                         "upload radii")))
         return rc;
+    if ((rc = record(c, EV_SPH0, st))) return rc;
     if ((rc = hip_check(launch_sph_geom((const SphGeom*)c->d_sph_geo.p, n_geo, (const VRowDev*)c->prep.rows_all.p,
                                         (const int4*)c->prep.trow.p, (const double*)c->prep.tp64.p, ns,
                                         (const double2*)(tb + c->sph_off[0]), (const int*)(tb + c->sph_off[1]),
                                         (const int*)(tb + c->sph_off[2]), n_nlm, Lmax, (double4*)c->d_sph_gdat.p,
                                         (double2*)c->d_sph_Yc.p, (double2*)c->d_sph_W.p, st),
                         "spherical geometry kernel")) ||
+        (rc = record(c, EV_SPH1, st)) ||
         (rc = hip_check(launch_sph_q((const double4*)c->d_sph_gdat.p, (const double2*)c->d_sph_Yc.p,
                                      (const double2*)c->d_sph_W.p, n_geo, ns, Lmax, (const int*)(tb + c->sph_off[3]),
-                                     n_nlm, (const double*)c->d_sph_q.p, n_q, (double2*)c->d_sph_Q.p, st),
+                                     n_nlm, (const double*)c->d_sph_q.p, n_q, (double*)c->d_sph_J.p,
+                                     (double2*)c->d_sph_Q.p, st),
                         "spherical contraction kernel")) ||
+        (rc = record(c, EV_SPH2, st)) ||
         (rc = hip_check(launch_sph_couple((const double2*)c->d_sph_Q.p, (const double*)(tb + c->sph_off[4]), ns, lmax,
                                           Lmax, n_q, dR, st),
                         "spherical coupling kernel")))
@@ -1254,6 +1279,8 @@ int scff_eval_spherical(scff_ctx* c, int lmax, int n_q, const double* q, int n_t
                                                      df2, st),
                                      "spherical grid kernels")))
         return rc;
+    if ((rc = record(c, EV_SPH3, st))) return rc;
+    c->sph_recorded = c->timing;
     if (!out_on_device) {
         if ((rc = copy_out(df, f, df2, f2, nout, st))) return rc;
         if (R && (rc = hip_check(hipMemcpyAsync(R, dR, (size_t)ns * n_q * nl * sizeof(double2), hipMemcpyDeviceToHost,

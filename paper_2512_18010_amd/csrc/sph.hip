@@ -14,7 +14,10 @@
 //                        a = 4 pi i^L j_L(q |P_g|) Y_L^M*(P^_g),
 //                      a complex GEMM (rows: state x (lam mu), columns:
 //                      (L M), k: geometries) tiled in LDS, with the spherical
-//                      Bessel functions by Miller's downward recurrence;
+//                      Bessel functions j_L(q |P_g|) (sph_bessel_kernel: Miller's
+//                      downward recurrence from far above max(L, x), normalised
+//                      with j_0 = sin x / x or j_1, whichever is larger; the
+//                      two-term power series below x = 1e-4);
 //   sph_couple_kernel  R^s_lm(q) = sum_{lam mu, L} G^{mu, m-mu}_{lam L l} Q^s[lam mu][L, m-mu]
 //                      (eq. RTensor with the Gaunt coefficients of eq. YYY);
 //   sph_legendre_kernel / sph_phi_kernel
@@ -81,46 +84,6 @@ __device__ void ylm_conj_row(int Lmax, double theta, double phi, double2* out) {
     }
 }
 
-// Spherical Bessel functions j_L(x) for L in [L0, L1] into out[L - L0],
-// FP64: Miller's downward recurrence j_{L-1} = (2L+1)/x j_L - j_{L+1} from
-// far above max(L1, x), normalised with j_0 = sin x / x or j_1 (whichever is
-// larger); the two-term power series below x = 1e-4.
-__device__ void bessel_range(double x, int L0, int L1, double* out) {
-    if (x < 1e-4) {
-        double df = 1.0;   // (2L+1)!!
-        double xl = 1.0;   // x^L
-        for (int L = 0; L <= L1; ++L) {
-            if (L > 0) {
-                df *= 2.0 * L + 1.0;
-                xl *= x;
-            }
-            if (L >= L0) out[L - L0] = xl / df * (1.0 - x * x / (2.0 * (2.0 * L + 3.0)));
-        }
-        return;
-    }
-    const int N = max(L1, (int)x) + 32;
-    double fp = 0.0, f = 1e-280, f0 = 0.0, f1 = 0.0;
-    for (int L = N; L >= 1; --L) {
-        const double fm = (2.0 * L + 1.0) / x * f - fp;   // f_{L-1}
-        fp = f;
-        f = fm;
-        if (L - 1 >= L0 && L - 1 <= L1) out[L - 1 - L0] = f;
-        if (L - 1 == 1) f1 = f;
-        if (fabs(f) > 1e250) {   // rescale everything kept so far
-            f *= 1e-250;
-            fp *= 1e-250;
-            f1 *= 1e-250;
-            for (int k = max(L - 1, L0); k <= L1; ++k) out[k - L0] *= 1e-250;
-        }
-    }
-    f0 = f;
-    double sn, cs;
-    sincos(x, &sn, &cs);
-    const double j0 = sn / x, j1 = sn / (x * x) - cs / x;
-    const double scale = fabs(j0) >= fabs(j1) ? j0 / f0 : j1 / f1;
-    for (int L = L0; L <= L1; ++L) out[L - L0] *= scale;
-}
-
 __global__ __launch_bounds__(128) void sph_geom_kernel(const SphGeom* __restrict__ geo, int n_geo,
                                                        const VRowDev* __restrict__ rows,
                                                        const int4* __restrict__ trow,
@@ -132,8 +95,10 @@ __global__ __launch_bounds__(128) void sph_geom_kernel(const SphGeom* __restrict
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_geo) return;
     const SphGeom G = geo[g];
-    double2* Wg = W + (size_t)g * n_nlm * ns;
-    for (int i = 0; i < n_nlm * ns; ++i) Wg[i] = make_double2(0.0, 0.0);
+    // W[(b ns + s) n_geo + g]: geometries fastest, so the contraction kernel's
+    // loads of one (b, s) over a chunk of geometries are contiguous
+    double2* Wg = W + g;
+    for (int i = 0; i < n_nlm * ns; ++i) Wg[(size_t)i * n_geo] = make_double2(0.0, 0.0);
     const int4 t0 = trow[G.term0 + G.pp];
     const double Px = rows[t0.x].P, Py = rows[t0.y].P, Pz = rows[t0.z].P;
     const double d = sqrt(Px * Px + Py * Py + Pz * Pz);
@@ -160,7 +125,7 @@ __global__ __launch_bounds__(128) void sph_geom_kernel(const SphGeom* __restrict
                         if (th_ab.x == 0.0 && th_ab.y == 0.0) continue;
                         const double2 x = cmul(coef, th_ab);
                         for (int s = 0; s < ns; ++s) {
-                            double2& o = Wg[(size_t)b * ns + s];
+                            double2& o = Wg[((size_t)b * ns + s) * n_geo];
                             o.x += tp[s] * x.x;
                             o.y += tp[s] * x.y;
                         }
@@ -169,19 +134,68 @@ __global__ __launch_bounds__(128) void sph_geom_kernel(const SphGeom* __restrict
     }
 }
 
-// Tile: 32 rows (state, lam mu) x 64 columns (L M) per workgroup, all
-// geometries in chunks of 32; thread (ty, tx) holds rows 2 ty + {0, 1} and
-// columns 4 tx + {0..3}.
-constexpr int kQRows = 32, kQCols = 64, kQK = 32, kQLspan = 10;
+// Spherical Bessel functions and Gaussian of every (radius, geometry):
+// J[(iq (Lmax + 2) + L) n_geo + g] = j_L(q |P_g|) for L <= Lmax and, at
+// L = Lmax + 1, e^{-q^2 / 4p_g}.  One thread per (radius, geometry); the
+// recurrence of bessel_range, written straight to the strided table.
+__global__ void sph_bessel_kernel(const double4* __restrict__ gdat, int n_geo, int Lmax, const double* __restrict__ qs,
+                                  int n_q, double* __restrict__ J) {
+    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx >= (long long)n_q * n_geo) return;
+    const int g = (int)(idx % n_geo), iq = (int)(idx / n_geo);
+    const double4 gg = gdat[g];
+    const double q = qs[iq], x = q * gg.x;
+    double* o = J + (size_t)iq * (Lmax + 2) * n_geo + g;
+    o[(size_t)(Lmax + 1) * n_geo] = exp(-q * q * gg.w);
+    if (x < 1e-4) {
+        double df = 1.0, xl = 1.0;
+        for (int L = 0; L <= Lmax; ++L) {
+            if (L > 0) {
+                df *= 2.0 * L + 1.0;
+                xl *= x;
+            }
+            o[(size_t)L * n_geo] = xl / df * (1.0 - x * x / (2.0 * (2.0 * L + 3.0)));
+        }
+        return;
+    }
+    const int N = max(Lmax, (int)x) + 32;
+    const double rx = 1.0 / x;
+    double fp = 0.0, f = 1e-280, f1 = 0.0;
+    for (int L = N; L >= 1; --L) {
+        const double fm = (2.0 * L + 1.0) * rx * f - fp;   // f_{L-1}
+        fp = f;
+        f = fm;
+        if (L - 1 <= Lmax) o[(size_t)(L - 1) * n_geo] = f;
+        if (L - 1 == 1) f1 = f;
+        if (fabs(f) > 1e250) {   // rescale everything kept so far
+            f *= 1e-250;
+            fp *= 1e-250;
+            f1 *= 1e-250;
+            for (int k = L - 1; k <= Lmax; ++k) o[(size_t)k * n_geo] *= 1e-250;
+        }
+    }
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    const double j0 = sn * rx, j1 = (sn * rx - cs) * rx;
+    const double scale = fabs(j0) >= fabs(j1) ? j0 / f : j1 / f1;
+    for (int L = 0; L <= Lmax; ++L) o[(size_t)L * n_geo] *= scale;
+}
 
-__global__ __launch_bounds__(256) void sph_q_kernel(const double4* __restrict__ gdat, const double2* __restrict__ Yc,
+// Tile: 64 rows (state, lam mu) x 128 columns (L M) per workgroup, all
+// geometries in chunks of 16; thread (ty, tx) holds rows 4 ty + {0..3} and
+// columns 8 tx + {0..7} (32 complex accumulators: 12 operand loads from LDS
+// per 32 complex multiply-adds).
+constexpr int kQRows = 64, kQCols = 128, kQK = 16, kQLspan = 14;
+constexpr int kQTC = 8;   // columns per thread
+
+__global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J, const double2* __restrict__ Yc,
                                                     const double2* __restrict__ W, int n_geo, int ns, int Lmax,
                                                     const int* __restrict__ nlm_of, int n_nlm,
                                                     const double* __restrict__ qs, double2* __restrict__ Q) {
     __shared__ double2 Bs[kQRows][kQK + 1];
     __shared__ double2 As[kQK][kQCols + 1];
-    __shared__ double jt[kQK][kQLspan];
-    __shared__ double4 gd[kQK];
+    __shared__ double jt[kQLspan + 1][kQK];
+    __shared__ int colL[kQCols];
     const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
     const int nrows = ns * kLam, ncols = (Lmax + 1) * (Lmax + 1);
     const int r0 = blockIdx.y * kQRows, c0 = blockIdx.x * kQCols;
@@ -189,19 +203,21 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double4* __restrict__ 
     const double q = qs[iq];
     const int cl = min(c0 + kQCols, ncols) - 1;
     const int Lmin = (int)sqrt((double)c0 + 0.5), Lhi = (int)sqrt((double)cl + 0.5);
-    double2 acc[2][4];
+    const int span = Lhi - Lmin + 1;
+    const double* Jq = J + (size_t)iq * (Lmax + 2) * n_geo;
+    for (int cc = tid; cc < kQCols; cc += 256) colL[cc] = (int)sqrt((double)(c0 + cc) + 0.5);
+    double2 acc[4][kQTC];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+        for (int j = 0; j < kQTC; ++j) acc[i][j] = make_double2(0.0, 0.0);
     for (int g0 = 0; g0 < n_geo; g0 += kQK) {
-        if (tid < kQK) {
-            const int g = g0 + tid;
-            if (g < n_geo) {
-                const double4 gg = gdat[g];
-                gd[tid] = gg;
-                bessel_range(q * gg.x, Lmin, Lhi, jt[tid]);
-            }
+        // Bessel values of this column block's L range and the Gaussians (row kQLspan)
+        for (int e = tid; e < (span + 1) * kQK; e += 256) {
+            const int li = e / kQK, gg = e - li * kQK;
+            const int g = g0 + gg;
+            const int L = li < span ? Lmin + li : Lmax + 1;
+            jt[li < span ? li : kQLspan][gg] = g < n_geo ? Jq[(size_t)L * n_geo + g] : 0.0;
         }
         __syncthreads();
         // B: rows (state, lam mu) x geometries
@@ -211,19 +227,18 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double4* __restrict__ 
             double2 b = make_double2(0.0, 0.0);
             if (r < nrows && g < n_geo) {
                 const int s = r / kLam, lm = r - s * kLam;
-                const int lam = (int)sqrt((double)lm + 0.5);
-                const double2* Wg = W + (size_t)g * n_nlm * ns;
+                const int lam = lm < 1 ? 0 : lm < 4 ? 1 : lm < 9 ? 2 : lm < 16 ? 3 : 4;
                 double qn = 1.0;
                 for (int n = 0; n <= kSphMaxN; ++n) {
                     if (n >= lam && ((n - lam) & 1) == 0) {
                         const int b_i = nlm_of[n * kLam + lm];
-                        const double2 w = Wg[(size_t)b_i * ns + s];
+                        const double2 w = W[((size_t)b_i * ns + s) * n_geo + g];
                         b.x += qn * w.x;
                         b.y += qn * w.y;
                     }
                     qn *= q;
                 }
-                b = cscale(b, exp(-q * q * gd[gg].w));
+                b = cscale(b, jt[kQLspan][gg]);
             }
             Bs[row][gg] = b;
         }
@@ -233,32 +248,35 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double4* __restrict__ 
             const int col = c0 + cc, g = g0 + gg;
             double2 a = make_double2(0.0, 0.0);
             if (col < ncols && g < n_geo) {
-                const int L = (int)sqrt((double)col + 0.5);
-                const double jl = jt[gg][L - Lmin] * 4.0 * M_PI;
+                const int L = colL[cc];
+                const double jl = jt[L - Lmin][gg] * 4.0 * M_PI;
                 a = cmul(cscale(ipow(L), jl), Yc[(size_t)g * ncols + col]);
             }
             As[gg][cc] = a;
         }
         __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
         for (int k = 0; k < kQK; ++k) {
-            const double2 b0 = Bs[2 * ty][k], b1 = Bs[2 * ty + 1][k];
+            double2 b[4], a[kQTC];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const double2 a = As[k][4 * tx + j];
-                acc[0][j].x += b0.x * a.x - b0.y * a.y;
-                acc[0][j].y += b0.x * a.y + b0.y * a.x;
-                acc[1][j].x += b1.x * a.x - b1.y * a.y;
-                acc[1][j].y += b1.x * a.y + b1.y * a.x;
-            }
+            for (int i = 0; i < 4; ++i) b[i] = Bs[4 * ty + i][k];
+#pragma unroll
+            for (int j = 0; j < kQTC; ++j) a[j] = As[k][kQTC * tx + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < kQTC; ++j) {
+                    acc[i][j].x += b[i].x * a[j].x - b[i].y * a[j].y;
+                    acc[i][j].y += b[i].x * a[j].y + b[i].y * a[j].x;
+                }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = r0 + 2 * ty + i, col = c0 + 4 * tx + j;
+        for (int j = 0; j < kQTC; ++j) {
+            const int r = r0 + 4 * ty + i, col = c0 + kQTC * tx + j;
             if (r < nrows && col < ncols) Q[((size_t)iq * nrows + r) * ncols + col] = acc[i][j];
         }
 }
@@ -384,11 +402,16 @@ hipError_t launch_sph_geom(const SphGeom* geo, int n_geo, const VRowDev* rows, c
 }
 
 hipError_t launch_sph_q(const double4* gdat, const double2* Yc, const double2* W, int n_geo, int ns, int Lmax,
-                        const int* nlm_of, int n_nlm, const double* qs, int n_q, double2* Q, hipStream_t st) {
+                        const int* nlm_of, int n_nlm, const double* qs, int n_q, double* J, double2* Q, hipStream_t st) {
+    const long long nb = (long long)n_q * n_geo;
+    hipLaunchKernelGGL(sph_bessel_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, gdat, n_geo, Lmax, qs,
+                       n_q, J);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int nrows = ns * kLam, ncols = (Lmax + 1) * (Lmax + 1);
-    // the Bessel span of one column block: 64 consecutive (L M) cover at most 8 values of L
+    // 128 consecutive (L M) cover at most 12 values of L (kQLspan)
     dim3 grid((ncols + kQCols - 1) / kQCols, (nrows + kQRows - 1) / kQRows, n_q);
-    hipLaunchKernelGGL(sph_q_kernel, grid, dim3(256), 0, st, gdat, Yc, W, n_geo, ns, Lmax, nlm_of, n_nlm, qs, Q);
+    hipLaunchKernelGGL(sph_q_kernel, grid, dim3(256), 0, st, J, Yc, W, n_geo, ns, Lmax, nlm_of, n_nlm, qs, Q);
     return hipGetLastError();
 }
 

@@ -22,11 +22,18 @@ def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
     csrc = tmp_path / "paper_2512_18010_amd" / "csrc"
     csrc.mkdir(parents=True)
     (csrc / "kernels.hip").write_text("int a; // one\n\nint b;\n")
-    (csrc / "engine.h").write_text("int c;\n")
+    eng = "#include <x>\nnamespace scff {\nint c;\nstruct DeviceBuffer {};\nint runtime_decl();\n}\n"
+    (csrc / "engine.h").write_text(eng)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     h0 = bench.kernel_source_hash()
     (csrc / "kernels.hip").write_text("int a; // a different comment\n// and a new one\nint b;   \n")
     assert bench.kernel_source_hash() == h0
+    # engine.h outside the kernel's layout part (includes, runtime declarations) is not hashed
+    (csrc / "engine.h").write_text(eng.replace("#include <x>", "#include <y>").replace("runtime_decl", "other"))
+    assert bench.kernel_source_hash() == h0
+    (csrc / "engine.h").write_text(eng.replace("int c;", "int c2;"))
+    assert bench.kernel_source_hash() != h0
+    (csrc / "engine.h").write_text(eng)
     (csrc / "kernels.hip").write_text("int a;\nint b2;\n")
     assert bench.kernel_source_hash() != h0
 
