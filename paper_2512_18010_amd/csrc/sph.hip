@@ -12,8 +12,8 @@
 //                        Q^s[lam mu][L M](q) = sum_g b^s_g[lam mu](q) a_g[L M](q),
 //                        b = e^{-q^2/4p} sum_n q^n W^s_g[n lam mu],
 //                        a = 4 pi i^L j_L(q |P_g|) Y_L^M*(P^_g),
-//                      a complex GEMM (rows: state x (lam mu), columns:
-//                      (L M), k: geometries) tiled in LDS, with the spherical
+//                      a complex GEMM on the FP64 matrix cores (rows: state x
+//                      (lam mu), columns: (L M), k: geometries) tiled in LDS, with the spherical
 //                      Bessel functions j_L(q |P_g|) (sph_bessel_kernel: Miller's
 //                      downward recurrence from far above max(L, x), normalised
 //                      with j_0 = sin x / x or j_1, whichever is larger; the
@@ -182,21 +182,26 @@ __global__ void sph_bessel_kernel(const double4* __restrict__ gdat, int n_geo, i
 }
 
 // Tile: 64 rows (state, lam mu) x 128 columns (L M) per workgroup, all
-// geometries in chunks of 16; thread (ty, tx) holds rows 4 ty + {0..3} and
-// columns 8 tx + {0..7} (32 complex accumulators: 12 operand loads from LDS
-// per 32 complex multiply-adds).
+// geometries in chunks of 16, on the FP64 matrix cores
+// (v_mfma_f64_16x16x4_f64: A = 16 rows x 4 geometries, B = 4 geometries x
+// 16 columns; lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and the
+// results D[4 i + l / 16][l % 16], i = 0..3, as measured on the device).  Wave w owns the 16 rows 16 w .. 16 w + 15
+// and all 8 column blocks; the complex product takes four real products
+// (re re - im im, re im + im re).  The operands are staged in LDS as real and
+// imaginary planes.
 constexpr int kQRows = 64, kQCols = 128, kQK = 16, kQLspan = 14;
-constexpr int kQTC = 8;   // columns per thread
+typedef double sph_double4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J, const double2* __restrict__ Yc,
                                                     const double2* __restrict__ W, int n_geo, int ns, int Lmax,
                                                     const int* __restrict__ nlm_of, int n_nlm,
                                                     const double* __restrict__ qs, double2* __restrict__ Q) {
-    __shared__ double2 Bs[kQRows][kQK + 1];
-    __shared__ double2 As[kQK][kQCols + 1];
+    __shared__ double Br[kQRows][kQK + 1], Bi[kQRows][kQK + 1];
+    __shared__ double Ar[kQK][kQCols + 1], Ai[kQK][kQCols + 1];
     __shared__ double jt[kQLspan + 1][kQK];
     __shared__ int colL[kQCols];
-    const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nrows = ns * kLam, ncols = (Lmax + 1) * (Lmax + 1);
     const int r0 = blockIdx.y * kQRows, c0 = blockIdx.x * kQCols;
     const int iq = blockIdx.z;
@@ -206,11 +211,13 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
     const int span = Lhi - Lmin + 1;
     const double* Jq = J + (size_t)iq * (Lmax + 2) * n_geo;
     for (int cc = tid; cc < kQCols; cc += 256) colL[cc] = (int)sqrt((double)(c0 + cc) + 0.5);
-    double2 acc[4][kQTC];
+    sph_double4 accR[8], accI[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < kQTC; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    for (int cb = 0; cb < 8; ++cb) {
+        accR[cb] = (sph_double4){0.0, 0.0, 0.0, 0.0};
+        accI[cb] = (sph_double4){0.0, 0.0, 0.0, 0.0};
+    }
+    const int lr = lane & 15, lk = lane >> 4;
     for (int g0 = 0; g0 < n_geo; g0 += kQK) {
         // Bessel values of this column block's L range and the Gaussians (row kQLspan)
         for (int e = tid; e < (span + 1) * kQK; e += 256) {
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
         for (int e = tid; e < kQRows * kQK; e += 256) {
             const int row = e / kQK, gg = e - row * kQK;
             const int r = r0 + row, g = g0 + gg;
-            double2 b = make_double2(0.0, 0.0);
+            double br = 0.0, bi = 0.0;
             if (r < nrows && g < n_geo) {
                 const int s = r / kLam, lm = r - s * kLam;
                 const int lam = lm < 1 ? 0 : lm < 4 ? 1 : lm < 9 ? 2 : lm < 16 ? 3 : 4;
@@ -233,14 +240,17 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
                     if (n >= lam && ((n - lam) & 1) == 0) {
                         const int b_i = nlm_of[n * kLam + lm];
                         const double2 w = W[((size_t)b_i * ns + s) * n_geo + g];
-                        b.x += qn * w.x;
-                        b.y += qn * w.y;
+                        br += qn * w.x;
+                        bi += qn * w.y;
                     }
                     qn *= q;
                 }
-                b = cscale(b, jt[kQLspan][gg]);
+                const double ga = jt[kQLspan][gg];
+                br *= ga;
+                bi *= ga;
             }
-            Bs[row][gg] = b;
+            Br[row][gg] = br;
+            Bi[row][gg] = bi;
         }
         // A: geometries x (L M)
         for (int e = tid; e < kQK * kQCols; e += 256) {
@@ -252,32 +262,30 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
                 const double jl = jt[L - Lmin][gg] * 4.0 * M_PI;
                 a = cmul(cscale(ipow(L), jl), Yc[(size_t)g * ncols + col]);
             }
-            As[gg][cc] = a;
+            Ar[gg][cc] = a.x;
+            Ai[gg][cc] = a.y;
         }
         __syncthreads();
-#pragma unroll 2
-        for (int k = 0; k < kQK; ++k) {
-            double2 b[4], a[kQTC];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) b[i] = Bs[4 * ty + i][k];
+        for (int ks = 0; ks < kQK / 4; ++ks) {
+            const double ar = Br[16 * wave + lr][4 * ks + lk], ai = Bi[16 * wave + lr][4 * ks + lk];
 #pragma unroll
-            for (int j = 0; j < kQTC; ++j) a[j] = As[k][kQTC * tx + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < kQTC; ++j) {
-                    acc[i][j].x += b[i].x * a[j].x - b[i].y * a[j].y;
-                    acc[i][j].y += b[i].x * a[j].y + b[i].y * a[j].x;
-                }
+            for (int cb = 0; cb < 8; ++cb) {
+                const double br = Ar[4 * ks + lk][16 * cb + lr], bi = Ai[4 * ks + lk][16 * cb + lr];
+                accR[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accR[cb], 0, 0, 0);
+                accR[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accR[cb], 0, 0, 0);
+                accI[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, accI[cb], 0, 0, 0);
+                accI[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, accI[cb], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int cb = 0; cb < 8; ++cb)
 #pragma unroll
-        for (int j = 0; j < kQTC; ++j) {
-            const int r = r0 + 4 * ty + i, col = c0 + kQTC * tx + j;
-            if (r < nrows && col < ncols) Q[((size_t)iq * nrows + r) * ncols + col] = acc[i][j];
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + 16 * wave + 4 * i + lk, col = c0 + 16 * cb + lr;
+            if (r < nrows && col < ncols) Q[((size_t)iq * nrows + r) * ncols + col] = make_double2(accR[cb][i], accI[cb][i]);
         }
 }
 
