@@ -432,7 +432,7 @@ def main():
     ap.add_argument("--no-symmetric", action="store_true",
                     help="skip the symmetric-grid measurement (f(-q) = f(q)*, half the planes evaluated)")
     ap.add_argument("--serve-pool", type=int, default=24, help="distinct requests in the serving pool")
-    ap.add_argument("--serve-sat", type=int, default=48, help="requests of the closed-loop saturation run")
+    ap.add_argument("--serve-sat", type=int, default=120, help="requests of the closed-loop saturation run")
     ap.add_argument("--serve-requests", type=int, default=96, help="requests per Poisson arrival rate")
     ap.add_argument("--serve-warmup", type=int, default=8)
     ap.add_argument("--serve-inflight", type=int, default=4)
