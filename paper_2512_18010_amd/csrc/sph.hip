@@ -181,15 +181,16 @@ __global__ void sph_bessel_kernel(const double4* __restrict__ gdat, int n_geo, i
     for (int L = 0; L <= Lmax; ++L) o[(size_t)L * n_geo] *= scale;
 }
 
-// Tile: 64 rows (state, lam mu) x 128 columns (L M) per workgroup, all
+// Tile: 64 rows (state, lam mu) x 64 columns (L M) per workgroup, all
 // geometries in chunks of 16, on the FP64 matrix cores
 // (v_mfma_f64_16x16x4_f64: A = 16 rows x 4 geometries, B = 4 geometries x
 // 16 columns; lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and the
 // results D[4 i + l / 16][l % 16], i = 0..3, as measured on the device).  Wave w owns the 16 rows 16 w .. 16 w + 15
-// and all 8 column blocks; the complex product takes four real products
+// and all 4 column blocks; the complex product takes four real products
 // (re re - im im, re im + im re).  The operands are staged in LDS as real and
 // imaginary planes.
-constexpr int kQRows = 64, kQCols = 128, kQK = 16, kQLspan = 14;
+constexpr int kQRows = 64, kQCols = 64, kQK = 16, kQLspan = 14;
+constexpr int kQCB = kQCols / 16;   // column blocks per wave
 typedef double sph_double4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J, const double2* __restrict__ Yc,
@@ -211,9 +212,9 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
     const int span = Lhi - Lmin + 1;
     const double* Jq = J + (size_t)iq * (Lmax + 2) * n_geo;
     for (int cc = tid; cc < kQCols; cc += 256) colL[cc] = (int)sqrt((double)(c0 + cc) + 0.5);
-    sph_double4 accR[8], accI[8];
+    sph_double4 accR[kQCB], accI[kQCB];
 #pragma unroll
-    for (int cb = 0; cb < 8; ++cb) {
+    for (int cb = 0; cb < kQCB; ++cb) {
         accR[cb] = (sph_double4){0.0, 0.0, 0.0, 0.0};
         accI[cb] = (sph_double4){0.0, 0.0, 0.0, 0.0};
     }
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
         for (int ks = 0; ks < kQK / 4; ++ks) {
             const double ar = Br[16 * wave + lr][4 * ks + lk], ai = Bi[16 * wave + lr][4 * ks + lk];
 #pragma unroll
-            for (int cb = 0; cb < 8; ++cb) {
+            for (int cb = 0; cb < kQCB; ++cb) {
                 const double br = Ar[4 * ks + lk][16 * cb + lr], bi = Ai[4 * ks + lk][16 * cb + lr];
                 accR[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accR[cb], 0, 0, 0);
                 accR[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accR[cb], 0, 0, 0);
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
         __syncthreads();
     }
 #pragma unroll
-    for (int cb = 0; cb < 8; ++cb)
+    for (int cb = 0; cb < kQCB; ++cb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = r0 + 16 * wave + 4 * i + lk, col = c0 + 16 * cb + lr;
@@ -417,7 +418,7 @@ hipError_t launch_sph_q(const double4* gdat, const double2* Yc, const double2* W
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nrows = ns * kLam, ncols = (Lmax + 1) * (Lmax + 1);
-    // 128 consecutive (L M) cover at most 12 values of L (kQLspan)
+    // kQCols consecutive (L M) cover at most kQLspan values of L
     dim3 grid((ncols + kQCols - 1) / kQCols, (nrows + kQRows - 1) / kQRows, n_q);
     hipLaunchKernelGGL(sph_q_kernel, grid, dim3(256), 0, st, J, Yc, W, n_geo, ns, Lmax, nlm_of, n_nlm, qs, Q);
     return hipGetLastError();
