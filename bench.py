@@ -263,11 +263,12 @@ def grid_roofline(K, R, ns, nq, precision, grid_ms):
                             "mfma_achieved_tflops": con_issued / grid_s / 1e12}}
 
 
-def fft_benchmark(ctx, stream, n_axis, steps, warmup, log):
+def fft_benchmark(ctx, stream, n_axis, steps, warmup, log, precision="fp32"):
     """FFT method on the config-1 molecule and its 12 transitions in the
     paper's doubled box (bounding box + 5 bohr, times 2) sampled at n_axis^3
     points: one step = molecule load + T from HBM + weight packing + density +
-    transforms + finishing, f and |f|^2 left in HBM."""
+    transforms + finishing, f and |f|^2 left in HBM.  precision: the density
+    contraction's arithmetic ("fp32" or split "bf16x3")."""
     import torch
     import workload as wl
     W = wl.make_config(1)
@@ -282,7 +283,7 @@ def fft_benchmark(ctx, stream, n_axis, steps, warmup, log):
         ctx.load_molecule(W.mol)
         ctx.load_transitions_device(T_dev, stream)
         ctx.set_options(0.0, 1.0)
-        ctx.eval_fft_device(n, xmin, L, f, f2, None, stream=stream)
+        ctx.eval_fft_device(n, xmin, L, f, f2, None, stream=stream, precision=precision)
 
     for _ in range(warmup):
         step()
@@ -298,7 +299,8 @@ def fft_benchmark(ctx, stream, n_axis, steps, warmup, log):
     pack_ms, dens_ms, tr_ms = (float(np.mean(st[:, i])) for i in range(3))
     # checks: the density on seeded points against the oracle, Parseval's identity
     import oracle
-    _, _, phi, ps = ctx.eval_fft_host(n, xmin, L, want_f=False, want_f2=False, want_phi=True, parseval=True)
+    _, _, phi, ps = ctx.eval_fft_host(n, xmin, L, want_f=False, want_f2=False, want_phi=True, parseval=True,
+                                      precision=precision)
     rng = np.random.Generator(np.random.PCG64(99))
     idx = np.concatenate([rng.integers(0, npts, 200), np.abs(phi.reshape(ns, -1)).argmax(axis=1)])
     ax = oracle.real_space_axes(n, xmin, L)
@@ -313,18 +315,29 @@ def fft_benchmark(ctx, stream, n_axis, steps, warmup, log):
     nb = (ns + 1) // 2
     passes = sum(1 for a in range(3) if n[a] > 1)
     tr_bytes = passes * 2 * nb * npts * 8 + 2 * nb * npts * 8 + ns * npts * 12
-    log(f"fft method {n}: {ms:.2f} ms/step, density {dens_ms:.2f} ms ({flops / dens_ms / 1e9:.1f} TFLOP/s), "
+    bf = precision == "bf16x3"
+    peak = PEAK_BF16_MFMA if bf else PEAK_FP32_MFMA
+    # matrix-core instructions as issued: per 16-point tile, state and row block rb
+    # of 16 functions, the k-steps from the block's diagonal to the end
+    nbf_pad = (nbf + 15) // 16 * 16
+    RB, kstep = nbf_pad // 16, (8 if bf else 4)
+    n_mfma = ns * ((npts + 15) // 16) * sum(nbf_pad // kstep - 16 * rb // kstep for rb in range(RB))
+    issued = n_mfma * 2.0 * 16 * 16 * (32 if bf else 4)
+    log(f"fft method {n} {precision}: {ms:.2f} ms/step, density {dens_ms:.2f} ms ({flops / dens_ms / 1e9:.1f} TFLOP/s), "
         f"transforms {tr_ms:.2f} ms, density error {e_phi.max():.2e}, Parseval {e_par.max():.2e}")
     return {
         "workload": f"{W.name}; FFT box {n[0]}x{n[1]}x{n[2]} = bounding box + 5 bohr, doubled",
+        "precision": precision,
         "box": {"n": list(n), "xmin": list(xmin), "L": list(L)},
         "steps": steps, "ms_per_step": ms,
         "value": ns * npts / (ms * 1e-3), "unit": "q-points*transitions/s",
         "stages_ms": {"pack": pack_ms, "density": dens_ms, "transforms": tr_ms},
         "roofline": {"bound": "mfma", "kernel": "fft_density_kernel",
-                     "achieved": flops / (dens_ms * 1e-3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / (dens_ms * 1e-3) / PEAK_FP32_MFMA,
+                     "achieved": flops / (dens_ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / (dens_ms * 1e-3) / peak,
                      "per_unit": "2 flops per (unordered AO pair, real-space point, transition) on the matrix cores",
+                     "issued_tflops": issued / (dens_ms * 1e-3) / 1e12,
+                     "issued_frac": issued / (dens_ms * 1e-3) / peak,
                      "units": {"pairs": pairs, "points": npts, "n_states": ns}},
         "transforms_roofline": {"bound": "hbm", "achieved": tr_bytes / (tr_ms * 1e-3) / 1e9,
                                 "peak": PEAK_HBM / 1e9, "unit": "GB/s",
@@ -588,6 +601,8 @@ def main():
     fft_leg = None
     if not args.no_fft:
         fft_leg = fft_benchmark(ctx, stream, args.fft_n, max(5, args.steps // 2), 2, log)
+        fft_leg["other_precision"] = fft_benchmark(ctx, stream, args.fft_n, max(5, args.steps // 2), 2, log,
+                                                   precision="bf16x3")
 
     # ---- spherical method (Sec. 4, Sec. 5.4): config-1 molecule and transitions
     sph_leg = None

@@ -271,6 +271,8 @@ int scff_export_vtensors(scff_ctx* ctx, const scff_grid* grid, long long* n_term
  * shrinks (the method's discretisation is the caller's choice: the paper
  * takes x_lim = pi / dq and dx = 2 pi / q_lim).
  *   grid       n[a] powers of two in 1..1024; L[a] > 0 (bohr)
+ *   precision  SCFF_FP32 or SCFF_BF16X3: the arithmetic of the density
+ *              contraction (below)
  *   f          complex64 [n_states][n0][n1][n2] interleaved, or NULL
  *   f2         |f|^2, float [n_states][n0][n1][n2], or NULL
  *   phi        the transition density Phi_s, float [n_states][n0][n1][n2], or NULL
@@ -281,7 +283,10 @@ int scff_export_vtensors(scff_ctx* ctx, const scff_grid* grid, long long* n_term
  * they are written) or device buffers (out_on_device = 1, asynchronous on
  * hip_stream unless parseval is requested, which waits for the stream).
  * The density is FP32 (AO values built in FP64 and rounded once, weights
- * contracted on the matrix cores with FP64 sums over each 16 functions),
+ * contracted on the matrix cores with FP64 sums over each 16 functions;
+ * SCFF_BF16X3 splits weights and AO values into BF16 hi + lo halves and
+ * keeps hi*hi + hi*lo + lo*hi, about 2^-16 relative per product, in half
+ * the matrix-core instructions),
  * the transform FP32 radix-2, the corner phase FP64.  The context's
  * screening threshold is not applied (primitives below the FP32 range are
  * skipped); the spin factor is.  Basis size: up to 1232 functions.
@@ -294,8 +299,8 @@ typedef struct {
     double L[3];      /* box lengths, bohr */
 } scff_fft_grid;
 
-int scff_eval_fft(scff_ctx* ctx, const scff_fft_grid* grid, float* f, float* f2, float* phi, double* parseval,
-                  int out_on_device, void* hip_stream);
+int scff_eval_fft(scff_ctx* ctx, const scff_fft_grid* grid, int precision, float* f, float* f2, float* phi,
+                  double* parseval, int out_on_device, void* hip_stream);
 
 /* With scff_set_timing(ctx, 1): HIP-event durations (ms) of the last
  * scff_eval_fft's weight packing, transition-density kernel, and transforms

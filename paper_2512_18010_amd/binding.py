@@ -114,7 +114,8 @@ scff_export_vtensors = _fn("scff_export_vtensors", c_int,
 scff_eval_separable = _fn("scff_eval_separable", c_int,
                           [c_void_p, P(scff_grid), P(c_double), P(c_double), P(c_double), P(c_double)])
 scff_eval_fft = _fn("scff_eval_fft", c_int,
-                    [c_void_p, P(scff_fft_grid), c_void_p, c_void_p, c_void_p, P(c_double), c_int, c_void_p])
+                    [c_void_p, P(scff_fft_grid), c_int, c_void_p, c_void_p, c_void_p, P(c_double), c_int,
+                     c_void_p])
 scff_eval_spherical = _fn("scff_eval_spherical", c_int,
                           [c_void_p, c_int, c_int, P(c_double), c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                            c_int, c_void_p])
@@ -323,23 +324,25 @@ class Context:
                              f2.data_ptr() if f2 is not None else None, 1, _stream_ptr(stream)))
         return f, f2
 
-    def eval_fft_host(self, n, xmin, L, want_f=True, want_f2=True, want_phi=False, parseval=True):
+    def eval_fft_host(self, n, xmin, L, want_f=True, want_f2=True, want_phi=False, parseval=True,
+                      precision="fp32"):
         """FFT method on the box [xmin, xmin + L) sampled at n points per axis (host outputs):
         (f complex64 [s,n0,n1,n2] or None, f2 or None, phi float32 [s,n0,n1,n2] or None,
-        parseval float64 [s, 2] or None)."""
+        parseval float64 [s, 2] or None).  precision: "fp32" or "bf16x3" (density contraction)."""
         g = make_fft_grid(n, xmin, L)
         shape = (self.n_states,) + tuple(int(x) for x in n)
         f = np.empty(shape + (2,), np.float32) if want_f else None
         f2 = np.empty(shape, np.float32) if want_f2 else None
         phi = np.empty(shape, np.float32) if want_phi else None
         ps = np.empty((self.n_states, 2), np.float64) if parseval else None
-        check(scff_eval_fft(self._h, ctypes.byref(g), f.ctypes.data if f is not None else None,
+        check(scff_eval_fft(self._h, ctypes.byref(g), PRECISIONS[precision],
+                            f.ctypes.data if f is not None else None,
                             f2.ctypes.data if f2 is not None else None,
                             phi.ctypes.data if phi is not None else None,
                             _d(ps) if ps is not None else None, 0, None))
         return (f.view(np.complex64)[..., 0] if f is not None else None), f2, phi, ps
 
-    def eval_fft_device(self, n, xmin, L, f=None, f2=None, phi=None, stream=None):
+    def eval_fft_device(self, n, xmin, L, f=None, f2=None, phi=None, stream=None, precision="fp32"):
         """FFT method into torch tensors f ([s,n0,n1,n2,2] float32), f2 / phi ([s,n0,n1,n2] float32)."""
         import torch
         g = make_fft_grid(n, xmin, L)
@@ -350,7 +353,8 @@ class Context:
             _check_device_tensor(f2, "f2", torch.float32, shape, self.device)
         if phi is not None:
             _check_device_tensor(phi, "phi", torch.float32, shape, self.device)
-        check(scff_eval_fft(self._h, ctypes.byref(g), f.data_ptr() if f is not None else None,
+        check(scff_eval_fft(self._h, ctypes.byref(g), PRECISIONS[precision],
+                            f.data_ptr() if f is not None else None,
                             f2.data_ptr() if f2 is not None else None,
                             phi.data_ptr() if phi is not None else None, None, 1, _stream_ptr(stream)))
         return f, f2, phi

@@ -179,11 +179,13 @@ struct FftMol {
 constexpr size_t kFftLdsBytes = (size_t)78 << 10;
 // LDS bytes of one density workgroup for nbf_pad basis rows.
 size_t fft_density_lds(int nbf_pad);
-hipError_t launch_fft_pack(const double* T, const double* cnorm, int nbf, int ns, int RB, int KS, double spin,
-                           float* Ap, hipStream_t st);
-hipError_t launch_fft_density(const FftMol& m, const float* Ap, int nbf_pad, int ns, int RB, int KS, const int n[3],
-                              const double x0[3], const double h[3], float* Z, float* phi, double* psum,
-                              size_t lds_limit, long long* n_part, hipStream_t st);
+// precision: SCFF_FP32 (FP32 weights, Ap holds ns RB KS 64 floats) or
+// SCFF_BF16X3 (split-BF16 weight pairs, the same bytes as ns RB KS/2 64 uint2).
+hipError_t launch_fft_pack(int precision, const double* T, const double* cnorm, int nbf, int ns, int RB, int KS,
+                           double spin, void* Ap, hipStream_t st);
+hipError_t launch_fft_density(int precision, const FftMol& m, const void* Ap, int nbf_pad, int ns, int RB, int KS,
+                              const int n[3], const double x0[3], const double h[3], float* Z, float* phi,
+                              double* psum, size_t lds_limit, long long* n_part, hipStream_t st);
 hipError_t launch_fft_lines(float2* Z, int nb, const int n[3], hipStream_t st);
 hipError_t launch_fft_finish(const float2* Z, const int n[3], int ns, double vpix, const double u[3], float2* f,
                              float* f2, double* psum, long long* n_part, hipStream_t st);

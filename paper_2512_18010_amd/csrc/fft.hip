@@ -31,6 +31,19 @@
 namespace scff {
 
 typedef float fft_floatx4 __attribute__((ext_vector_type(4)));
+typedef float fft_floatx2 __attribute__((ext_vector_type(2)));
+typedef unsigned int fft_uintx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 fft_bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 fft_bf16x8 __attribute__((ext_vector_type(8)));
+
+// Split-BF16 of one value in one dword: hi = RNE(v) in the low half,
+// lo = RNE(v - hi) in the high half (v - hi is exact in FP32).
+__device__ inline uint32_t fft_split(float v) {
+    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(fft_floatx2{v, 0.f}, fft_bf16x2)) & 0xffffu;
+    const float r = v - __builtin_bit_cast(float, h << 16);
+    const uint32_t l = __builtin_bit_cast(uint32_t, __builtin_convertvector(fft_floatx2{r, 0.f}, fft_bf16x2)) & 0xffffu;
+    return h | (l << 16);
+}
 
 // Primitives whose exponent argument alpha r^2 exceeds this are skipped (the
 // paper's thresholding of negligible primitives): e^{-103} is below the
@@ -61,6 +74,38 @@ __global__ void fft_pack_kernel(const double* __restrict__ T, const double* __re
             v = spin * cnorm[mu] * cnorm[nu] * t;
         }
         Ap[i] = (float)v;
+    }
+}
+
+// Split-BF16 A operands of v_mfma_f32_16x16x32_bf16 for the same weights:
+// k-group t holds nu = 8 t .. 8 t + 7; lane (row = lane % 16, kk = lane / 16)
+// carries nu0 = 8 t + kk and nu1 = 8 t + 4 + kk as (hi(nu0) | hi(nu1) << 16,
+// lo(nu0) | lo(nu1) << 16) in Ap[((s RB + rb) KS8 + t) 64 + lane].
+__global__ void fft_pack_bf_kernel(const double* __restrict__ T, const double* __restrict__ cnorm, int nbf, int ns,
+                                   int RB, int KS8, double spin, uint2* __restrict__ Ap) {
+    const long long total = (long long)ns * RB * KS8 * 64;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int lane = (int)(i & 63);
+        long long r = i >> 6;
+        const int t = (int)(r % KS8);
+        r /= KS8;
+        const int rb = (int)(r % RB);
+        const int s = (int)(r / RB);
+        const int mu = 16 * rb + (lane & 15);
+        const double* Ts = T + (size_t)s * nbf * nbf;
+        uint32_t w[2];
+        for (int h = 0; h < 2; ++h) {
+            const int nu = 8 * t + 4 * h + (lane >> 4);
+            double v = 0.0;
+            if (mu < nbf && nu < nbf && mu <= nu) {
+                const double tt =
+                    mu == nu ? Ts[(size_t)mu * nbf + mu] : Ts[(size_t)mu * nbf + nu] + Ts[(size_t)nu * nbf + mu];
+                v = spin * cnorm[mu] * cnorm[nu] * tt;
+            }
+            w[h] = fft_split((float)v);
+        }
+        Ap[i] = make_uint2((w[0] & 0xffffu) | (w[1] << 16), (w[0] >> 16) | (w[1] & 0xffff0000u));
     }
 }
 
@@ -117,7 +162,12 @@ __device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, 
 // workgroup small, so up to 8 waves per SIMD hide the operand latencies; the
 // four waves read the same A operands at nearly the same time, mostly from
 // the vector L1.
-__global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const float* __restrict__ Ap, int nbf_pad, int ns,
+// BF: split-BF16 contraction (three products per k item pair in one
+// v_mfma_f32_16x16x32_bf16, as the Cartesian split-BF16 path): the AO block is
+// split once per tile in LDS (hi | lo << 16 per value), A comes from
+// fft_pack_bf_kernel, k-groups of 8 functions per MFMA.
+template <bool BF>
+__global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* __restrict__ Av, int nbf_pad, int ns,
                                                           int RB, int KS, int3 n, double3 x0, double3 h,
                                                           long long npts, float* __restrict__ Z,
                                                           float* __restrict__ phi_out, double* __restrict__ psum) {
@@ -146,16 +196,62 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const float*
         }
     }
     __syncthreads();
+    uint32_t* pu = reinterpret_cast<uint32_t*>(ph);
+    if constexpr (BF) {
+        for (int i = tid; i < nbf_pad * NP; i += 256) pu[i] = fft_split(ph[i]);
+        __syncthreads();
+    }
 
     const int kk = lane >> 4, col = lane & 15;
     const float* phc = ph + col;   // phi[row][col] = phc[row * NP]
+    const uint32_t* puc = pu + col;
     const long long g = p0 + col;
     const bool valid = g < npts;
+    // the AO value of row r at this lane's point (hi + lo in the split form)
+    auto phi_at = [&](int r) -> double {
+        if constexpr (BF) {
+            const uint32_t x = puc[r * NP];
+            return (double)__builtin_bit_cast(float, x << 16) + (double)__builtin_bit_cast(float, x & 0xffff0000u);
+        } else {
+            return (double)phc[r * NP];
+        }
+    };
     for (int s = 0; s < ns; ++s) {
         double acc = 0.0;
         for (int rb = wave; rb < RB; rb += 4) {
             fft_floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-            const float* ap = Ap + (size_t)(s * RB + rb) * KS * 64 + lane;
+            if constexpr (BF) {
+                // k-groups 2 rb .. KS/2 - 1 (an even number of them), A loaded 8 groups ahead
+                const int KS8 = KS / 2, t0 = 2 * rb, nk = KS8 - t0;
+                const uint2* ap = reinterpret_cast<const uint2*>(Av) + (size_t)(s * RB + rb) * KS8 * 64 + lane;
+                uint2 A0[8], A1[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) A0[j] = ap[(size_t)(t0 + j) * 64];
+                auto step = [&](const uint2 a, int t, fft_floatx4& c) {
+                    const uint32_t x0v = puc[(8 * t + kk) * NP], x1v = puc[(8 * t + 4 + kk) * NP];
+                    const uint32_t hr = (x0v & 0xffffu) | (x1v << 16), lr = (x0v >> 16) | (x1v & 0xffff0000u);
+                    const fft_bf16x8 A = __builtin_bit_cast(fft_bf16x8, fft_uintx4{a.y, 0u, a.x, a.x});
+                    const fft_bf16x8 B = __builtin_bit_cast(fft_bf16x8, fft_uintx4{hr, lr, hr, lr});
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, c, 0, 0, 0);
+                };
+                for (int t = 0; t < nk; t += 16) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) A1[j] = ap[(size_t)(t0 + t + 8 + j) * 64];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (t + j < nk) step(A0[j], t0 + t + j, (j & 1) ? c1 : c0);
+                    if (t + 8 >= nk) break;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) A0[j] = ap[(size_t)(t0 + t + 16 + j) * 64];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (t + 8 + j < nk) step(A1[j], t0 + t + 8 + j, (j & 1) ? c1 : c0);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc += phi_at(16 * rb + 4 * kk + i) * ((double)c0[i] + (double)c1[i]);
+                continue;
+            }
+            const float* ap = reinterpret_cast<const float*>(Av) + (size_t)(s * RB + rb) * KS * 64 + lane;
             // k-steps k0 .. KS-1 (a multiple of 4 of them).  The A operands of
             // the next 8 k-steps are loaded while the current 8 run (two
             // register sets); loads past the row block read the next block or
@@ -191,8 +287,7 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const float*
             }
             // lane (kk, col) holds rows 4 kk + i of column col
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                acc += (double)phc[(16 * rb + 4 * kk + i) * NP] * ((double)c0[i] + (double)c1[i]);
+            for (int i = 0; i < 4; ++i) acc += phi_at(16 * rb + 4 * kk + i) * ((double)c0[i] + (double)c1[i]);
         }
         acc += __shfl_xor(acc, 16);
         acc += __shfl_xor(acc, 32);
@@ -377,16 +472,21 @@ __global__ __launch_bounds__(256) void fft_sum_kernel(const double* __restrict__
 
 size_t fft_density_lds(int nbf_pad) { return (size_t)nbf_pad * kFftTile * sizeof(float) + 4 * 16 * sizeof(double); }
 
-hipError_t launch_fft_pack(const double* T, const double* cnorm, int nbf, int ns, int RB, int KS, double spin,
-                           float* Ap, hipStream_t st) {
-    const long long total = (long long)ns * RB * KS * 64;
+hipError_t launch_fft_pack(int precision, const double* T, const double* cnorm, int nbf, int ns, int RB, int KS,
+                           double spin, void* Ap, hipStream_t st) {
+    const long long total = (long long)ns * RB * (precision == SCFF_BF16X3 ? KS / 2 : KS) * 64;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(fft_pack_kernel, dim3(blocks), dim3(256), 0, st, T, cnorm, nbf, ns, RB, KS, spin, Ap);
+    if (precision == SCFF_BF16X3)
+        hipLaunchKernelGGL(fft_pack_bf_kernel, dim3(blocks), dim3(256), 0, st, T, cnorm, nbf, ns, RB, KS / 2, spin,
+                           (uint2*)Ap);
+    else
+        hipLaunchKernelGGL(fft_pack_kernel, dim3(blocks), dim3(256), 0, st, T, cnorm, nbf, ns, RB, KS, spin,
+                           (float*)Ap);
     return hipGetLastError();
 }
 
-hipError_t launch_fft_density(const FftMol& m, const float* Ap, int nbf_pad, int ns, int RB, int KS, const int n[3],
-                              const double x0[3], const double h[3], float* Z, float* phi, double* psum,
+hipError_t launch_fft_density(int precision, const FftMol& m, const void* Ap, int nbf_pad, int ns, int RB, int KS,
+                              const int n[3], const double x0[3], const double h[3], float* Z, float* phi, double* psum,
                               size_t lds_limit, long long* n_part, hipStream_t st) {
     const long long npts = (long long)n[0] * n[1] * n[2];
     const size_t lds = fft_density_lds(nbf_pad);
@@ -394,15 +494,21 @@ hipError_t launch_fft_density(const FftMol& m, const float* Ap, int nbf_pad, int
     const long long tiles = (npts + kFftTile - 1) / kFftTile;
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
     *n_part = tiles;
+    const bool bf = precision == SCFF_BF16X3;
+    const void* fn = bf ? (const void*)fft_density_kernel<true> : (const void*)fft_density_kernel<false>;
     if (lds > 65536) {
         // dynamic LDS beyond 64 KiB per workgroup must be allowed explicitly
-        const hipError_t e =
-            hipFuncSetAttribute((const void*)fft_density_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fft_density_kernel, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns, RB, KS,
-                       make_int3(n[0], n[1], n[2]), make_double3(x0[0], x0[1], x0[2]),
-                       make_double3(h[0], h[1], h[2]), npts, Z, phi, psum);
+    const int3 nn = make_int3(n[0], n[1], n[2]);
+    const double3 xx = make_double3(x0[0], x0[1], x0[2]), hh = make_double3(h[0], h[1], h[2]);
+    if (bf)
+        hipLaunchKernelGGL(fft_density_kernel<true>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns,
+                           RB, KS, nn, xx, hh, npts, Z, phi, psum);
+    else
+        hipLaunchKernelGGL(fft_density_kernel<false>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns,
+                           RB, KS, nn, xx, hh, npts, Z, phi, psum);
     return hipGetLastError();
 }
 

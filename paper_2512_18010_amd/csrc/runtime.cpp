@@ -1052,10 +1052,12 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 
 }  // namespace
 
-int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, float* phi, double* parseval,
-                  int out_on_device, void* hip_stream) {
+int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, int precision, float* f, float* f2, float* phi,
+                  double* parseval, int out_on_device, void* hip_stream) {
     if (!c) return fail(SCFF_EINVAL, "ctx is NULL");
     if (!g) return fail(SCFF_EINVAL, "grid is NULL");
+    if (precision != SCFF_FP32 && precision != SCFF_BF16X3)
+        return fail(SCFF_EINVAL, "precision must be SCFF_FP32 or SCFF_BF16X3");
     for (int a = 0; a < 3; ++a) {
         const int na = g->n[a];
         if (na < 1 || na > 1024 || (na & (na - 1)))
@@ -1080,7 +1082,8 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, floa
     const long long npts = (long long)g->n[0] * g->n[1] * g->n[2];
     const size_t nout = (size_t)npts * ns;
     const long long part_d = (npts + 15) / 16, part_f = (npts + 63) / 64;
-    // the density kernel loads A operands up to 24 k-steps past a row block (unused): slack of 32
+    // the density kernel loads A operands up to 24 k-steps (FP32) or 15 k-groups of 8 bytes (split
+    // BF16) past a row block (unused): slack of 32 x 64 floats covers both
     if ((rc = dev_reserve(c, c->d_fft_A, ((size_t)ns * RB * KS + 32) * 64 * sizeof(float))) ||
         (rc = dev_reserve(c, c->d_fft_Z, (size_t)nb * npts * sizeof(float2))))
         return rc;
@@ -1121,11 +1124,11 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, float* f, float* f2, floa
     long long np_d = 0, np_f = 0;
     c->fft_recorded = false;
     if ((rc = record(c, EV_FFT0, st))) return rc;
-    if ((rc = hip_check(launch_fft_pack((const double*)c->d_T.p, m.cnorm, nbf, ns, RB, KS, c->spin,
-                                       (float*)c->d_fft_A.p, st),
+    if ((rc = hip_check(launch_fft_pack(precision, (const double*)c->d_T.p, m.cnorm, nbf, ns, RB, KS, c->spin,
+                                       c->d_fft_A.p, st),
                         "FFT weight packing")) ||
         (rc = record(c, EV_FFT1, st)) ||
-        (rc = hip_check(launch_fft_density(m, (const float*)c->d_fft_A.p, nbf_pad, ns, RB, KS, g->n, g->xmin, h,
+        (rc = hip_check(launch_fft_density(precision, m, c->d_fft_A.p, nbf_pad, ns, RB, KS, g->n, g->xmin, h,
                                            (float*)c->d_fft_Z.p, dphi, part, lds_limit, &np_d, st),
                         "transition density kernel")) ||
         (rc = record(c, EV_FFT2, st)))

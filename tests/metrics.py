@@ -12,6 +12,9 @@ TOL_F2 = {"fp32": 1e-6, "bf16x3": 1e-4}
 # FFT method against the oracle's FFT method on the same grid (FP32 density
 # and FP32 radix-2 transforms)
 TOL_FFT = 1e-6
+# split-BF16 density contraction: three products of 8-bit halves (about
+# 2^-16 relative each, over sums of a few hundred terms)
+TOL_FFT_BF16 = 1e-4
 
 # Error lines recorded by the GPU tests, printed in the terminal summary of
 # the run (so the error of every transition is visible without -s).

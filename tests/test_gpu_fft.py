@@ -9,6 +9,7 @@ of grid points against the oracle's density, and the transform against the
 oracle's transform steps applied to the GPU's own density; the two stages
 then cover the whole path.
 """
+import ctypes
 import dataclasses
 import os
 import sys
@@ -17,7 +18,7 @@ import numpy as np
 import pytest
 
 import workload as wl
-from tests.metrics import TOL_FFT, errors, report
+from tests.metrics import TOL_FFT, TOL_FFT_BF16, errors, report
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +45,7 @@ def load(eng, mol, T, spin=1.0):
     eng.set_options(0.0, spin)
 
 
-def compare(name, oracle_mod, mol, T, n, xmin, L, f, f2, phi, ps, spin=1.0):
+def compare(name, oracle_mod, mol, T, n, xmin, L, f, f2, phi, ps, spin=1.0, tol=TOL_FFT):
     f_ref, phi_ref = oracle_mod.fft_form_factor(mol, T, n, xmin, L, spin_factor=spin, n_threads=NTH)
     ns = T.shape[0]
     e = errors(f, f_ref)
@@ -56,9 +57,9 @@ def compare(name, oracle_mod, mol, T, n, xmin, L, f, f2, phi, ps, spin=1.0):
         f"phi {ephi.max():.2e} parseval {eps_p.max():.2e}")
     report(f"[fft {name}] |f|^2 per transition: " + " ".join(f"{x:.2e}" for x in e["f2_peak_norm"]))
     np.testing.assert_allclose(f2, np.abs(f) ** 2, rtol=2e-6, atol=1e-12 * np.abs(f).max() ** 2)
-    assert e["f2_peak_norm"].max() <= TOL_FFT, e["f2_peak_norm"]
-    assert ephi.max() <= TOL_FFT, ephi
-    assert eps_p.max() <= TOL_FFT, (ps, a, b)
+    assert e["f2_peak_norm"].max() <= tol, e["f2_peak_norm"]
+    assert ephi.max() <= tol, ephi
+    assert eps_p.max() <= tol, (ps, a, b)
     # the GPU's own two Parseval sums agree (identity of the discrete transform)
     assert np.abs(ps[:, 0] / ps[:, 1] - 1).max() <= TOL_FFT
 
@@ -100,14 +101,36 @@ def test_fft_large_basis_tiles(eng, oracle_mod, n_heavy, n_states):
     compare(f"{mol.nbf} bf", oracle_mod, mol, T, n, xmin, L, f, f2, phi, ps)
 
 
-def test_fft_benchmark_size_sampled(eng, oracle_mod):
+@pytest.mark.parametrize("n_heavy,n_states", [(4, 1), (36, 3)])
+def test_fft_bf16x3_matches_oracle(eng, oracle_mod, n_heavy, n_states):
+    """Split-BF16 density contraction: config-0-sized and 685-function bases
+    against the oracle, element by element, at the split-BF16 tolerance."""
+    rng = np.random.Generator(np.random.PCG64(970 + n_heavy))
+    if n_heavy == 4:
+        W = wl.make_config(0)
+        mol, T, box = W.mol, W.T, (16, 32, 8)
+    else:
+        mol = wl.make_molecule(rng, n_heavy, int(round(0.8 * n_heavy)), layout="box",
+                               box_A=12.0 * (n_heavy / 30.0) ** (1 / 3))
+        T = wl.make_transitions(rng, mol.nbf, wl.n_occupied(mol.Z), n_states)
+        box = (8, 16, 16)
+    n, xmin, L = wl.fft_box(mol, box, margin_bohr=3.0, scale=1.0)
+    load(eng, mol, T, spin=np.sqrt(2.0))
+    f, f2, phi, ps = eng.eval_fft_host(n, xmin, L, want_phi=True, precision="bf16x3")
+    compare(f"bf16x3 {mol.nbf} bf", oracle_mod, mol, T, n, xmin, L, f, f2, phi, ps, spin=np.sqrt(2.0),
+            tol=TOL_FFT_BF16)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_fft_benchmark_size_sampled(eng, oracle_mod, precision):
     """Config-1 molecule and its 12 transitions on the benchmark's 128^3 box:
     the density on 400 seeded grid points against the oracle's FP64 density,
     and f against the oracle's transform of the GPU's own density."""
+    tol = TOL_FFT if precision == "fp32" else TOL_FFT_BF16
     W = wl.make_config(1)
     n, xmin, L = wl.fft_box(W.mol, (128, 128, 128))
     load(eng, W.mol, W.T)
-    f, f2, phi, ps = eng.eval_fft_host(n, xmin, L, want_phi=True)
+    f, f2, phi, ps = eng.eval_fft_host(n, xmin, L, want_phi=True, precision=precision)
     ns = W.T.shape[0]
     rng = np.random.Generator(np.random.PCG64(77))
     idx = rng.integers(0, np.prod(n), size=400)
@@ -122,10 +145,11 @@ def test_fft_benchmark_size_sampled(eng, oracle_mod):
     ephi = np.abs(got - ref).max(axis=1) / peak
     f_ref, _ = oracle_mod.fft_form_factor(W.mol, W.T, n, xmin, L, phi=phi.astype(np.float64))
     e = errors(f, f_ref)
-    log(f"[fft cfg1 128^3] phi sampled {ephi.max():.2e}, transform |f|^2 {e['f2_peak_norm'].max():.2e}")
-    report("[fft cfg1 128^3] density, per transition: " + " ".join(f"{x:.2e}" for x in ephi))
-    report("[fft cfg1 128^3] transform |f|^2, per transition: " + " ".join(f"{x:.2e}" for x in e["f2_peak_norm"]))
-    assert ephi.max() <= TOL_FFT, ephi
+    log(f"[fft cfg1 128^3 {precision}] phi sampled {ephi.max():.2e}, transform |f|^2 {e['f2_peak_norm'].max():.2e}")
+    report(f"[fft cfg1 128^3 {precision}] density, per transition: " + " ".join(f"{x:.2e}" for x in ephi))
+    report(f"[fft cfg1 128^3 {precision}] transform |f|^2, per transition: " +
+           " ".join(f"{x:.2e}" for x in e["f2_peak_norm"]))
+    assert ephi.max() <= tol, ephi
     assert e["f2_peak_norm"].max() <= TOL_FFT, e["f2_peak_norm"]
     assert np.abs(ps[:, 0] / ps[:, 1] - 1).max() <= TOL_FFT
 
@@ -163,6 +187,11 @@ def test_fft_argument_errors(eng):
     with pytest.raises(binding.ScffError) as ei:
         eng.eval_fft_host(n, xmin, L, want_f=False, want_f2=False, want_phi=False, parseval=False)
     assert ei.value.code == binding.SCFF_EINVAL
+    g = binding.make_fft_grid(n, xmin, L)
+    ps = np.empty((1, 2), np.float64)
+    rc = binding.scff_eval_fft(eng._h, ctypes.byref(g), 7, None, None, None,
+                               ps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, None)
+    assert rc == binding.SCFF_EINVAL
     fresh = binding.Context(0)
     try:
         with pytest.raises(binding.ScffError) as ei:
