@@ -177,8 +177,9 @@ struct FftMol {
 // LDS a density workgroup may hold (its AO block grows with the basis: up to
 // 1232 functions).
 constexpr size_t kFftLdsBytes = (size_t)78 << 10;
-// LDS bytes of one density workgroup for nbf_pad basis rows.
-size_t fft_density_lds(int nbf_pad);
+// Column blocks of 16 points per density workgroup for nbf_pad basis rows
+// (4, 2 or 1), 0 if the AO block does not fit lds_limit bytes of LDS.
+int fft_density_cb(int nbf_pad, size_t lds_limit);
 // precision: SCFF_FP32 (FP32 weights, Ap holds ns RB KS 64 floats) or
 // SCFF_BF16X3 (split-BF16 weight pairs, the same bytes as ns RB KS/2 64 uint2).
 hipError_t launch_fft_pack(int precision, const double* T, const double* cnorm, int nbf, int ns, int RB, int KS,

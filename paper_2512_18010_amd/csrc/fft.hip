@@ -51,7 +51,6 @@ __device__ inline uint32_t fft_split(float v) {
 constexpr double kExpCut = 103.0;
 
 // Grid points per density workgroup: one MFMA column block.
-constexpr int kFftTile = 16;
 
 namespace {
 
@@ -110,10 +109,10 @@ __global__ void fft_pack_bf_kernel(const double* __restrict__ T, const double* _
 }
 
 // AO values of one shell at one point before the contracted normalisation
-// (c_mu is folded into the packed weights), FP64, rounded to FP32 into
-// ph[(bf0 + c) * RS + p] for each Cartesian component c (RS: LDS row stride).
-__device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, double y, double z, float* ph, int RS,
-                                             int p) {
+// (c_mu is folded into the packed weights), FP64, handed to put(row, value)
+// for each Cartesian component (row = bf0 + c).
+template <typename Put>
+__device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, double y, double z, Put put) {
     const PrepShell S = m.shells[sh];
     const double* A = m.xyz + 3 * S.atom;
     const double dx = x - A[0], dy = y - A[1], dz = z - A[2];
@@ -136,180 +135,268 @@ __device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, 
         }
     }
     const int b0 = m.bf0[sh];
-    float* o = ph + (size_t)b0 * RS + p;
     if (S.l == 0) {
-        o[0] = (float)ra;
+        put(b0, ra);
     } else if (S.l == 1) {
-        o[0] = (float)(dx * ra);
-        o[RS] = (float)(dy * ra);
-        o[2 * RS] = (float)(dz * ra);
+        put(b0, dx * ra);
+        put(b0 + 1, dy * ra);
+        put(b0 + 2, dz * ra);
     } else {
-        o[0] = (float)(dx * dx * ra);
-        o[RS] = (float)(dx * dy * rb);
-        o[2 * RS] = (float)(dx * dz * rb);
-        o[3 * RS] = (float)(dy * dy * ra);
-        o[4 * RS] = (float)(dy * dz * rb);
-        o[5 * RS] = (float)(dz * dz * ra);
+        put(b0, dx * dx * ra);
+        put(b0 + 1, dx * dy * rb);
+        put(b0 + 2, dx * dz * rb);
+        put(b0 + 3, dy * dy * ra);
+        put(b0 + 4, dy * dz * rb);
+        put(b0 + 5, dz * dz * ra);
     }
 }
 
-// One workgroup (4 waves) per tile of 16 consecutive grid points (flattened
-// [ix][iy][iz], z fastest).  Wave w takes the row blocks rb = w (mod 4) of
-// every state; the four partial densities of a point are summed through LDS
-// at the end of each state.  LDS: phi[nbf_pad][16] FP32 (a wave reads rows
-// 4 ks + kk, kk = 0..3, at the 16 points per MFMA operand: 64 distinct
-// banks), then 4 x 16 FP64 for the sum.  Small tiles keep the LDS per
-// workgroup small, so up to 8 waves per SIMD hide the operand latencies; the
-// four waves read the same A operands at nearly the same time, mostly from
-// the vector L1.
-// BF: split-BF16 contraction (three products per k item pair in one
-// v_mfma_f32_16x16x32_bf16, as the Cartesian split-BF16 path): the AO block is
-// split once per tile in LDS (hi | lo << 16 per value), A comes from
-// fft_pack_bf_kernel, k-groups of 8 functions per MFMA.
-template <bool BF>
+// LDS bytes of a density workgroup: the AO block of nbf_pad rows x 16 CB
+// points (4 bytes per value in either layout) and two buffers of 4 x 16 CB
+// FP64 partial densities.
+__host__ __device__ constexpr size_t fft_lds_bytes(int nbf_pad, int cb) {
+    return (size_t)cb * (64 * (size_t)nbf_pad + 1024);
+}
+
+// One workgroup (4 waves) per tile of NP = 16 CB consecutive grid points
+// (flattened [ix][iy][iz], z fastest; column c = 16 cb + col of the tile).
+//
+// AO phase: a lane evaluates one shell at one point (64 / NP shells per wave
+// step; with NP = 64 every lane of a wave takes the same shell, so its data
+// are scalar loads), FP64, rounded into the LDS block:
+//   FP32  phi(r, c) at float index r NP + col CB + cb, so that a lane reads the
+//         CB values of its column in one ds_read (b32 / b64 / b128) and a
+//         quarter wave reads one contiguous run (no bank conflicts);
+//   BF    split halves, laid out as the B operands of v_mfma_f32_16x16x32_bf16:
+//         entry (t, j, col) for rows 8t + j and 8t + 4 + j (j < 4) holds
+//         hr = hi(8t+j) | hi(8t+4+j) << 16 and lr = lo(..) | lo(..) << 16;
+//         CB = 1: uint2 {hr, lr} at entry (4t + j) 16 + col; CB >= 2: uint4
+//         {hr, lr of column block 2P, hr, lr of 2P + 1} at entry
+//         ((P T8 + t) 4 + j) 16 + col (T8 = nbf_pad / 8).
+//
+// Contraction: wave w takes row blocks rb of 16 functions in a snake order
+// (0 1 2 3 3 2 1 0 ...), which evens out the triangle's rows; per row block
+// the k-steps from the diagonal block on, with the A operands of the next 8
+// k-steps loaded while the current 8 run and each A operand used by CB
+// MFMAs.  The 16-row block is folded into FP64 with its AO values, the four
+// waves' partial densities are summed through LDS (double-buffered by state
+// parity: one barrier per state) and wave 0 writes the tile.
+template <bool BF, int CB>
 __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* __restrict__ Av, int nbf_pad, int ns,
                                                           int RB, int KS, int3 n, double3 x0, double3 h,
                                                           long long npts, float* __restrict__ Z,
                                                           float* __restrict__ phi_out, double* __restrict__ psum) {
     extern __shared__ __align__(16) float fft_lds[];
-    constexpr int NP = kFftTile;
+    constexpr int NP = 16 * CB;
+    constexpr int NCH = CB == 1 ? 2 : CB;   // independent MFMA accumulator chains
     const int tid = threadIdx.x, lane = tid & 63;
     // wave-uniform: the row-block loop and the A-operand addresses stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const long long p0 = (long long)blockIdx.x * NP;
+    const int T8 = nbf_pad / 8;
     float* ph = fft_lds;
+    uint32_t* pu = reinterpret_cast<uint32_t*>(fft_lds);
+    unsigned short* ps16 = reinterpret_cast<unsigned short*>(fft_lds);
     double* red = reinterpret_cast<double*>(fft_lds + (size_t)nbf_pad * NP);
 
-    for (int i = tid; i < nbf_pad * NP; i += 256) ph[i] = 0.f;
+    for (int i = tid; i < nbf_pad * NP; i += 256) pu[i] = 0u;
     __syncthreads();
     {
-        // one lane per (shell, point): a wave takes 4 shells at a time
+        constexpr int SPI = 64 / NP;   // shells per wave step
         const int p = lane % NP;
         const long long g = p0 + p;
         const int iz = (int)(g % n.z);
         const long long r1 = g / n.z;
         const int iy = (int)(r1 % n.y), ix = (int)(r1 / n.y);
         const double x = x0.x + ix * h.x, y = x0.y + iy * h.y, z = x0.z + iz * h.z;
-        for (int sh0 = wave * 4; sh0 < m.n_shells; sh0 += 16) {
+        const int col = p & 15, cb = p >> 4;
+        auto put = [&](int r, double v) {
+            if constexpr (BF) {
+                const uint32_t w = fft_split((float)v);
+                const int t = r >> 3, j = r & 3, hh = (r >> 2) & 1;
+                int wd;   // dword of hr; lr follows
+                if constexpr (CB == 1)
+                    wd = ((t * 4 + j) * 16 + col) * 2;
+                else
+                    wd = ((((cb >> 1) * T8 + t) * 4 + j) * 16 + col) * 4 + 2 * (cb & 1);
+                ps16[2 * wd + hh] = (unsigned short)(w & 0xffffu);
+                ps16[2 * wd + 2 + hh] = (unsigned short)(w >> 16);
+            } else {
+                ph[r * NP + col * CB + cb] = (float)v;
+            }
+        };
+        for (int sh0 = wave * SPI; sh0 < m.n_shells; sh0 += 4 * SPI) {
             const int sh = sh0 + lane / NP;
-            if (sh < m.n_shells && g < npts) shell_values(m, sh, x, y, z, ph, NP, p);
+            if (sh < m.n_shells && g < npts) shell_values(m, sh, x, y, z, put);
         }
-    }
-    __syncthreads();
-    uint32_t* pu = reinterpret_cast<uint32_t*>(ph);
-    if constexpr (BF) {
-        for (int i = tid; i < nbf_pad * NP; i += 256) pu[i] = fft_split(ph[i]);
-        __syncthreads();
     }
 
     const int kk = lane >> 4, col = lane & 15;
-    const float* phc = ph + col;   // phi[row][col] = phc[row * NP]
-    const uint32_t* puc = pu + col;
-    const long long g = p0 + col;
-    const bool valid = g < npts;
-    // the AO value of row r at this lane's point (hi + lo in the split form)
-    auto phi_at = [&](int r) -> double {
+    // the CB AO values of row r at this lane's column (hi + lo in the split form)
+    auto phi_row = [&](int r, double (&v)[CB]) {
         if constexpr (BF) {
-            const uint32_t x = puc[r * NP];
-            return (double)__builtin_bit_cast(float, x << 16) + (double)__builtin_bit_cast(float, x & 0xffff0000u);
+            const int t = r >> 3, j = r & 3, sft = 16 * ((r >> 2) & 1);
+            auto val = [&](uint32_t hr, uint32_t lr) {
+                return (double)__uint_as_float((hr >> sft) << 16) + (double)__uint_as_float((lr >> sft) << 16);
+            };
+            if constexpr (CB == 1) {
+                const uint2 e = reinterpret_cast<const uint2*>(pu)[(t * 4 + j) * 16 + col];
+                v[0] = val(e.x, e.y);
+            } else {
+#pragma unroll
+                for (int P = 0; P < CB / 2; ++P) {
+                    const uint4 e = reinterpret_cast<const uint4*>(pu)[((P * T8 + t) * 4 + j) * 16 + col];
+                    v[2 * P] = val(e.x, e.y);
+                    v[2 * P + 1] = val(e.z, e.w);
+                }
+            }
         } else {
-            return (double)phc[r * NP];
+            const float* q = ph + r * NP + col * CB;
+            if constexpr (CB == 1) {
+                v[0] = q[0];
+            } else if constexpr (CB == 2) {
+                const float2 e = *reinterpret_cast<const float2*>(q);
+                v[0] = e.x;
+                v[1] = e.y;
+            } else {
+                const float4 e = *reinterpret_cast<const float4*>(q);
+                v[0] = e.x;
+                v[1] = e.y;
+                v[2] = e.z;
+                v[3] = e.w;
+            }
         }
     };
-    for (int s = 0; s < ns; ++s) {
-        double acc = 0.0;
-        for (int rb = wave; rb < RB; rb += 4) {
-            fft_floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-            if constexpr (BF) {
-                // k-groups 2 rb .. KS/2 - 1 (an even number of them), A loaded 8 groups ahead
-                const int KS8 = KS / 2, t0 = 2 * rb, nk = KS8 - t0;
-                const uint2* ap = reinterpret_cast<const uint2*>(Av) + (size_t)(s * RB + rb) * KS8 * 64 + lane;
-                uint2 A0[8], A1[8];
+    __syncthreads();
+
+    // one k-step (FP32: functions 4k .. 4k+3) or k-group (BF: 8t .. 8t+7) of
+    // row block rb for all CB column blocks
+    auto kstep = [&](auto a, int k, int par, fft_floatx4 (&c)[NCH]) {
+        if constexpr (BF) {
+            const fft_bf16x8 A = __builtin_bit_cast(fft_bf16x8, fft_uintx4{a.y, 0u, a.x, a.x});
+            auto mm = [&](int q, uint32_t hr, uint32_t lr) {
+                const fft_bf16x8 B = __builtin_bit_cast(fft_bf16x8, fft_uintx4{hr, lr, hr, lr});
+                c[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, c[q], 0, 0, 0);
+            };
+            if constexpr (CB == 1) {
+                const uint2 e = reinterpret_cast<const uint2*>(pu)[(k * 4 + kk) * 16 + col];
+                mm(par, e.x, e.y);
+            } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) A0[j] = ap[(size_t)(t0 + j) * 64];
-                auto step = [&](const uint2 a, int t, fft_floatx4& c) {
-                    const uint32_t x0v = puc[(8 * t + kk) * NP], x1v = puc[(8 * t + 4 + kk) * NP];
-                    const uint32_t hr = (x0v & 0xffffu) | (x1v << 16), lr = (x0v >> 16) | (x1v & 0xffff0000u);
-                    const fft_bf16x8 A = __builtin_bit_cast(fft_bf16x8, fft_uintx4{a.y, 0u, a.x, a.x});
-                    const fft_bf16x8 B = __builtin_bit_cast(fft_bf16x8, fft_uintx4{hr, lr, hr, lr});
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, c, 0, 0, 0);
-                };
-                for (int t = 0; t < nk; t += 16) {
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) A1[j] = ap[(size_t)(t0 + t + 8 + j) * 64];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        if (t + j < nk) step(A0[j], t0 + t + j, (j & 1) ? c1 : c0);
-                    if (t + 8 >= nk) break;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) A0[j] = ap[(size_t)(t0 + t + 16 + j) * 64];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        if (t + 8 + j < nk) step(A1[j], t0 + t + 8 + j, (j & 1) ? c1 : c0);
+                for (int P = 0; P < CB / 2; ++P) {
+                    const uint4 e = reinterpret_cast<const uint4*>(pu)[((P * T8 + k) * 4 + kk) * 16 + col];
+                    mm(2 * P, e.x, e.y);
+                    mm(2 * P + 1, e.z, e.w);
                 }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc += phi_at(16 * rb + 4 * kk + i) * ((double)c0[i] + (double)c1[i]);
-                continue;
             }
-            const float* ap = reinterpret_cast<const float*>(Av) + (size_t)(s * RB + rb) * KS * 64 + lane;
-            // k-steps k0 .. KS-1 (a multiple of 4 of them).  The A operands of
-            // the next 8 k-steps are loaded while the current 8 run (two
-            // register sets); loads past the row block read the next block or
-            // the array's slack and are not used
-            const int k0 = 4 * rb, nk = KS - k0;
-            float A0[8], A1[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) A0[j] = ap[(size_t)(k0 + j) * 64];
-            for (int t = 0; t < nk; t += 16) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) A1[j] = ap[(size_t)(k0 + t + 8 + j) * 64];
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (j < 4 || t + 4 < nk) {
-                        const float b = phc[(4 * (k0 + t + j) + kk) * NP];
-                        if (j & 1)
-                            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A0[j], b, c1, 0, 0, 0);
-                        else
-                            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A0[j], b, c0, 0, 0, 0);
-                    }
-                if (t + 8 >= nk) break;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) A0[j] = ap[(size_t)(k0 + t + 16 + j) * 64];
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (j < 4 || t + 12 < nk) {
-                        const float b = phc[(4 * (k0 + t + 8 + j) + kk) * NP];
-                        if (j & 1)
-                            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A1[j], b, c1, 0, 0, 0);
-                        else
-                            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A1[j], b, c0, 0, 0, 0);
-                    }
+        } else {
+            const float* q = ph + (4 * k + kk) * NP + col * CB;
+            if constexpr (CB == 1) {
+                c[par] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, q[0], c[par], 0, 0, 0);
+            } else if constexpr (CB == 2) {
+                const float2 e = *reinterpret_cast<const float2*>(q);
+                c[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, e.x, c[0], 0, 0, 0);
+                c[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, e.y, c[1], 0, 0, 0);
+            } else {
+                const float4 e = *reinterpret_cast<const float4*>(q);
+                c[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, e.x, c[0], 0, 0, 0);
+                c[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, e.y, c[1], 0, 0, 0);
+                c[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, e.z, c[2], 0, 0, 0);
+                c[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, e.w, c[3], 0, 0, 0);
             }
-            // lane (kk, col) holds rows 4 kk + i of column col
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc += phi_at(16 * rb + 4 * kk + i) * ((double)c0[i] + (double)c1[i]);
         }
-        acc += __shfl_xor(acc, 16);
-        acc += __shfl_xor(acc, 32);
-        if (lane < 16) red[wave * 16 + lane] = acc;
+    };
+
+    // the k-steps k0 .. k0 + nk - 1 of one row block (nk a multiple of GS, at
+    // least GS).  The A operands of the next 8 k-steps are loaded while the
+    // current 8 run; the row block may end only at a multiple of GS k-steps,
+    // so the MFMAs between two exits are unconditional and the accumulators
+    // keep their registers.  Loads past the row block read the next block or
+    // the array's slack and are not used.
+    constexpr int GS = BF ? 2 : 4;
+    auto run_row = [&](const auto* ap, auto (&A0)[8], auto (&A1)[8], int k0, int nk, fft_floatx4 (&c)[NCH]) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) A0[j] = ap[j * 64];
+        for (int t = 0;; t += 16) {
+            const auto* q = ap + (size_t)t * 64;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) A1[j] = q[(8 + j) * 64];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j > 0 && j % GS == 0 && t + j >= nk) return;
+                kstep(A0[j], k0 + t + j, j & 1, c);
+            }
+            if (t + 8 >= nk) return;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) A0[j] = q[(16 + j) * 64];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j > 0 && j % GS == 0 && t + 8 + j >= nk) return;
+                kstep(A1[j], k0 + t + 8 + j, j & 1, c);
+            }
+            if (t + 16 >= nk) return;
+        }
+    };
+
+    for (int s = 0; s < ns; ++s) {
+        double acc[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+        for (int i4 = 0; i4 < RB; i4 += 4) {
+            // snake order: blocks i4 .. i4+3 go to waves 0..3, then 3..0
+            const int rb = i4 + (((i4 >> 2) & 1) ? 3 - wave : wave);
+            if (rb >= RB) continue;
+            fft_floatx4 c[NCH];
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) c[q] = fft_floatx4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (BF) {
+                const int KS8 = KS / 2, k0 = 2 * rb, nk = KS8 - k0;
+                const uint2* ap = reinterpret_cast<const uint2*>(Av) + ((size_t)(s * RB + rb) * KS8 + k0) * 64 + lane;
+                uint2 A0[8], A1[8];
+                run_row(ap, A0, A1, k0, nk, c);
+            } else {
+                const int k0 = 4 * rb, nk = KS - k0;
+                const float* ap = reinterpret_cast<const float*>(Av) + ((size_t)(s * RB + rb) * KS + k0) * 64 + lane;
+                float A0[8], A1[8];
+                run_row(ap, A0, A1, k0, nk, c);
+            }
+            // lane (kk, col) holds rows 16 rb + 4 kk + i of its columns
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double v[CB];
+                phi_row(16 * rb + 4 * kk + i, v);
+#pragma unroll
+                for (int q = 0; q < CB; ++q) {
+                    const float y = CB == 1 ? c[0][i] + c[1][i] : c[q][i];
+                    acc[q] += v[q] * (double)y;
+                }
+            }
+        }
+        double* rd = red + (s & 1) * 4 * NP;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            acc[q] += __shfl_xor(acc[q], 16);
+            acc[q] += __shfl_xor(acc[q], 32);
+            if (lane < 16) rd[wave * NP + q * 16 + lane] = acc[q];
+        }
         __syncthreads();
         if (wave == 0) {
-            acc += red[16 + col] + red[32 + col] + red[48 + col];
-            if (valid && lane < 16) {
-                const float v = (float)acc;
+            const long long g = p0 + lane;
+            const bool valid = lane < NP && g < npts;
+            double d = 0.0;
+            if (lane < NP) d = rd[lane] + rd[NP + lane] + rd[2 * NP + lane] + rd[3 * NP + lane];
+            if (valid) {
+                const float v = (float)d;
                 float* zp = Z + ((size_t)(s >> 1) * npts + g) * 2;
                 zp[s & 1] = v;
                 if ((ns & 1) && s == ns - 1) zp[1] = 0.f;
                 if (phi_out) phi_out[(size_t)s * npts + g] = v;
             }
-            double q = valid ? acc * acc : 0.0;
-            q += __shfl_xor(q, 1);
-            q += __shfl_xor(q, 2);
-            q += __shfl_xor(q, 4);
-            q += __shfl_xor(q, 8);
+            double q = valid ? d * d : 0.0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) q += __shfl_xor(q, o);
             if (psum && lane == 0) psum[(size_t)s * gridDim.x + blockIdx.x] = q;
         }
-        __syncthreads();
     }
 }
 
@@ -470,8 +557,6 @@ __global__ __launch_bounds__(256) void fft_sum_kernel(const double* __restrict__
 
 }  // namespace
 
-size_t fft_density_lds(int nbf_pad) { return (size_t)nbf_pad * kFftTile * sizeof(float) + 4 * 16 * sizeof(double); }
-
 hipError_t launch_fft_pack(int precision, const double* T, const double* cnorm, int nbf, int ns, int RB, int KS,
                            double spin, void* Ap, hipStream_t st) {
     const long long total = (long long)ns * RB * (precision == SCFF_BF16X3 ? KS / 2 : KS) * 64;
@@ -485,30 +570,51 @@ hipError_t launch_fft_pack(int precision, const double* T, const double* cnorm, 
     return hipGetLastError();
 }
 
+int fft_density_cb(int nbf_pad, size_t lds_limit) {
+    // the widest tile whose block stays within 64 KiB (several workgroups per
+    // CU); 16-point tiles up to the device limit for the largest bases
+    for (int cb : {4, 2})
+        if (fft_lds_bytes(nbf_pad, cb) <= std::min<size_t>(lds_limit, 64u << 10)) return cb;
+    return fft_lds_bytes(nbf_pad, 1) <= lds_limit ? 1 : 0;
+}
+
 hipError_t launch_fft_density(int precision, const FftMol& m, const void* Ap, int nbf_pad, int ns, int RB, int KS,
                               const int n[3], const double x0[3], const double h[3], float* Z, float* phi, double* psum,
                               size_t lds_limit, long long* n_part, hipStream_t st) {
     const long long npts = (long long)n[0] * n[1] * n[2];
-    const size_t lds = fft_density_lds(nbf_pad);
-    if (lds > lds_limit) return hipErrorInvalidValue;
-    const long long tiles = (npts + kFftTile - 1) / kFftTile;
+    const int cb = fft_density_cb(nbf_pad, lds_limit);
+    if (cb == 0 || nbf_pad % 16 || KS * 4 != nbf_pad || RB * 16 != nbf_pad) return hipErrorInvalidValue;
+    const size_t lds = fft_lds_bytes(nbf_pad, cb);
+    const long long tiles = (npts + 16 * cb - 1) / (16 * cb);
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
     *n_part = tiles;
     const bool bf = precision == SCFF_BF16X3;
-    const void* fn = bf ? (const void*)fft_density_kernel<true> : (const void*)fft_density_kernel<false>;
+    const void* fns[2][3] = {{(const void*)fft_density_kernel<false, 1>, (const void*)fft_density_kernel<false, 2>,
+                              (const void*)fft_density_kernel<false, 4>},
+                             {(const void*)fft_density_kernel<true, 1>, (const void*)fft_density_kernel<true, 2>,
+                              (const void*)fft_density_kernel<true, 4>}};
+    const int ci = cb == 4 ? 2 : cb - 1;
     if (lds > 65536) {
         // dynamic LDS beyond 64 KiB per workgroup must be allowed explicitly
-        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t e = hipFuncSetAttribute(fns[bf][ci], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const int3 nn = make_int3(n[0], n[1], n[2]);
     const double3 xx = make_double3(x0[0], x0[1], x0[2]), hh = make_double3(h[0], h[1], h[2]);
-    if (bf)
-        hipLaunchKernelGGL(fft_density_kernel<true>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns,
-                           RB, KS, nn, xx, hh, npts, Z, phi, psum);
-    else
-        hipLaunchKernelGGL(fft_density_kernel<false>, dim3((unsigned)tiles), dim3(256), lds, st, m, Ap, nbf_pad, ns,
-                           RB, KS, nn, xx, hh, npts, Z, phi, psum);
+    const dim3 grid((unsigned)tiles), block(256);
+#define SCFF_FFT_DENSITY(B, C)                                                                                  \
+    hipLaunchKernelGGL((fft_density_kernel<B, C>), grid, block, lds, st, m, Ap, nbf_pad, ns, RB, KS, nn, xx, hh, \
+                       npts, Z, phi, psum)
+    if (bf) {
+        if (cb == 4) SCFF_FFT_DENSITY(true, 4);
+        else if (cb == 2) SCFF_FFT_DENSITY(true, 2);
+        else SCFF_FFT_DENSITY(true, 1);
+    } else {
+        if (cb == 4) SCFF_FFT_DENSITY(false, 4);
+        else if (cb == 2) SCFF_FFT_DENSITY(false, 2);
+        else SCFF_FFT_DENSITY(false, 1);
+    }
+#undef SCFF_FFT_DENSITY
     return hipGetLastError();
 }
 

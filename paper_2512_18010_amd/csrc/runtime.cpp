@@ -1071,7 +1071,7 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, int precision, float* f, 
     const int nbf = c->basis.nbf, ns = c->n_states;
     const int nbf_pad = (nbf + 15) & ~15;
     const size_t lds_limit = std::min(c->lds_block, kFftLdsBytes);
-    if (fft_density_lds(nbf_pad) > lds_limit)
+    if (fft_density_cb(nbf_pad, lds_limit) == 0)
         return fail(SCFF_EINVAL, "basis too large for the FFT method's density tile (" + std::to_string(nbf) +
                                      " functions)");
     int rc;
