@@ -181,7 +181,8 @@ constexpr size_t kFftLdsBytes = (size_t)78 << 10;
 // (4, 2 or 1), 0 if the AO block does not fit lds_limit bytes of LDS.
 int fft_density_cb(int nbf_pad, size_t lds_limit);
 // precision: SCFF_FP32 (FP32 weights, Ap holds ns RB KS 64 floats) or
-// SCFF_BF16X3 (split-BF16 weight pairs, the same bytes as ns RB KS/2 64 uint2).
+// SCFF_BF16X3 (split-BF16 weights of 4 functions per lane, ns RB RB 64 uint4:
+// the same bytes).
 hipError_t launch_fft_pack(int precision, const double* T, const double* cnorm, int nbf, int ns, int RB, int KS,
                            double spin, void* Ap, hipStream_t st);
 hipError_t launch_fft_density(int precision, const FftMol& m, const void* Ap, int nbf_pad, int ns, int RB, int KS,

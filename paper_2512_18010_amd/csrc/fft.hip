@@ -76,62 +76,90 @@ __global__ void fft_pack_kernel(const double* __restrict__ T, const double* __re
     }
 }
 
-// Split-BF16 A operands of v_mfma_f32_16x16x32_bf16 for the same weights:
-// k-group t holds nu = 8 t .. 8 t + 7; lane (row = lane % 16, kk = lane / 16)
-// carries nu0 = 8 t + kk and nu1 = 8 t + 4 + kk as (hi(nu0) | hi(nu1) << 16,
-// lo(nu0) | lo(nu1) << 16) in Ap[((s RB + rb) KS8 + t) 64 + lane].
+// Split-BF16 A operands for the same weights.  Function group g holds
+// nu = 16 g .. 16 g + 15; lane (row = lane % 16, kk = lane / 16) carries
+// nu_j = 16 g + 4 kk + j, j < 4, as the words (hi(nu_0) | hi(nu_1) << 16,
+// hi(nu_2) | hi(nu_3) << 16, lo(nu_0) | lo(nu_1) << 16, lo(nu_2) | lo(nu_3) << 16)
+// in Ap[((s RB + rb) RB + g) 64 + lane].
 __global__ void fft_pack_bf_kernel(const double* __restrict__ T, const double* __restrict__ cnorm, int nbf, int ns,
-                                   int RB, int KS8, double spin, uint2* __restrict__ Ap) {
-    const long long total = (long long)ns * RB * KS8 * 64;
+                                   int RB, double spin, uint4* __restrict__ Ap) {
+    const long long total = (long long)ns * RB * RB * 64;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x) {
         const int lane = (int)(i & 63);
         long long r = i >> 6;
-        const int t = (int)(r % KS8);
-        r /= KS8;
+        const int g = (int)(r % RB);
+        r /= RB;
         const int rb = (int)(r % RB);
         const int s = (int)(r / RB);
         const int mu = 16 * rb + (lane & 15);
         const double* Ts = T + (size_t)s * nbf * nbf;
-        uint32_t w[2];
-        for (int h = 0; h < 2; ++h) {
-            const int nu = 8 * t + 4 * h + (lane >> 4);
+        uint32_t w[4];
+        for (int j = 0; j < 4; ++j) {
+            const int nu = 16 * g + 4 * (lane >> 4) + j;
             double v = 0.0;
             if (mu < nbf && nu < nbf && mu <= nu) {
                 const double tt =
                     mu == nu ? Ts[(size_t)mu * nbf + mu] : Ts[(size_t)mu * nbf + nu] + Ts[(size_t)nu * nbf + mu];
                 v = spin * cnorm[mu] * cnorm[nu] * tt;
             }
-            w[h] = fft_split((float)v);
+            w[j] = fft_split((float)v);
         }
-        Ap[i] = make_uint2((w[0] & 0xffffu) | (w[1] << 16), (w[0] >> 16) | (w[1] & 0xffff0000u));
+        Ap[i] = make_uint4((w[0] & 0xffffu) | (w[1] << 16), (w[2] & 0xffffu) | (w[3] << 16),
+                           (w[0] >> 16) | (w[1] & 0xffff0000u), (w[2] >> 16) | (w[3] & 0xffff0000u));
     }
 }
 
+// e^{-x} for 0 <= x <= kExpCut in FP64, accurate to ~5e-9 relative (the
+// value is rounded to FP32 afterwards): x = n ln2 + r with |r| <= ln2 / 2
+// (ln2 in two parts, so r is exact to ~1e-16), e^{-r} by its Taylor
+// polynomial of degree 7 (remainder r^8 / 8! < 5.2e-9), scaled by 2^{-n}.
+__device__ __forceinline__ double fft_exp_neg(double x) {
+    const double n = __builtin_rint(x * 1.4426950408889634);
+    const double r = fma(n, 1.9082149292705877e-10, fma(n, 0.6931471803691238, -x));   // -(x - n ln2)
+    double p = 1.0 / 5040.0;
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return __builtin_ldexp(p, -(int)n);
+}
+
 // AO values of one shell at one point before the contracted normalisation
-// (c_mu is folded into the packed weights), FP64, handed to put(row, value)
-// for each Cartesian component (row = bf0 + c).
-template <typename Put>
+// (c_mu is folded into the packed weights), handed to put(row, value) for
+// each Cartesian component (row = bf0 + c).  F is double (the FP32
+// contraction: values rounded once to FP32) or float (the split-BF16
+// contraction, whose operands keep 16 significant bits: the offsets from the
+// centre are formed in FP64 and rounded, the rest runs in FP32 with the
+// hardware 2^x).
+template <typename F, typename Put>
 __device__ __forceinline__ void shell_values(const FftMol& m, int sh, double x, double y, double z, Put put) {
     const PrepShell S = m.shells[sh];
     const double* A = m.xyz + 3 * S.atom;
-    const double dx = x - A[0], dy = y - A[1], dz = z - A[2];
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const F dx = (F)(x - A[0]), dy = (F)(y - A[1]), dz = (F)(z - A[2]);
+    const F r2 = dx * dx + dy * dy + dz * dz;
     // radial sums: sum_k d_k (product of 1D norms for the power pattern) e^{-alpha_k r^2}
-    double ra = 0.0, rb = 0.0;   // l = 2: ra for xx-type, rb for xy-type; l < 2: ra only
+    F ra = 0, rb = 0;   // l = 2: ra for xx-type, rb for xy-type; l < 2: ra only
     for (int k = 0; k < S.nprim; ++k) {
         const int o = S.off + k;
-        const double ar = m.exps[o] * r2;
-        if (ar > kExpCut) continue;
-        const double e = m.coefs[o] * exp(-ar);
-        const double n0 = m.n1d[3 * o], n1 = m.n1d[3 * o + 1], n2 = m.n1d[3 * o + 2];
+        const F ar = (F)m.exps[o] * r2;
+        if (ar > (F)kExpCut) continue;
+        F e;
+        if constexpr (sizeof(F) == 8)
+            e = (F)m.coefs[o] * fft_exp_neg(ar);
+        else
+            e = (F)m.coefs[o] * __builtin_amdgcn_exp2f(ar * -1.44269504f);
+        const F n0 = (F)m.n1d[3 * o], n1 = (F)m.n1d[3 * o + 1], n2 = (F)m.n1d[3 * o + 2];
         if (S.l == 0) {
-            ra += e * n0 * n0 * n0;
+            ra += e * (n0 * n0 * n0);
         } else if (S.l == 1) {
-            ra += e * n1 * n0 * n0;
+            ra += e * (n1 * n0 * n0);
         } else {
-            ra += e * n2 * n0 * n0;
-            rb += e * n1 * n1 * n0;
+            ra += e * (n2 * n0 * n0);
+            rb += e * (n1 * n1 * n0);
         }
     }
     const int b0 = m.bf0[sh];
@@ -167,12 +195,16 @@ __host__ __device__ constexpr size_t fft_lds_bytes(int nbf_pad, int cb) {
 //   FP32  phi(r, c) at float index r NP + col CB + cb, so that a lane reads the
 //         CB values of its column in one ds_read (b32 / b64 / b128) and a
 //         quarter wave reads one contiguous run (no bank conflicts);
-//   BF    split halves, laid out as the B operands of v_mfma_f32_16x16x32_bf16:
-//         entry (t, j, col) for rows 8t + j and 8t + 4 + j (j < 4) holds
-//         hr = hi(8t+j) | hi(8t+4+j) << 16 and lr = lo(..) | lo(..) << 16;
-//         CB = 1: uint2 {hr, lr} at entry (4t + j) 16 + col; CB >= 2: uint4
-//         {hr, lr of column block 2P, hr, lr of 2P + 1} at entry
-//         ((P T8 + t) 4 + j) 16 + col (T8 = nbf_pad / 8).
+//   BF    split halves as the B operands of v_mfma_f32_16x16x32_bf16: the
+//         uint4 entry ((g 4 + kk) CB + cb) 16 + col holds rows r_j = 16 g +
+//         4 kk + j (j < 4) of column c as (hi(r_0) | hi(r_1) << 16, hi(r_2) |
+//         hi(r_3) << 16, lo(r_0) | lo(r_1) << 16, lo(r_2) | lo(r_3) << 16).
+//         A lane (kk, col) takes it as the 8 k-items of one MFMA (no operand
+//         copies), and the same entry holds the rows 16 rb + 4 kk + i that
+//         the lane folds after row block rb.
+// Split-BF16 products per function group and column block: MFMA 1 with
+// A = (W hi, W hi) gives hi*hi + hi*lo over the items, MFMA 2 with
+// A = (W lo, 0) gives lo*hi.
 //
 // Contraction: wave w takes row blocks rb of 16 functions in a snake order
 // (0 1 2 3 3 2 1 0 ...), which evens out the triangle's rows; per row block
@@ -193,7 +225,6 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
     // wave-uniform: the row-block loop and the A-operand addresses stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const long long p0 = (long long)blockIdx.x * NP;
-    const int T8 = nbf_pad / 8;
     float* ph = fft_lds;
     uint32_t* pu = reinterpret_cast<uint32_t*>(fft_lds);
     unsigned short* ps16 = reinterpret_cast<unsigned short*>(fft_lds);
@@ -210,60 +241,54 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
         const int iy = (int)(r1 % n.y), ix = (int)(r1 / n.y);
         const double x = x0.x + ix * h.x, y = x0.y + iy * h.y, z = x0.z + iz * h.z;
         const int col = p & 15, cb = p >> 4;
-        auto put = [&](int r, double v) {
+        auto put = [&](int r, auto v) {
             if constexpr (BF) {
                 const uint32_t w = fft_split((float)v);
-                const int t = r >> 3, j = r & 3, hh = (r >> 2) & 1;
-                int wd;   // dword of hr; lr follows
-                if constexpr (CB == 1)
-                    wd = ((t * 4 + j) * 16 + col) * 2;
-                else
-                    wd = ((((cb >> 1) * T8 + t) * 4 + j) * 16 + col) * 4 + 2 * (cb & 1);
-                ps16[2 * wd + hh] = (unsigned short)(w & 0xffffu);
-                ps16[2 * wd + 2 + hh] = (unsigned short)(w >> 16);
+                const int i = r & 3;
+                // dword of the hi half; the lo half is two dwords on
+                const int wd = ((((r >> 4) * 4 + ((r >> 2) & 3)) * CB + cb) * 16 + col) * 4 + (i >> 1);
+                ps16[2 * wd + (i & 1)] = (unsigned short)(w & 0xffffu);
+                ps16[2 * wd + 4 + (i & 1)] = (unsigned short)(w >> 16);
             } else {
                 ph[r * NP + col * CB + cb] = (float)v;
             }
         };
         for (int sh0 = wave * SPI; sh0 < m.n_shells; sh0 += 4 * SPI) {
             const int sh = sh0 + lane / NP;
-            if (sh < m.n_shells && g < npts) shell_values(m, sh, x, y, z, put);
+            if (sh < m.n_shells && g < npts) shell_values<std::conditional_t<BF, float, double>>(m, sh, x, y, z, put);
         }
     }
 
     const int kk = lane >> 4, col = lane & 15;
-    // the CB AO values of row r at this lane's column (hi + lo in the split form)
-    auto phi_row = [&](int r, double (&v)[CB]) {
+    // the AO values of rows 16 rb + 4 kk + i (i < 4) at this lane's CB columns
+    // (hi + lo in the split form), v[i][cb]
+    auto phi_rows = [&](int rb, double (&v)[4][CB]) {
         if constexpr (BF) {
-            const int t = r >> 3, j = r & 3, sft = 16 * ((r >> 2) & 1);
-            auto val = [&](uint32_t hr, uint32_t lr) {
-                return (double)__uint_as_float((hr >> sft) << 16) + (double)__uint_as_float((lr >> sft) << 16);
-            };
-            if constexpr (CB == 1) {
-                const uint2 e = reinterpret_cast<const uint2*>(pu)[(t * 4 + j) * 16 + col];
-                v[0] = val(e.x, e.y);
-            } else {
 #pragma unroll
-                for (int P = 0; P < CB / 2; ++P) {
-                    const uint4 e = reinterpret_cast<const uint4*>(pu)[((P * T8 + t) * 4 + j) * 16 + col];
-                    v[2 * P] = val(e.x, e.y);
-                    v[2 * P + 1] = val(e.z, e.w);
-                }
+            for (int q = 0; q < CB; ++q) {
+                const uint4 e = reinterpret_cast<const uint4*>(pu)[((rb * 4 + kk) * CB + q) * 16 + col];
+                v[0][q] = (double)__uint_as_float(e.x << 16) + (double)__uint_as_float(e.z << 16);
+                v[1][q] = (double)__uint_as_float(e.x & 0xffff0000u) + (double)__uint_as_float(e.z & 0xffff0000u);
+                v[2][q] = (double)__uint_as_float(e.y << 16) + (double)__uint_as_float(e.w << 16);
+                v[3][q] = (double)__uint_as_float(e.y & 0xffff0000u) + (double)__uint_as_float(e.w & 0xffff0000u);
             }
         } else {
-            const float* q = ph + r * NP + col * CB;
-            if constexpr (CB == 1) {
-                v[0] = q[0];
-            } else if constexpr (CB == 2) {
-                const float2 e = *reinterpret_cast<const float2*>(q);
-                v[0] = e.x;
-                v[1] = e.y;
-            } else {
-                const float4 e = *reinterpret_cast<const float4*>(q);
-                v[0] = e.x;
-                v[1] = e.y;
-                v[2] = e.z;
-                v[3] = e.w;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float* q = ph + (16 * rb + 4 * kk + i) * NP + col * CB;
+                if constexpr (CB == 1) {
+                    v[i][0] = q[0];
+                } else if constexpr (CB == 2) {
+                    const float2 e = *reinterpret_cast<const float2*>(q);
+                    v[i][0] = e.x;
+                    v[i][1] = e.y;
+                } else {
+                    const float4 e = *reinterpret_cast<const float4*>(q);
+                    v[i][0] = e.x;
+                    v[i][1] = e.y;
+                    v[i][2] = e.z;
+                    v[i][3] = e.w;
+                }
             }
         }
     };
@@ -273,22 +298,21 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
     // row block rb for all CB column blocks
     auto kstep = [&](auto a, int k, int par, fft_floatx4 (&c)[NCH]) {
         if constexpr (BF) {
-            const fft_bf16x8 A = __builtin_bit_cast(fft_bf16x8, fft_uintx4{a.y, 0u, a.x, a.x});
-            auto mm = [&](int q, uint32_t hr, uint32_t lr) {
-                const fft_bf16x8 B = __builtin_bit_cast(fft_bf16x8, fft_uintx4{hr, lr, hr, lr});
-                c[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, c[q], 0, 0, 0);
-            };
-            if constexpr (CB == 1) {
-                const uint2 e = reinterpret_cast<const uint2*>(pu)[(k * 4 + kk) * 16 + col];
-                mm(par, e.x, e.y);
-            } else {
+            const fft_bf16x8 A1 = __builtin_bit_cast(fft_bf16x8, fft_uintx4{a.x, a.y, a.x, a.y});
+            const fft_bf16x8 A2 = __builtin_bit_cast(fft_bf16x8, fft_uintx4{a.z, a.w, 0u, 0u});
+            fft_bf16x8 B[CB];
 #pragma unroll
-                for (int P = 0; P < CB / 2; ++P) {
-                    const uint4 e = reinterpret_cast<const uint4*>(pu)[((P * T8 + k) * 4 + kk) * 16 + col];
-                    mm(2 * P, e.x, e.y);
-                    mm(2 * P + 1, e.z, e.w);
-                }
+            for (int q = 0; q < CB; ++q) {
+                const uint4 e = reinterpret_cast<const uint4*>(pu)[((k * 4 + kk) * CB + q) * 16 + col];
+                B[q] = __builtin_bit_cast(fft_bf16x8, fft_uintx4{e.x, e.y, e.z, e.w});
             }
+            // the two products of a column block go to different chains (CB = 1)
+            // or are CB instructions apart
+#pragma unroll
+            for (int q = 0; q < CB; ++q) c[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B[q], c[q], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < CB; ++q)
+                c[CB == 1 ? 1 : q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2, B[q], c[CB == 1 ? 1 : q], 0, 0, 0);
         } else {
             const float* q = ph + (4 * k + kk) * NP + col * CB;
             if constexpr (CB == 1) {
@@ -308,33 +332,34 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
     };
 
     // the k-steps k0 .. k0 + nk - 1 of one row block (nk a multiple of GS, at
-    // least GS).  The A operands of the next 8 k-steps are loaded while the
-    // current 8 run; the row block may end only at a multiple of GS k-steps,
+    // least GS).  The A operands of the next PD k-steps are loaded while the
+    // current PD run; the row block may end only at a multiple of GS k-steps,
     // so the MFMAs between two exits are unconditional and the accumulators
     // keep their registers.  Loads past the row block read the next block or
     // the array's slack and are not used.
-    constexpr int GS = BF ? 2 : 4;
-    auto run_row = [&](const auto* ap, auto (&A0)[8], auto (&A1)[8], int k0, int nk, fft_floatx4 (&c)[NCH]) {
+    constexpr int GS = BF ? 1 : 4;
+    constexpr int PD = BF ? 2 : 8;   // k-steps per register set (prefetch depth)
+    auto run_row = [&](const auto* ap, auto (&A0)[PD], auto (&A1)[PD], int k0, int nk, fft_floatx4 (&c)[NCH]) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) A0[j] = ap[j * 64];
-        for (int t = 0;; t += 16) {
+        for (int j = 0; j < PD; ++j) A0[j] = ap[j * 64];
+        for (int t = 0;; t += 2 * PD) {
             const auto* q = ap + (size_t)t * 64;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) A1[j] = q[(8 + j) * 64];
+            for (int j = 0; j < PD; ++j) A1[j] = q[(PD + j) * 64];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < PD; ++j) {
                 if (j > 0 && j % GS == 0 && t + j >= nk) return;
                 kstep(A0[j], k0 + t + j, j & 1, c);
             }
-            if (t + 8 >= nk) return;
+            if (t + PD >= nk) return;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) A0[j] = q[(16 + j) * 64];
+            for (int j = 0; j < PD; ++j) A0[j] = q[(2 * PD + j) * 64];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (j > 0 && j % GS == 0 && t + 8 + j >= nk) return;
-                kstep(A1[j], k0 + t + 8 + j, j & 1, c);
+            for (int j = 0; j < PD; ++j) {
+                if (j > 0 && j % GS == 0 && t + PD + j >= nk) return;
+                kstep(A1[j], k0 + t + PD + j, j & 1, c);
             }
-            if (t + 16 >= nk) return;
+            if (t + 2 * PD >= nk) return;
         }
     };
 
@@ -350,27 +375,26 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
 #pragma unroll
             for (int q = 0; q < NCH; ++q) c[q] = fft_floatx4{0.f, 0.f, 0.f, 0.f};
             if constexpr (BF) {
-                const int KS8 = KS / 2, k0 = 2 * rb, nk = KS8 - k0;
-                const uint2* ap = reinterpret_cast<const uint2*>(Av) + ((size_t)(s * RB + rb) * KS8 + k0) * 64 + lane;
-                uint2 A0[8], A1[8];
+                const int k0 = rb, nk = RB - k0;
+                const uint4* ap = reinterpret_cast<const uint4*>(Av) + ((size_t)(s * RB + rb) * RB + k0) * 64 + lane;
+                uint4 A0[PD], A1[PD];
                 run_row(ap, A0, A1, k0, nk, c);
             } else {
                 const int k0 = 4 * rb, nk = KS - k0;
                 const float* ap = reinterpret_cast<const float*>(Av) + ((size_t)(s * RB + rb) * KS + k0) * 64 + lane;
-                float A0[8], A1[8];
+                float A0[PD], A1[PD];
                 run_row(ap, A0, A1, k0, nk, c);
             }
             // lane (kk, col) holds rows 16 rb + 4 kk + i of its columns
+            double v[4][CB];
+            phi_rows(rb, v);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                double v[CB];
-                phi_row(16 * rb + 4 * kk + i, v);
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int q = 0; q < CB; ++q) {
                     const float y = CB == 1 ? c[0][i] + c[1][i] : c[q][i];
-                    acc[q] += v[q] * (double)y;
+                    acc[q] += v[i][q] * (double)y;
                 }
-            }
         }
         double* rd = red + (s & 1) * 4 * NP;
 #pragma unroll
@@ -559,11 +583,11 @@ __global__ __launch_bounds__(256) void fft_sum_kernel(const double* __restrict__
 
 hipError_t launch_fft_pack(int precision, const double* T, const double* cnorm, int nbf, int ns, int RB, int KS,
                            double spin, void* Ap, hipStream_t st) {
-    const long long total = (long long)ns * RB * (precision == SCFF_BF16X3 ? KS / 2 : KS) * 64;
+    const long long total = (long long)ns * RB * (precision == SCFF_BF16X3 ? RB : KS) * 64;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 65536);
     if (precision == SCFF_BF16X3)
-        hipLaunchKernelGGL(fft_pack_bf_kernel, dim3(blocks), dim3(256), 0, st, T, cnorm, nbf, ns, RB, KS / 2, spin,
-                           (uint2*)Ap);
+        hipLaunchKernelGGL(fft_pack_bf_kernel, dim3(blocks), dim3(256), 0, st, T, cnorm, nbf, ns, RB, spin,
+                           (uint4*)Ap);
     else
         hipLaunchKernelGGL(fft_pack_kernel, dim3(blocks), dim3(256), 0, st, T, cnorm, nbf, ns, RB, KS, spin,
                            (float*)Ap);

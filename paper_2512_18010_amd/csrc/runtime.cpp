@@ -1082,8 +1082,8 @@ int scff_eval_fft(scff_ctx* c, const scff_fft_grid* g, int precision, float* f, 
     const long long npts = (long long)g->n[0] * g->n[1] * g->n[2];
     const size_t nout = (size_t)npts * ns;
     const long long part_d = (npts + 15) / 16, part_f = (npts + 63) / 64;
-    // the density kernel loads A operands up to 24 k-steps (FP32) or 15 k-groups of 8 bytes (split
-    // BF16) past a row block (unused): slack of 32 x 64 floats covers both
+    // the density kernel loads A operands up to 15 k-steps of 4 bytes (FP32) or 7 function groups
+    // of 16 bytes (split BF16) per lane past a row block (unused): slack of 32 x 64 floats covers both
     if ((rc = dev_reserve(c, c->d_fft_A, ((size_t)ns * RB * KS + 32) * 64 * sizeof(float))) ||
         (rc = dev_reserve(c, c->d_fft_Z, (size_t)nb * npts * sizeof(float2))))
         return rc;
