@@ -218,8 +218,10 @@ struct SphGeom {
 hipError_t launch_sph_geom(const SphGeom* geo, int n_geo, const VRowDev* rows, const int4* trow, const double* tp64,
                            int ns, const double2* theta, const int* uvw_idx, const int* nfirst, int n_nlm, int Lmax,
                            double4* gdat, double2* Yc, double2* W, hipStream_t st);
+// Bq: workspace of nqb radii x ns 25 rows x n_geo double2 (the row operands
+// of one batch of radii).
 hipError_t launch_sph_q(const double4* gdat, const double2* Yc, const double2* W, int n_geo, int ns, int Lmax,
-                        const int* nlm_of, int n_nlm, const double* qs, int n_q, double* J, double2* Q,
+                        const int* nlm_of, const double* qs, int n_q, double* J, double2* Bq, int nqb, double2* Q,
                         hipStream_t st);
 hipError_t launch_sph_couple(const double2* Q, const double* gaunt, int ns, int lmax, int Lmax, int n_q, double2* R,
                              hipStream_t st);

@@ -113,7 +113,7 @@ struct scff_ctx {
     // spherical method: constant tables (for sph_lmax), geometries, per-geometry
     // data, harmonics and W tensor, radii, contraction, R tensor, Legendre stage,
     // angular average
-    DeviceBuffer d_sph_tab, d_sph_geo, d_sph_gdat, d_sph_Yc, d_sph_W, d_sph_q, d_sph_Q, d_sph_R, d_sph_F, d_sph_avg,
+    DeviceBuffer d_sph_tab, d_sph_geo, d_sph_gdat, d_sph_Yc, d_sph_W, d_sph_B, d_sph_q, d_sph_Q, d_sph_R, d_sph_F, d_sph_avg,
         d_sph_J;
     int sph_lmax = -1;
     size_t sph_off[5] = {};   // theta, uvw index, nfirst, nlm_of, gaunt
@@ -437,7 +437,7 @@ void free_all(scff_ctx* c) {
     for (DeviceBuffer* b : {&c->d_mol, &c->d_T, &c->d_vtab, &c->d_part, &c->d_f, &c->d_f2, &c->d_q,
                             &c->d_lq_in, &c->d_lq_S, &c->d_lq_G, &c->d_lq_out, &c->d_fft_A, &c->d_fft_Z,
                             &c->d_fft_part, &c->d_fft_out, &c->d_phi, &c->d_sph_tab, &c->d_sph_geo,
-                            &c->d_sph_gdat, &c->d_sph_Yc, &c->d_sph_W, &c->d_sph_q, &c->d_sph_Q, &c->d_sph_R,
+                            &c->d_sph_gdat, &c->d_sph_Yc, &c->d_sph_W, &c->d_sph_B, &c->d_sph_q, &c->d_sph_Q, &c->d_sph_R,
                             &c->d_sph_F, &c->d_sph_avg, &c->d_sph_J})
         dev_free(c, *b);
     PrepWork& w = c->prep;
@@ -1226,10 +1226,17 @@ int scff_eval_spherical(scff_ctx* c, int lmax, int n_q, const double* q, int n_t
     }
     const int n_geo = (int)geo.size();
     const size_t nrows = (size_t)ns * 25;
+    // row operands of the contraction for a batch of radii: all of them when
+    // they fit 4 GiB (an eighth of a set HBM budget), else as many as fit (a
+    // batch of few radii would leave part of the device idle)
+    const size_t per_q = nrows * (size_t)std::max(n_geo, 1) * sizeof(double2);
+    const size_t bcap = c->budget ? std::min((size_t)4 << 30, c->budget / 8) : (size_t)4 << 30;
+    const int nqb = (int)std::max<size_t>(1, std::min<size_t>((size_t)n_q, bcap / per_q));
     if ((rc = dev_reserve(c, c->d_sph_geo, geo.size() * sizeof(SphGeom))) ||
         (rc = dev_reserve(c, c->d_sph_gdat, geo.size() * sizeof(double4))) ||
         (rc = dev_reserve(c, c->d_sph_Yc, (size_t)n_geo * nL * sizeof(double2))) ||
         (rc = dev_reserve(c, c->d_sph_W, (size_t)n_geo * n_nlm * ns * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_sph_B, (size_t)nqb * per_q)) ||
         (rc = dev_reserve(c, c->d_sph_q, (size_t)n_q * sizeof(double))) ||
         (rc = dev_reserve(c, c->d_sph_Q, (size_t)n_q * nrows * nL * sizeof(double2))) ||
         (rc = dev_reserve(c, c->d_sph_J, (size_t)n_q * (Lmax + 2) * n_geo * sizeof(double))) ||
@@ -1269,8 +1276,8 @@ int scff_eval_spherical(scff_ctx* c, int lmax, int n_q, const double* q, int n_t
         (rc = record(c, EV_SPH1, st)) ||
         (rc = hip_check(launch_sph_q((const double4*)c->d_sph_gdat.p, (const double2*)c->d_sph_Yc.p,
                                      (const double2*)c->d_sph_W.p, n_geo, ns, Lmax, (const int*)(tb + c->sph_off[3]),
-                                     n_nlm, (const double*)c->d_sph_q.p, n_q, (double*)c->d_sph_J.p,
-                                     (double2*)c->d_sph_Q.p, st),
+                                     (const double*)c->d_sph_q.p, n_q, (double*)c->d_sph_J.p,
+                                     (double2*)c->d_sph_B.p, nqb, (double2*)c->d_sph_Q.p, st),
                         "spherical contraction kernel")) ||
         (rc = record(c, EV_SPH2, st)) ||
         (rc = hip_check(launch_sph_couple((const double2*)c->d_sph_Q.p, (const double*)(tb + c->sph_off[4]), ns, lmax,

@@ -7,7 +7,7 @@
 //                      with their packed transition weights,
 //                        W^s_g[n lam mu] = sum_c Tp_s(c) sum_{u+v+w=n} D_c^{uvw} Theta^{uvw}_{lam mu},
 //                      D_c^{uvw} = i^n e^x_u e^y_v e^z_w from the 1D rows of the
-//                      pair precompute; and Y_L^M*(P^_g) for L <= lmax + 4;
+//                      pair precompute; and 4 pi i^L Y_L^M*(P^_g) for L <= lmax + 4;
 //   sph_q_kernel       for each radius q, the contraction over geometries
 //                        Q^s[lam mu][L M](q) = sum_g b^s_g[lam mu](q) a_g[L M](q),
 //                        b = e^{-q^2/4p} sum_n q^n W^s_g[n lam mu],
@@ -48,7 +48,8 @@ __device__ __forceinline__ double2 ipow(int n) {
     }
 }
 
-// Y_L^M*(theta, phi) for L <= Lmax into out[L^2 + L + M] (Condon-Shortley,
+// 4 pi i^L Y_L^M*(theta, phi) for L <= Lmax into out[L^2 + L + M] (the
+// plane-wave factor of the contraction with the harmonic; Condon-Shortley,
 // orthonormal; associated Legendre functions by upward recurrence in L).
 __device__ void ylm_conj_row(int Lmax, double theta, double phi, double2* out) {
     double sn, cs;
@@ -75,10 +76,11 @@ __device__ void ylm_conj_row(int Lmax, double theta, double phi, double2* out) {
                 p1 = cur;
             }
             // conj(Y_l^m) = cur e^{-i m phi};  conj(Y_l^{-m}) = (-1)^m cur e^{+i m phi}
-            out[l * l + l + m] = make_double2(cur * ec, -cur * es);
+            const double2 f = cscale(ipow(l), 4.0 * M_PI);
+            out[l * l + l + m] = cmul(f, make_double2(cur * ec, -cur * es));
             if (m > 0) {
                 const double sg = (m & 1) ? -1.0 : 1.0;
-                out[l * l + l - m] = make_double2(sg * cur * ec, sg * cur * es);
+                out[l * l + l - m] = cmul(f, make_double2(sg * cur * ec, sg * cur * es));
             }
         }
     }
@@ -181,6 +183,39 @@ __global__ void sph_bessel_kernel(const double4* __restrict__ gdat, int n_geo, i
     for (int L = 0; L <= Lmax; ++L) o[(size_t)L * n_geo] *= scale;
 }
 
+// Row operands of the contraction for a batch of nqb radii from iq0 on,
+//   Bq[(k nrows + row) n_geo + g] = e^{-q^2/4p_g} sum_n q^n W^s_g[n lam mu],
+// row = (s, lam mu), q = qs[iq0 + k]; the Gaussian is row Lmax + 1 of the
+// radius's Bessel table.  One thread per (row, geometry): its W values (n =
+// lam, lam + 2, .. <= 4) are loaded once for the batch.
+__global__ __launch_bounds__(256) void sph_b_kernel(const double2* __restrict__ W, const double* __restrict__ J,
+                                                    const int* __restrict__ nlm_of, int n_geo, int ns, int Lmax,
+                                                    const double* __restrict__ qs, int iq0, int nqb,
+                                                    double2* __restrict__ Bq) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_geo) return;
+    const int row = blockIdx.y, nrows = ns * kLam;
+    const int st = row / kLam, lm = row - st * kLam;
+    const int lam = lm < 1 ? 0 : lm < 4 ? 1 : lm < 9 ? 2 : lm < 16 ? 3 : 4;
+    double2 w[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    int cnt = 0;
+    for (int n = lam; n <= kSphMaxN; n += 2) w[cnt++] = W[((size_t)nlm_of[n * kLam + lm] * ns + st) * n_geo + g];
+    for (int k = 0; k < nqb; ++k) {
+        const int iq = iq0 + k;
+        const double q = qs[iq];
+        const double ga = J[((size_t)iq * (Lmax + 2) + Lmax + 1) * n_geo + g];
+        double p = 1.0;
+        for (int n = 0; n < lam; ++n) p *= q;
+        double br = 0.0, bi = 0.0;
+        for (int m = 0; m < cnt; ++m) {
+            br = fma(p, w[m].x, br);
+            bi = fma(p, w[m].y, bi);
+            p *= q * q;
+        }
+        Bq[((size_t)k * nrows + row) * n_geo + g] = make_double2(br * ga, bi * ga);
+    }
+}
+
 // Tile: 64 rows (state, lam mu) x 64 columns (L M) per workgroup, all
 // geometries in chunks of 16, on the FP64 matrix cores
 // (v_mfma_f64_16x16x4_f64: A = 16 rows x 4 geometries, B = 4 geometries x
@@ -188,30 +223,37 @@ __global__ void sph_bessel_kernel(const double4* __restrict__ gdat, int n_geo, i
 // results D[4 i + l / 16][l % 16], i = 0..3, as measured on the device).  Wave w owns the 16 rows 16 w .. 16 w + 15
 // and all 4 column blocks; the complex product takes four real products
 // (re re - im im, re im + im re).  The operands are staged in LDS as real and
-// imaginary planes.
-constexpr int kQRows = 64, kQCols = 64, kQK = 16, kQLspan = 14;
+// imaginary planes: thread t copies the row operand of row t / 4 at the four
+// geometries 4 (t % 4) .. + 3 (formed per batch of radii by sph_b_kernel) and
+// forms the column operand of column t % 64 at geometries t / 64 + 4 j
+// (a = j_L Yt, Yt = 4 pi i^L Y* stored by the geometry kernel); every global
+// load of a chunk is issued before its arithmetic.
+constexpr int kQRows = 64, kQCols = 64, kQK = 16;
 constexpr int kQCB = kQCols / 16;   // column blocks per wave
 typedef double sph_double4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J, const double2* __restrict__ Yc,
-                                                    const double2* __restrict__ W, int n_geo, int ns, int Lmax,
-                                                    const int* __restrict__ nlm_of, int n_nlm,
-                                                    const double* __restrict__ qs, double2* __restrict__ Q) {
+__global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J, const double2* __restrict__ Yt,
+                                                    const double2* __restrict__ Bq, int n_geo, int ns, int Lmax,
+                                                    int iq0, double2* __restrict__ Q) {
     __shared__ double Br[kQRows][kQK + 1], Bi[kQRows][kQK + 1];
     __shared__ double Ar[kQK][kQCols + 1], Ai[kQK][kQCols + 1];
-    __shared__ double jt[kQLspan + 1][kQK];
-    __shared__ int colL[kQCols];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nrows = ns * kLam, ncols = (Lmax + 1) * (Lmax + 1);
     const int r0 = blockIdx.y * kQRows, c0 = blockIdx.x * kQCols;
-    const int iq = blockIdx.z;
-    const double q = qs[iq];
-    const int cl = min(c0 + kQCols, ncols) - 1;
-    const int Lmin = (int)sqrt((double)c0 + 0.5), Lhi = (int)sqrt((double)cl + 0.5);
-    const int span = Lhi - Lmin + 1;
+    const int iq = iq0 + blockIdx.z;
     const double* Jq = J + (size_t)iq * (Lmax + 2) * n_geo;
-    for (int cc = tid; cc < kQCols; cc += 256) colL[cc] = (int)sqrt((double)(c0 + cc) + 0.5);
+
+    // row operand: row rb_ of the tile, geometries gq_ .. gq_ + 3 of a chunk
+    const int rb_ = tid >> 2, gq_ = 4 * (tid & 3);
+    const bool row_ok = r0 + rb_ < nrows;
+    const double2* Brow = Bq + ((size_t)blockIdx.z * nrows + (row_ok ? r0 + rb_ : 0)) * n_geo;
+    // column operand: column ca_ of the tile, geometries ga_ + 4 j of a chunk
+    const int ca_ = tid & 63, ga_ = tid >> 6;
+    const int colA = c0 + ca_;
+    const bool colA_ok = colA < ncols;
+    const double* JL = Jq + (size_t)(colA_ok ? (int)sqrt((double)colA + 0.5) : 0) * n_geo;
+
     sph_double4 accR[kQCB], accI[kQCB];
 #pragma unroll
     for (int cb = 0; cb < kQCB; ++cb) {
@@ -220,51 +262,29 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
     }
     const int lr = lane & 15, lk = lane >> 4;
     for (int g0 = 0; g0 < n_geo; g0 += kQK) {
-        // Bessel values of this column block's L range and the Gaussians (row kQLspan)
-        for (int e = tid; e < (span + 1) * kQK; e += 256) {
-            const int li = e / kQK, gg = e - li * kQK;
-            const int g = g0 + gg;
-            const int L = li < span ? Lmin + li : Lmax + 1;
-            jt[li < span ? li : kQLspan][gg] = g < n_geo ? Jq[(size_t)L * n_geo + g] : 0.0;
+        // loads of the chunk: the row operand's run of 4 geometries, then Yt
+        // and j_L at the column's four geometries
+        double2 b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int g = g0 + gq_ + j;
+            b[j] = (row_ok && g < n_geo) ? Brow[g] : make_double2(0.0, 0.0);
         }
-        __syncthreads();
-        // B: rows (state, lam mu) x geometries
-        for (int e = tid; e < kQRows * kQK; e += 256) {
-            const int row = e / kQK, gg = e - row * kQK;
-            const int r = r0 + row, g = g0 + gg;
-            double br = 0.0, bi = 0.0;
-            if (r < nrows && g < n_geo) {
-                const int s = r / kLam, lm = r - s * kLam;
-                const int lam = lm < 1 ? 0 : lm < 4 ? 1 : lm < 9 ? 2 : lm < 16 ? 3 : 4;
-                double qn = 1.0;
-                for (int n = 0; n <= kSphMaxN; ++n) {
-                    if (n >= lam && ((n - lam) & 1) == 0) {
-                        const int b_i = nlm_of[n * kLam + lm];
-                        const double2 w = W[((size_t)b_i * ns + s) * n_geo + g];
-                        br += qn * w.x;
-                        bi += qn * w.y;
-                    }
-                    qn *= q;
-                }
-                const double ga = jt[kQLspan][gg];
-                br *= ga;
-                bi *= ga;
-            }
-            Br[row][gg] = br;
-            Bi[row][gg] = bi;
+        double2 y[4];
+        double jl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int g = g0 + ga_ + 4 * j;
+            const bool ok = colA_ok && g < n_geo;
+            y[j] = ok ? Yt[(size_t)g * ncols + colA] : make_double2(0.0, 0.0);
+            jl[j] = ok ? JL[g] : 0.0;
         }
-        // A: geometries x (L M)
-        for (int e = tid; e < kQK * kQCols; e += 256) {
-            const int gg = e / kQCols, cc = e - gg * kQCols;
-            const int col = c0 + cc, g = g0 + gg;
-            double2 a = make_double2(0.0, 0.0);
-            if (col < ncols && g < n_geo) {
-                const int L = colL[cc];
-                const double jl = jt[L - Lmin][gg] * 4.0 * M_PI;
-                a = cmul(cscale(ipow(L), jl), Yc[(size_t)g * ncols + col]);
-            }
-            Ar[gg][cc] = a.x;
-            Ai[gg][cc] = a.y;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Br[rb_][gq_ + j] = b[j].x;
+            Bi[rb_][gq_ + j] = b[j].y;
+            Ar[ga_ + 4 * j][ca_] = jl[j] * y[j].x;
+            Ai[ga_ + 4 * j][ca_] = jl[j] * y[j].y;
         }
         __syncthreads();
 #pragma unroll
@@ -411,17 +431,25 @@ hipError_t launch_sph_geom(const SphGeom* geo, int n_geo, const VRowDev* rows, c
 }
 
 hipError_t launch_sph_q(const double4* gdat, const double2* Yc, const double2* W, int n_geo, int ns, int Lmax,
-                        const int* nlm_of, int n_nlm, const double* qs, int n_q, double* J, double2* Q, hipStream_t st) {
+                        const int* nlm_of, const double* qs, int n_q, double* J, double2* Bq, int nqb, double2* Q,
+                        hipStream_t st) {
+    if (nqb < 1) return hipErrorInvalidValue;
     const long long nb = (long long)n_q * n_geo;
     hipLaunchKernelGGL(sph_bessel_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, gdat, n_geo, Lmax, qs,
                        n_q, J);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nrows = ns * kLam, ncols = (Lmax + 1) * (Lmax + 1);
-    // kQCols consecutive (L M) cover at most kQLspan values of L
-    dim3 grid((ncols + kQCols - 1) / kQCols, (nrows + kQRows - 1) / kQRows, n_q);
-    hipLaunchKernelGGL(sph_q_kernel, grid, dim3(256), 0, st, J, Yc, W, n_geo, ns, Lmax, nlm_of, n_nlm, qs, Q);
-    return hipGetLastError();
+    if (nrows > 65535) return hipErrorInvalidValue;
+    for (int iq0 = 0; iq0 < n_q; iq0 += nqb) {
+        const int nk = std::min(nqb, n_q - iq0);
+        hipLaunchKernelGGL(sph_b_kernel, dim3((n_geo + 255) / 256, nrows), dim3(256), 0, st, W, J, nlm_of, n_geo, ns,
+                           Lmax, qs, iq0, nk, Bq);
+        dim3 grid((ncols + kQCols - 1) / kQCols, (nrows + kQRows - 1) / kQRows, nk);
+        hipLaunchKernelGGL(sph_q_kernel, grid, dim3(256), 0, st, J, Yc, Bq, n_geo, ns, Lmax, iq0, Q);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_sph_couple(const double2* Q, const double* gaunt, int ns, int lmax, int Lmax, int n_q, double2* R,
