@@ -226,8 +226,8 @@ __global__ __launch_bounds__(256) void sph_b_kernel(const double2* __restrict__ 
 // imaginary planes: thread t copies the row operand of row t / 4 at the four
 // geometries 4 (t % 4) .. + 3 (formed per batch of radii by sph_b_kernel) and
 // forms the column operand of column t % 64 at geometries t / 64 + 4 j
-// (a = j_L Yt, Yt = 4 pi i^L Y* stored by the geometry kernel); every global
-// load of a chunk is issued before its arithmetic.
+// (a = j_L Yt, Yt = 4 pi i^L Y* stored by the geometry kernel); the global
+// loads of the next chunk are in flight while the current one is multiplied.
 constexpr int kQRows = 64, kQCols = 64, kQK = 16;
 constexpr int kQCB = kQCols / 16;   // column blocks per wave
 typedef double sph_double4 __attribute__((ext_vector_type(4)));
@@ -261,17 +261,17 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
         accI[cb] = (sph_double4){0.0, 0.0, 0.0, 0.0};
     }
     const int lr = lane & 15, lk = lane >> 4;
-    for (int g0 = 0; g0 < n_geo; g0 += kQK) {
-        // loads of the chunk: the row operand's run of 4 geometries, then Yt
-        // and j_L at the column's four geometries
-        double2 b[4];
+    // loads of a chunk: the row operand's run of 4 geometries, then Yt and
+    // j_L at the column's four geometries; chunk g0 + kQK is loaded while the
+    // matrix cores work on chunk g0
+    double2 b[4], y[4];
+    double jl[4];
+    auto load_chunk = [&](int g0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int g = g0 + gq_ + j;
             b[j] = (row_ok && g < n_geo) ? Brow[g] : make_double2(0.0, 0.0);
         }
-        double2 y[4];
-        double jl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int g = g0 + ga_ + 4 * j;
@@ -279,6 +279,9 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
             y[j] = ok ? Yt[(size_t)g * ncols + colA] : make_double2(0.0, 0.0);
             jl[j] = ok ? JL[g] : 0.0;
         }
+    };
+    load_chunk(0);
+    for (int g0 = 0; g0 < n_geo; g0 += kQK) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             Br[rb_][gq_ + j] = b[j].x;
@@ -287,6 +290,7 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
             Ai[ga_ + 4 * j][ca_] = jl[j] * y[j].y;
         }
         __syncthreads();
+        if (g0 + kQK < n_geo) load_chunk(g0 + kQK);
 #pragma unroll
         for (int ks = 0; ks < kQK / 4; ++ks) {
             const double ar = Br[16 * wave + lr][4 * ks + lk], ai = Bi[16 * wave + lr][4 * ks + lk];
