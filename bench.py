@@ -600,8 +600,8 @@ def main():
     # ---- FFT method (Sec. 3, Sec. 5.2): config-1 molecule and transitions
     fft_leg = None
     if not args.no_fft:
-        fft_leg = fft_benchmark(ctx, stream, args.fft_n, max(5, args.steps // 2), 2, log)
-        fft_leg["other_precision"] = fft_benchmark(ctx, stream, args.fft_n, max(5, args.steps // 2), 2, log,
+        fft_leg = fft_benchmark(ctx, stream, args.fft_n, max(10, args.steps // 2), 2, log)
+        fft_leg["other_precision"] = fft_benchmark(ctx, stream, args.fft_n, max(10, args.steps // 2), 2, log,
                                                    precision="bf16x3")
 
     # ---- spherical method (Sec. 4, Sec. 5.4): config-1 molecule and transitions

@@ -260,17 +260,19 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
     }
 
     const int kk = lane >> 4, col = lane & 15;
-    // the AO values of rows 16 rb + 4 kk + i (i < 4) at this lane's CB columns
-    // (hi + lo in the split form), v[i][cb]
-    auto phi_rows = [&](int rb, double (&v)[4][CB]) {
+    // the AO values of rows 16 rb + 4 kk + i (i < 4) at this lane's CB columns,
+    // v[i][cb] (in the split form hi + lo, exact in FP32: the halves span at
+    // most 16 significant bits)
+    using FV = std::conditional_t<BF, float, double>;
+    auto phi_rows = [&](int rb, FV (&v)[4][CB]) {
         if constexpr (BF) {
 #pragma unroll
             for (int q = 0; q < CB; ++q) {
                 const uint4 e = reinterpret_cast<const uint4*>(pu)[((rb * 4 + kk) * CB + q) * 16 + col];
-                v[0][q] = (double)__uint_as_float(e.x << 16) + (double)__uint_as_float(e.z << 16);
-                v[1][q] = (double)__uint_as_float(e.x & 0xffff0000u) + (double)__uint_as_float(e.z & 0xffff0000u);
-                v[2][q] = (double)__uint_as_float(e.y << 16) + (double)__uint_as_float(e.w << 16);
-                v[3][q] = (double)__uint_as_float(e.y & 0xffff0000u) + (double)__uint_as_float(e.w & 0xffff0000u);
+                v[0][q] = __uint_as_float(e.x << 16) + __uint_as_float(e.z << 16);
+                v[1][q] = __uint_as_float(e.x & 0xffff0000u) + __uint_as_float(e.z & 0xffff0000u);
+                v[2][q] = __uint_as_float(e.y << 16) + __uint_as_float(e.w << 16);
+                v[3][q] = __uint_as_float(e.y & 0xffff0000u) + __uint_as_float(e.w & 0xffff0000u);
             }
         } else {
 #pragma unroll
@@ -364,9 +366,11 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
     };
 
     for (int s = 0; s < ns; ++s) {
-        double acc[CB];
+        // the fold over a wave's row blocks: FP64 for the FP32 contraction, FP32
+        // for split-BF16 (whose products carry 16 significant bits)
+        FV acc[CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+        for (int q = 0; q < CB; ++q) acc[q] = 0;
         for (int i4 = 0; i4 < RB; i4 += 4) {
             // snake order: blocks i4 .. i4+3 go to waves 0..3, then 3..0
             const int rb = i4 + (((i4 >> 2) & 1) ? 3 - wave : wave);
@@ -386,22 +390,23 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
                 run_row(ap, A0, A1, k0, nk, c);
             }
             // lane (kk, col) holds rows 16 rb + 4 kk + i of its columns
-            double v[4][CB];
+            FV v[4][CB];
             phi_rows(rb, v);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int q = 0; q < CB; ++q) {
                     const float y = CB == 1 ? c[0][i] + c[1][i] : c[q][i];
-                    acc[q] += v[i][q] * (double)y;
+                    acc[q] += v[i][q] * (FV)y;
                 }
         }
         double* rd = red + (s & 1) * 4 * NP;
 #pragma unroll
         for (int q = 0; q < CB; ++q) {
-            acc[q] += __shfl_xor(acc[q], 16);
-            acc[q] += __shfl_xor(acc[q], 32);
-            if (lane < 16) rd[wave * NP + q * 16 + lane] = acc[q];
+            double a = acc[q];
+            a += __shfl_xor(a, 16);
+            a += __shfl_xor(a, 32);
+            if (lane < 16) rd[wave * NP + q * 16 + lane] = a;
         }
         __syncthreads();
         if (wave == 0) {
