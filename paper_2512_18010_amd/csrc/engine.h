@@ -175,7 +175,7 @@ struct FftMol {
     int n_shells;
 };
 // LDS a density workgroup may hold (its AO block grows with the basis: up to
-// 1232 functions).
+// 1232 functions; 64-point tiles up to 240 functions, 32-point tiles up to 496).
 constexpr size_t kFftLdsBytes = (size_t)78 << 10;
 // Column blocks of 16 points per density workgroup for nbf_pad basis rows
 // (4, 2 or 1), 0 if the AO block does not fit lds_limit bytes of LDS.

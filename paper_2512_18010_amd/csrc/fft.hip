@@ -1,18 +1,20 @@
 // The FFT method (paper Sec. 3 and Sec. 5.2) on the device:
 //
-//   1. fft_pack_kernel      transition weights as MFMA A operands:
-//                           s_f c_mu c_nu (T_{mu nu} + T_{nu mu}) per unordered
-//                           component pair (T_{mu mu} on the diagonal);
+//   1. fft_pack_kernel /    transition weights as MFMA A operands:
+//      fft_pack_bf_kernel   s_f c_mu c_nu (T_{mu nu} + T_{nu mu}) per unordered
+//                           component pair (T_{mu mu} on the diagonal), FP32
+//                           or split into BF16 halves;
 //   2. fft_density_kernel   the transition density (eq. PhiTDM, AO form)
 //                             Phi_s(r) = sum_mu phi_mu(r) sum_{nu >= mu} Tp_s(mu,nu) phi_nu(r)
-//                           on a tile of real-space points: the AO values of
-//                           the tile are formed in LDS (FP64, rounded once),
-//                           Y_s(mu, r) = sum_nu Tp_s(mu,nu) phi_nu(r) runs on
-//                           the matrix cores (v_mfma_f32_16x16x4_f32; rows
-//                           mu of one state, k = nu, columns = points), and
-//                           sum_mu phi_mu Y_s(mu) is folded into FP64 per
-//                           16 rows.  Two states share one complex array
-//                           (Phi_2b + i Phi_2b+1), so each FFT carries two.
+//                           on a tile of up to 64 real-space points: the AO
+//                           values of the tile are formed in LDS (FP64 and
+//                           rounded once, or FP32 and split for the split-BF16
+//                           contraction), Y_s(mu, r) = sum_nu Tp_s(mu,nu) phi_nu(r)
+//                           runs on the matrix cores (rows mu of one state,
+//                           k = nu, columns = points), and sum_mu phi_mu Y_s(mu)
+//                           is folded per 16 rows.  Two states share one
+//                           complex array (Phi_2b + i Phi_2b+1), so each FFT
+//                           carries two.
 //   3. fft_lines_kernel     radix-2 transforms of all lines of one axis of the
 //                           complex arrays, a line group staged in LDS (eq.
 //                           Falbega as three 1D passes);
