@@ -87,10 +87,11 @@ def test_fft_odd_state_count_and_spin(eng, oracle_mod):
     compare("cfg0 3 states", oracle_mod, W.mol, T, n, xmin, L, f, f2, phi, ps, spin=np.sqrt(2.0))
 
 
-@pytest.mark.parametrize("n_heavy,n_states", [(30, 3), (36, 2)])
+@pytest.mark.parametrize("n_heavy,n_states", [(20, 2), (30, 3), (36, 2)])
 def test_fft_large_basis_tiles(eng, oracle_mod, n_heavy, n_states):
-    """Bases of 570 and 685 functions (36 and 43 row blocks of 16, so each
-    of the four waves of a tile takes a different number of them)."""
+    """Bases of 380, 570 and 685 functions: 32-point tiles for the first,
+    16-point tiles for the others (24, 36 and 43 row blocks of 16, so the four
+    waves of a tile take different numbers of them)."""
     rng = np.random.Generator(np.random.PCG64(950 + n_heavy))
     mol = wl.make_molecule(rng, n_heavy, int(round(0.8 * n_heavy)), layout="box",
                            box_A=12.0 * (n_heavy / 30.0) ** (1 / 3))
@@ -101,10 +102,11 @@ def test_fft_large_basis_tiles(eng, oracle_mod, n_heavy, n_states):
     compare(f"{mol.nbf} bf", oracle_mod, mol, T, n, xmin, L, f, f2, phi, ps)
 
 
-@pytest.mark.parametrize("n_heavy,n_states", [(4, 1), (36, 3)])
+@pytest.mark.parametrize("n_heavy,n_states", [(4, 1), (20, 2), (36, 3)])
 def test_fft_bf16x3_matches_oracle(eng, oracle_mod, n_heavy, n_states):
-    """Split-BF16 density contraction: config-0-sized and 685-function bases
-    against the oracle, element by element, at the split-BF16 tolerance."""
+    """Split-BF16 density contraction: config-0-sized, 380- and 685-function
+    bases (64-, 32- and 16-point tiles) against the oracle, element by
+    element, at the split-BF16 tolerance."""
     rng = np.random.Generator(np.random.PCG64(970 + n_heavy))
     if n_heavy == 4:
         W = wl.make_config(0)
