@@ -263,8 +263,8 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
 
     const int kk = lane >> 4, col = lane & 15;
     // the AO values of rows 16 rb + 4 kk + i (i < 4) at this lane's CB columns,
-    // v[i][cb] (in the split form hi + lo, exact in FP32: the halves span at
-    // most 16 significant bits)
+    // v[i][cb] (in the split form hi + lo, summed in FP32: within 2^-24 of the
+    // split value, far below the split's own 2^-16)
     using FV = std::conditional_t<BF, float, double>;
     auto phi_rows = [&](int rb, FV (&v)[4][CB]) {
         if constexpr (BF) {
