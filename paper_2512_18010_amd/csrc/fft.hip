@@ -336,34 +336,46 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
     };
 
     // the k-steps k0 .. k0 + nk - 1 of one row block (nk a multiple of GS, at
-    // least GS).  The A operands of the next PD k-steps are loaded while the
-    // current PD run; the row block may end only at a multiple of GS k-steps,
-    // so the MFMAs between two exits are unconditional and the accumulators
-    // keep their registers.  Loads past the row block read the next block or
-    // the array's slack and are not used.
+    // least GS).  The main loop runs whole blocks of 2 PD k-steps with no exit
+    // inside, the A operands of the next PD k-steps loaded while the current
+    // PD run (an exit between a load and its use lets the compiler sink the
+    // load to the use, which then waits for it); the last 0 .. 2 PD - GS
+    // k-steps run in a guarded tail.  Loads past the row block read the next
+    // block or the array's slack and are not used.
     constexpr int GS = BF ? 1 : 4;
-    constexpr int PD = BF ? 2 : 8;   // k-steps per register set (prefetch depth)
+    constexpr int PD = BF ? 4 : 8;   // k-steps per register set (prefetch depth)
     auto run_row = [&](const auto* ap, auto (&A0)[PD], auto (&A1)[PD], int k0, int nk, fft_floatx4 (&c)[NCH]) {
 #pragma unroll
         for (int j = 0; j < PD; ++j) A0[j] = ap[j * 64];
-        for (int t = 0;; t += 2 * PD) {
+        int t = 0;
+        for (; t + 2 * PD <= nk; t += 2 * PD) {
             const auto* q = ap + (size_t)t * 64;
 #pragma unroll
             for (int j = 0; j < PD; ++j) A1[j] = q[(PD + j) * 64];
 #pragma unroll
-            for (int j = 0; j < PD; ++j) {
-                if (j > 0 && j % GS == 0 && t + j >= nk) return;
-                kstep(A0[j], k0 + t + j, j & 1, c);
-            }
-            if (t + PD >= nk) return;
+            for (int j = 0; j < PD; ++j) kstep(A0[j], k0 + t + j, j & 1, c);
 #pragma unroll
             for (int j = 0; j < PD; ++j) A0[j] = q[(2 * PD + j) * 64];
 #pragma unroll
-            for (int j = 0; j < PD; ++j) {
-                if (j > 0 && j % GS == 0 && t + PD + j >= nk) return;
-                kstep(A1[j], k0 + t + PD + j, j & 1, c);
+            for (int j = 0; j < PD; ++j) kstep(A1[j], k0 + t + PD + j, j & 1, c);
+        }
+        const int r = nk - t;   // wave-uniform
+        if (r > 0) {
+            const auto* q = ap + (size_t)t * 64;
+#pragma unroll
+            for (int j = 0; j < PD; ++j) A1[j] = q[(PD + j) * 64];
+#pragma unroll
+            for (int j = 0; j < PD; j += GS) {
+                if (j >= r) return;
+#pragma unroll
+                for (int i = 0; i < GS; ++i) kstep(A0[j + i], k0 + t + j + i, (j + i) & 1, c);
             }
-            if (t + 2 * PD >= nk) return;
+#pragma unroll
+            for (int j = 0; j < PD; j += GS) {
+                if (PD + j >= r) return;
+#pragma unroll
+                for (int i = 0; i < GS; ++i) kstep(A1[j + i], k0 + t + PD + j + i, (j + i) & 1, c);
+            }
         }
     };
 
