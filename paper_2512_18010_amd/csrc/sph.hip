@@ -250,9 +250,9 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
     const double2* Brow = Bq + ((size_t)blockIdx.z * nrows + (row_ok ? r0 + rb_ : 0)) * n_geo;
     // column operand: column ca_ of the tile, geometries ga_ + 4 j of a chunk
     const int ca_ = tid & 63, ga_ = tid >> 6;
-    const int colA = c0 + ca_;
-    const bool colA_ok = colA < ncols;
-    const double* JL = Jq + (size_t)(colA_ok ? (int)sqrt((double)colA + 0.5) : 0) * n_geo;
+    const bool colA_ok = c0 + ca_ < ncols;
+    const int colA = colA_ok ? c0 + ca_ : 0;
+    const double* JL = Jq + (size_t)(int)sqrt((double)colA + 0.5) * n_geo;
 
     sph_double4 accR[kQCB], accI[kQCB];
 #pragma unroll
@@ -263,31 +263,32 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
     const int lr = lane & 15, lk = lane >> 4;
     // loads of a chunk: the row operand's run of 4 geometries, then Yt and
     // j_L at the column's four geometries; chunk g0 + kQK is loaded while the
-    // matrix cores work on chunk g0
+    // matrix cores work on chunk g0.  The loads are unconditional, from
+    // addresses clamped into the arrays, and the entries outside the problem
+    // are zeroed when they are written to LDS (a conditional load joined with
+    // a zero makes the compiler wait for it at once)
     double2 b[4], y[4];
     double jl[4];
     auto load_chunk = [&](int g0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int g = g0 + gq_ + j;
-            b[j] = (row_ok && g < n_geo) ? Brow[g] : make_double2(0.0, 0.0);
-        }
+        for (int j = 0; j < 4; ++j) b[j] = Brow[min(g0 + gq_ + j, n_geo - 1)];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int g = g0 + ga_ + 4 * j;
-            const bool ok = colA_ok && g < n_geo;
-            y[j] = ok ? Yt[(size_t)g * ncols + colA] : make_double2(0.0, 0.0);
-            jl[j] = ok ? JL[g] : 0.0;
+            const int g = min(g0 + ga_ + 4 * j, n_geo - 1);
+            y[j] = Yt[(size_t)g * ncols + colA];
+            jl[j] = JL[g];
         }
     };
     load_chunk(0);
     for (int g0 = 0; g0 < n_geo; g0 += kQK) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            Br[rb_][gq_ + j] = b[j].x;
-            Bi[rb_][gq_ + j] = b[j].y;
-            Ar[ga_ + 4 * j][ca_] = jl[j] * y[j].x;
-            Ai[ga_ + 4 * j][ca_] = jl[j] * y[j].y;
+            const bool bok = row_ok && g0 + gq_ + j < n_geo;
+            const bool aok = colA_ok && g0 + ga_ + 4 * j < n_geo;
+            Br[rb_][gq_ + j] = bok ? b[j].x : 0.0;
+            Bi[rb_][gq_ + j] = bok ? b[j].y : 0.0;
+            Ar[ga_ + 4 * j][ca_] = aok ? jl[j] * y[j].x : 0.0;
+            Ai[ga_ + 4 * j][ca_] = aok ? jl[j] * y[j].y : 0.0;
         }
         __syncthreads();
         if (g0 + kQK < n_geo) load_chunk(g0 + kQK);
