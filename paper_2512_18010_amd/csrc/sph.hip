@@ -197,9 +197,13 @@ __global__ __launch_bounds__(256) void sph_b_kernel(const double2* __restrict__ 
     const int row = blockIdx.y, nrows = ns * kLam;
     const int st = row / kLam, lm = row - st * kLam;
     const int lam = lm < 1 ? 0 : lm < 4 ? 1 : lm < 9 ? 2 : lm < 16 ? 3 : 4;
-    double2 w[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-    int cnt = 0;
-    for (int n = lam; n <= kSphMaxN; n += 2) w[cnt++] = W[((size_t)nlm_of[n * kLam + lm] * ns + st) * n_geo + g];
+    // slots m = 0..2 hold n = lam + 2 m (those above kSphMaxN are zero)
+    double2 w[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int n = lam + 2 * m;
+        w[m] = n <= kSphMaxN ? W[((size_t)nlm_of[n * kLam + lm] * ns + st) * n_geo + g] : make_double2(0.0, 0.0);
+    }
     for (int k = 0; k < nqb; ++k) {
         const int iq = iq0 + k;
         const double q = qs[iq];
@@ -207,7 +211,8 @@ __global__ __launch_bounds__(256) void sph_b_kernel(const double2* __restrict__ 
         double p = 1.0;
         for (int n = 0; n < lam; ++n) p *= q;
         double br = 0.0, bi = 0.0;
-        for (int m = 0; m < cnt; ++m) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
             br = fma(p, w[m].x, br);
             bi = fma(p, w[m].y, bi);
             p *= q * q;
