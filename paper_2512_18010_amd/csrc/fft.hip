@@ -210,11 +210,11 @@ __host__ __device__ constexpr size_t fft_lds_bytes(int nbf_pad, int cb) {
 //
 // Contraction: wave w takes row blocks rb of 16 functions in a snake order
 // (0 1 2 3 3 2 1 0 ...), which evens out the triangle's rows; per row block
-// the k-steps from the diagonal block on, with the A operands of the next 8
-// k-steps loaded while the current 8 run and each A operand used by CB
-// MFMAs.  The 16-row block is folded into FP64 with its AO values, the four
-// waves' partial densities are summed through LDS (double-buffered by state
-// parity: one barrier per state) and wave 0 writes the tile.
+// the k-steps from the diagonal block on, with the A operands of the next
+// k-steps loaded while the current ones run and each A operand used by CB
+// MFMAs.  The 16-row block is folded with its AO values, the four waves'
+// partial densities of a group of states are summed through LDS and wave 0
+// writes the tile.
 template <bool BF, int CB>
 __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* __restrict__ Av, int nbf_pad, int ns,
                                                           int RB, int KS, int3 n, double3 x0, double3 h,
@@ -379,67 +379,90 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
         }
     };
 
-    for (int s = 0; s < ns; ++s) {
-        // the fold over a wave's row blocks: FP64 for the FP32 contraction, FP32
-        // for split-BF16 (whose products carry 16 significant bits)
-        FV acc[CB];
+    // States in groups of SG: the AO values of a row block are formed once per
+    // group, and the four waves' partial densities of the group meet in one
+    // LDS slot (two barriers per group).  The fold over a wave's row blocks is
+    // FP64 for the FP32 contraction and FP32 for split-BF16 (whose products
+    // carry 16 significant bits); the slot holds SG x 4 x NP of them, within
+    // the 64 NP bytes set aside.
+    constexpr int SG = 2;
+    FV* rd = reinterpret_cast<FV*>(red);
+    for (int s0 = 0; s0 < ns; s0 += SG) {
+        FV acc[SG][CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) acc[q] = 0;
+        for (int si = 0; si < SG; ++si)
+#pragma unroll
+            for (int q = 0; q < CB; ++q) acc[si][q] = 0;
         for (int i4 = 0; i4 < RB; i4 += 4) {
             // snake order: blocks i4 .. i4+3 go to waves 0..3, then 3..0
             const int rb = i4 + (((i4 >> 2) & 1) ? 3 - wave : wave);
             if (rb >= RB) continue;
-            fft_floatx4 c[NCH];
-#pragma unroll
-            for (int q = 0; q < NCH; ++q) c[q] = fft_floatx4{0.f, 0.f, 0.f, 0.f};
-            if constexpr (BF) {
-                const int k0 = rb, nk = RB - k0;
-                const uint4* ap = reinterpret_cast<const uint4*>(Av) + ((size_t)(s * RB + rb) * RB + k0) * 64 + lane;
-                uint4 A0[PD], A1[PD];
-                run_row(ap, A0, A1, k0, nk, c);
-            } else {
-                const int k0 = 4 * rb, nk = KS - k0;
-                const float* ap = reinterpret_cast<const float*>(Av) + ((size_t)(s * RB + rb) * KS + k0) * 64 + lane;
-                float A0[PD], A1[PD];
-                run_row(ap, A0, A1, k0, nk, c);
-            }
             // lane (kk, col) holds rows 16 rb + 4 kk + i of its columns
             FV v[4][CB];
             phi_rows(rb, v);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int si = 0; si < SG; ++si) {
+                const int s = s0 + si;
+                if (s >= ns) break;
+                fft_floatx4 c[NCH];
 #pragma unroll
-                for (int q = 0; q < CB; ++q) {
-                    const float y = CB == 1 ? c[0][i] + c[1][i] : c[q][i];
-                    acc[q] += v[i][q] * (FV)y;
+                for (int q = 0; q < NCH; ++q) c[q] = fft_floatx4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (BF) {
+                    const int k0 = rb, nk = RB - k0;
+                    const uint4* ap =
+                        reinterpret_cast<const uint4*>(Av) + ((size_t)(s * RB + rb) * RB + k0) * 64 + lane;
+                    uint4 A0[PD], A1[PD];
+                    run_row(ap, A0, A1, k0, nk, c);
+                } else {
+                    const int k0 = 4 * rb, nk = KS - k0;
+                    const float* ap =
+                        reinterpret_cast<const float*>(Av) + ((size_t)(s * RB + rb) * KS + k0) * 64 + lane;
+                    float A0[PD], A1[PD];
+                    run_row(ap, A0, A1, k0, nk, c);
                 }
-        }
-        double* rd = red + (s & 1) * 4 * NP;
 #pragma unroll
-        for (int q = 0; q < CB; ++q) {
-            double a = acc[q];
-            a += __shfl_xor(a, 16);
-            a += __shfl_xor(a, 32);
-            if (lane < 16) rd[wave * NP + q * 16 + lane] = a;
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int q = 0; q < CB; ++q) {
+                        const float y = CB == 1 ? c[0][i] + c[1][i] : c[q][i];
+                        acc[si][q] += v[i][q] * (FV)y;
+                    }
+            }
         }
+#pragma unroll
+        for (int si = 0; si < SG; ++si)
+#pragma unroll
+            for (int q = 0; q < CB; ++q) {
+                FV a = acc[si][q];
+                a += __shfl_xor(a, 16);
+                a += __shfl_xor(a, 32);
+                if (lane < 16) rd[(si * 4 + wave) * NP + q * 16 + lane] = a;
+            }
         __syncthreads();
         if (wave == 0) {
             const long long g = p0 + lane;
             const bool valid = lane < NP && g < npts;
-            double d = 0.0;
-            if (lane < NP) d = rd[lane] + rd[NP + lane] + rd[2 * NP + lane] + rd[3 * NP + lane];
-            if (valid) {
-                const float v = (float)d;
-                float* zp = Z + ((size_t)(s >> 1) * npts + g) * 2;
-                zp[s & 1] = v;
-                if ((ns & 1) && s == ns - 1) zp[1] = 0.f;
-                if (phi_out) phi_out[(size_t)s * npts + g] = v;
-            }
-            double q = valid ? d * d : 0.0;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) q += __shfl_xor(q, o);
-            if (psum && lane == 0) psum[(size_t)s * gridDim.x + blockIdx.x] = q;
+            for (int si = 0; si < SG; ++si) {
+                const int s = s0 + si;
+                if (s >= ns) break;
+                const FV* r4 = rd + si * 4 * NP;
+                double d = 0.0;
+                if (lane < NP) d = (double)r4[lane] + (double)r4[NP + lane] + (double)r4[2 * NP + lane] + (double)r4[3 * NP + lane];
+                if (valid) {
+                    const float v = (float)d;
+                    float* zp = Z + ((size_t)(s >> 1) * npts + g) * 2;
+                    zp[s & 1] = v;
+                    if ((ns & 1) && s == ns - 1) zp[1] = 0.f;
+                    if (phi_out) phi_out[(size_t)s * npts + g] = v;
+                }
+                double q = valid ? d * d : 0.0;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) q += __shfl_xor(q, o);
+                if (psum && lane == 0) psum[(size_t)s * gridDim.x + blockIdx.x] = q;
+            }
         }
+        __syncthreads();
     }
 }
 
