@@ -266,6 +266,7 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
         accI[cb] = (sph_double4){0.0, 0.0, 0.0, 0.0};
     }
     const int lr = lane & 15, lk = lane >> 4;
+    const bool wave_rows = r0 + 16 * wave < nrows;   // wave-uniform
     // loads of a chunk: the row operand's run of 4 geometries, then Yt and
     // j_L at the column's four geometries; chunk g0 + kQK is loaded while the
     // matrix cores work on chunk g0.  The loads are unconditional, from
@@ -297,16 +298,19 @@ __global__ __launch_bounds__(256) void sph_q_kernel(const double* __restrict__ J
         }
         __syncthreads();
         if (g0 + kQK < n_geo) load_chunk(g0 + kQK);
+        // a wave whose 16 rows all lie past the last row skips the products
+        if (wave_rows) {
 #pragma unroll
-        for (int ks = 0; ks < kQK / 4; ++ks) {
-            const double ar = Br[16 * wave + lr][4 * ks + lk], ai = Bi[16 * wave + lr][4 * ks + lk];
+            for (int ks = 0; ks < kQK / 4; ++ks) {
+                const double ar = Br[16 * wave + lr][4 * ks + lk], ai = Bi[16 * wave + lr][4 * ks + lk];
 #pragma unroll
-            for (int cb = 0; cb < kQCB; ++cb) {
-                const double br = Ar[4 * ks + lk][16 * cb + lr], bi = Ai[4 * ks + lk][16 * cb + lr];
-                accR[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accR[cb], 0, 0, 0);
-                accR[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accR[cb], 0, 0, 0);
-                accI[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, accI[cb], 0, 0, 0);
-                accI[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, accI[cb], 0, 0, 0);
+                for (int cb = 0; cb < kQCB; ++cb) {
+                    const double br = Ar[4 * ks + lk][16 * cb + lr], bi = Ai[4 * ks + lk][16 * cb + lr];
+                    accR[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accR[cb], 0, 0, 0);
+                    accR[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accR[cb], 0, 0, 0);
+                    accI[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, accI[cb], 0, 0, 0);
+                    accI[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, accI[cb], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
