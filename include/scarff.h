@@ -334,7 +334,12 @@ int scff_last_fft_timing(scff_ctx* ctx, float* pack_ms, float* density_ms, float
  * Outputs are host (out_on_device = 0) or device buffers (1); the call
  * returns when they are written.  SCFF_EINVAL for bad sizes or no output,
  * SCFF_ESTATE before a molecule and transitions are loaded, SCFF_ENOMEM over
- * the budget.
+ * the budget.  Device memory held by the context: the per-geometry tables
+ * (harmonics to L = lmax + 4 and the W tensor, 16 bytes per geometry and
+ * entry), the Bessel table of every radius, and a workspace for the row
+ * operands of a batch of radii (n_states x 25 x geometries x 16 bytes per
+ * radius, at most 4 GiB or an eighth of a set HBM budget, at least one
+ * radius).
  */
 int scff_eval_spherical(scff_ctx* ctx, int lmax, int n_q, const double* q, int n_theta, int n_phi, double* R,
                         float* f, float* f2, double* avg, int out_on_device, void* hip_stream);
