@@ -31,6 +31,10 @@ constexpr int kMaxChunkTerms = kChunk * kMaxTermsPerPair;   // 72
 // (one workgroup per tile and range, FP64 partial sums reduced afterwards)
 // when the grid has too few tiles to fill the device.
 constexpr int kMaxSplit = 8;
+// The pair-sum buffer G of the separable-integral and dipole paths holds
+// nv x ncomp pair sums followed by ns x ncomp x kSepParts slices of their
+// transition-weighted reduction.
+constexpr int kSepParts = 64;
 struct ChunkSplit {
     int n;                   // number of ranges (1 = no split)
     int lo[kMaxSplit + 1];   // range j is chunks [lo[j], lo[j+1]); lo[0] = 0, lo[n] = n_chunks

@@ -27,25 +27,33 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// S[r] = sum_i w_a[i] V_r(q_a[i]) for the axis a of row r (w: x, y, z weights concatenated)
-__global__ void sep_rows_kernel(const VRowDev* __restrict__ rows, int nrows, const double2* __restrict__ w,
-                                int3 n, double3 qmin, double3 dq, double2* __restrict__ S) {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += gridDim.x * blockDim.x) {
-        const VRowDev row = rows[r];
-        const int a = row.axis;
-        const int na = a == 0 ? n.x : (a == 1 ? n.y : n.z);
-        const int off = a == 0 ? 0 : (a == 1 ? n.x : n.x + n.y);
-        const double q0 = a == 0 ? qmin.x : (a == 1 ? qmin.y : qmin.z);
-        const double d = a == 0 ? dq.x : (a == 1 ? dq.y : dq.z);
-        double sr = 0.0, si = 0.0;
-        for (int i = 0; i < na; ++i) {
-            const double2 v = eval_row_fp64(row, q0 + d * (double)i);
-            const double2 wi = w[off + i];
-            sr += wi.x * v.x - wi.y * v.y;
-            si += wi.x * v.y + wi.y * v.x;
-        }
-        S[r] = make_double2(sr, si);
+// S[r] = sum_i w_a[i] V_r(q_a[i]) for the axis a of row r (w: x, y, z
+// weights concatenated).  Eight lanes per row: lane l of a row's group takes
+// the values i = l, l + 8, ..., then a fixed butterfly sums the eight.
+__global__ __launch_bounds__(256) void sep_rows_kernel(const VRowDev* __restrict__ rows, int nrows,
+                                                       const double2* __restrict__ w, int3 n, double3 qmin,
+                                                       double3 dq, double2* __restrict__ S) {
+    const int l8 = threadIdx.x & 7;
+    const int r = blockIdx.x * 32 + (threadIdx.x >> 3);
+    const bool ok = r < nrows;
+    const VRowDev row = rows[ok ? r : 0];
+    const int a = row.axis;
+    const int na = ok ? (a == 0 ? n.x : (a == 1 ? n.y : n.z)) : 0;
+    const int off = a == 0 ? 0 : (a == 1 ? n.x : n.x + n.y);
+    const double q0 = a == 0 ? qmin.x : (a == 1 ? qmin.y : qmin.z);
+    const double d = a == 0 ? dq.x : (a == 1 ? dq.y : dq.z);
+    double sr = 0.0, si = 0.0;
+    for (int i = l8; i < na; i += 8) {
+        const double2 v = eval_row_fp64(row, q0 + d * (double)i);
+        const double2 wi = w[off + i];
+        sr += wi.x * v.x - wi.y * v.y;
+        si += wi.x * v.y + wi.y * v.x;
     }
+    for (int o = 1; o < 8; o <<= 1) {
+        sr += __shfl_xor(sr, o);
+        si += __shfl_xor(si, o);
+    }
+    if (ok && l8 == 0) S[r] = make_double2(sr, si);
 }
 
 // S[r] = (V(0), V'(0) / i) = (e_0, P e_0 + e_1), both real
@@ -96,15 +104,19 @@ __global__ void sep_pairs_kernel(const int4* __restrict__ slots, const int* __re
     }
 }
 
-// out[s * ncomp + c] = sum_o tp64[vcp[o] * ns + s] * G[o * ncomp + c]; one
-// block per (s, c), strided partial sums then a fixed tree in LDS
+// part[(s * ncomp + c) * nparts + b] = sum over the b-th of nparts slices of
+// o of tp64[vcp[o] * ns + s] * G[o * ncomp + c]; one block per (s, c, slice),
+// strided partial sums then a fixed tree in LDS.  sep_final_kernel adds the
+// slices in order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void sep_reduce_kernel(const double* __restrict__ tp64, const int* __restrict__ vcp,
                                                          int nv, int ns, const double2* __restrict__ G, int ncomp,
-                                                         double2* __restrict__ out) {
+                                                         int nparts, double2* __restrict__ part) {
     __shared__ double2 red[256];
-    const int s = blockIdx.x / ncomp, c = blockIdx.x - s * ncomp;
+    const int sc = blockIdx.x / nparts, b = blockIdx.x - sc * nparts;
+    const int s = sc / ncomp, c = sc - s * ncomp;
+    const int per = (nv + nparts - 1) / nparts, o0 = b * per, o1 = min(nv, o0 + per);
     double sr = 0.0, si = 0.0;
-    for (int o = threadIdx.x; o < nv; o += 256) {
+    for (int o = o0 + threadIdx.x; o < o1; o += 256) {
         const int k = vcp[o];
         if (k < 0) continue;
         const double t = tp64[(size_t)k * ns + s];
@@ -121,7 +133,18 @@ __global__ __launch_bounds__(256) void sep_reduce_kernel(const double* __restric
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sep_final_kernel(const double2* __restrict__ part, int n, int nparts, double2* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 a = make_double2(0.0, 0.0);
+    for (int b = 0; b < nparts; ++b) {
+        a.x += part[(size_t)i * nparts + b].x;
+        a.y += part[(size_t)i * nparts + b].y;
+    }
+    out[i] = a;
 }
 
 // |f_s(q)|^2 at points, all in FP64: f2[s * nq + i]
@@ -169,13 +192,29 @@ int blocks_for(long long n, int b) {
     return (int)g;
 }
 
+// slices of the transition-weighted reduction per (state, component): about
+// 2048 pairs each, at most kSepParts
+int sep_parts(int nv) { return std::max(1, std::min(kSepParts, nv / 2048)); }
+
+hipError_t launch_sep_reduce(const double* tp64, const int* vcp, int nv, int ns, const double2* G, int ncomp,
+                             double2* part, double2* out, hipStream_t st) {
+    const int np = sep_parts(nv);
+    hipLaunchKernelGGL(sep_reduce_kernel, dim3(ns * ncomp * np), dim3(256), 0, st, tp64, vcp, nv, ns, G, ncomp, np,
+                       part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sep_final_kernel, dim3((ns * ncomp + 63) / 64), dim3(64), 0, st, (const double2*)part,
+                       ns * ncomp, np, out);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_separable(const VRowDev* rows, int nrows, const int4* slots, const int* coff, const int* cnpp,
                             int n_units, const double* tp64, const int* vcp, int ns, const double2* w, const int n[3],
                             const double qmin[3], const double dq[3], double2* S, double2* G, double2* out,
                             hipStream_t st) {
-    hipLaunchKernelGGL(sep_rows_kernel, dim3(blocks_for(nrows, 128)), dim3(128), 0, st, rows, nrows, w,
+    hipLaunchKernelGGL(sep_rows_kernel, dim3((nrows + 31) / 32), dim3(256), 0, st, rows, nrows, w,
                        make_int3(n[0], n[1], n[2]), make_double3(qmin[0], qmin[1], qmin[2]),
                        make_double3(dq[0], dq[1], dq[2]), S);
     hipError_t e = hipGetLastError();
@@ -184,8 +223,7 @@ hipError_t launch_separable(const VRowDev* rows, int nrows, const int4* slots, c
     hipLaunchKernelGGL(sep_pairs_kernel, dim3(blocks_for(nv, 256)), dim3(256), 0, st, slots, coff, cnpp, n_units,
                        (const double2*)S, 0, G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(sep_reduce_kernel, dim3(ns), dim3(256), 0, st, tp64, vcp, nv, ns, (const double2*)G, 1, out);
-    return hipGetLastError();
+    return launch_sep_reduce(tp64, vcp, nv, ns, G, 1, G + nv, out, st);
 }
 
 hipError_t launch_dipole(const VRowDev* rows, int nrows, const int4* slots, const int* coff, const int* cnpp,
@@ -198,9 +236,7 @@ hipError_t launch_dipole(const VRowDev* rows, int nrows, const int4* slots, cons
     hipLaunchKernelGGL(sep_pairs_kernel, dim3(blocks_for(nv, 256)), dim3(256), 0, st, slots, coff, cnpp, n_units,
                        (const double2*)S, 1, G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(sep_reduce_kernel, dim3(ns * 4), dim3(256), 0, st, tp64, vcp, nv, ns, (const double2*)G, 4,
-                       out);
-    return hipGetLastError();
+    return launch_sep_reduce(tp64, vcp, nv, ns, G, 4, G + 4 * (size_t)nv, out, st);
 }
 
 hipError_t launch_points64(const VRowDev* rows, const int4* slots, const int* coff, const int* cnpp, int n_units,

@@ -1325,7 +1325,7 @@ int scff_eval_separable(scff_ctx* c, const scff_grid* g, const double* wx, const
     const size_t nv = (size_t)p.n_units * kChunk;
     if ((rc = dev_reserve(c, c->d_lq_in, nw * sizeof(double2))) ||
         (rc = dev_reserve(c, c->d_lq_S, (size_t)p.n_rows * sizeof(double2))) ||
-        (rc = dev_reserve(c, c->d_lq_G, nv * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_lq_G, (nv + (size_t)c->n_states * kSepParts) * sizeof(double2))) ||
         (rc = dev_reserve(c, c->d_lq_out, (size_t)c->n_states * sizeof(double2))))
         return rc;
     size_t off = 0;
@@ -1366,7 +1366,7 @@ int scff_dipole(scff_ctx* c, const double* dE, double* mu, double* f0) {
             if (!std::isfinite(dE[s])) return fail(SCFF_EINVAL, "non-finite transition energy");
     const size_t nv = (size_t)p.n_units * kChunk;
     if ((rc = dev_reserve(c, c->d_lq_S, (size_t)p.n_rows * sizeof(double2))) ||
-        (rc = dev_reserve(c, c->d_lq_G, 4 * nv * sizeof(double2))) ||
+        (rc = dev_reserve(c, c->d_lq_G, 4 * (nv + (size_t)ns * kSepParts) * sizeof(double2))) ||
         (rc = dev_reserve(c, c->d_lq_out, (size_t)ns * 4 * sizeof(double2))))
         return rc;
     if ((rc = hip_check(launch_dipole((const VRowDev*)c->prep.rows.p, p.n_rows, (const int4*)c->prep.slots.p,
