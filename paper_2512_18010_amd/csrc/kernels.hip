@@ -99,18 +99,24 @@ __global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int v
 //   raw slices  Vx[t][4], Vy[t][8], Vz[t][TZ]   global -> LDS by direct DMA
 //   W[t][line] = Vx * Vy                        cooperative, in LDS
 // plus the chunk's packed weights Tp[pairs][16*SB] (DMA as well).  The raw
-// buffers are double-buffered: the DMA for chunk c+1 is issued at the start
-// of chunk c and completes under chunk c's W phase and main loop; the row
-// ids it needs were loaded one chunk earlier.  Thread tid always moves slice
-// `part = tid & 15` of terms ptl = tid/16 + (NW*4)j, so the LDS destination
-// of a wave's DMA is contiguous (lane * 16 bytes), as the instruction
-// requires.  Lane (kk, ln): pair kk of the current MFMA k-step, 2 lines x QZL
-// qz.
+// slices and Tp are double-buffered: the DMA for chunk c+1 is issued at the
+// start of chunk c and completes under chunk c's W phase and main loop; the
+// row ids it needs were loaded one chunk earlier.  With one state block (SB =
+// 1) V^x and V^y, which only the W phase reads, have a single buffer of
+// their own, refilled for chunk c+1 right after chunk c's W phase: 50 KB of
+// LDS per workgroup instead of 60, which lets the split-BF16 variant (158
+// VGPRs) hold three workgroups per CU; the variants with two state blocks
+// keep all slices of a term in one double-buffered row (their registers
+// allow two workgroups per CU either way).  A term row holds RP float4
+// slices (8 in the split buffers, 16 otherwise) and thread tid always moves
+// slice `tid % RP` of terms tid/RP + (NT/RP)j, so the LDS destination of a
+// wave's DMA is contiguous (lane * 16 bytes), as the instruction requires.
+// Lane (kk, ln): pair kk of the current MFMA k-step, 2 lines x QZL qz.
 
 constexpr int kFoldUnits = 4;  // units (32 pairs) per FP64 fold of the FP32 MFMA sums
 constexpr int kWStride = 34;   // float2 per term row of W (32 lines + pad)
 constexpr int kNPT = kMaxChunkTerms;   // 72 terms per chunk at most
-constexpr int kParts = 16;     // float4 slices per term row of the raw buffer
+constexpr int kParts = 16;     // float4 slices per term row of a raw buffer holding all three axes
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -193,11 +199,17 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
     constexpr int ZPARTS = TZ / 2;     // float4 slices of a Z row
     constexpr int SLOTS = 2 * QZL;     // q values per lane
     constexpr int SW = 16 * SB;        // padded state count
-    constexpr int TPP = NT / 16;       // terms per DMA pass (16 slice-threads per term)
+    // V^x / V^y in a buffer of their own (one state block), or all slices of a
+    // term in one row of the double-buffered raw buffer
+    constexpr bool SXY = SB == 1;
+    constexpr int RP = SXY ? 8 : kParts;      // float4 slices per term row of a raw buffer
+    constexpr int ZOFF = SXY ? 0 : 6;         // first V^z slice of a row
+    constexpr int TPW8 = 64 / RP;             // terms per wave per DMA pass
+    constexpr int TPP = NT / RP;              // terms per DMA pass (RP slice-threads per term)
     constexpr int NJ = (kNPT + TPP - 1) / TPP;   // term groups per slice-thread
     static_assert(NW == 4 || NW == 8, "4 or 8 waves per workgroup");
     constexpr int TPW = kMaxUnitsPerChunk * kChunk * SW;   // Tp words per chunk at most
-    static_assert(2 + 4 + ZPARTS <= kParts, "slices per term");
+    static_assert(SXY ? (2 + 4 <= RP && ZPARTS <= RP) : (2 + 4 + ZPARTS <= RP), "slices per term");
     static_assert(QZL % 2 == 0, "q_z values per lane come in float4 pairs");
     static_assert(TPW / 4 <= 256, "Tp block per chunk fits one DMA per thread");
     // software prefetch of the next term's LDS slices (12 VGPRs): only where
@@ -205,8 +217,10 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
     // fold totals that the FP32 path needs at QZL = 4)
     constexpr bool PF = BF || QZL <= 2;
 
-    __shared__ __align__(16) float4 R0[kNPT * kParts];
-    __shared__ __align__(16) float4 R1[kNPT * kParts];
+    // raw slice buffers: V^z (split) or all slices (not split), double-buffered
+    __shared__ __align__(16) float4 Z0[kNPT * RP];
+    __shared__ __align__(16) float4 Z1[kNPT * RP];
+    __shared__ __align__(16) float4 XY[SXY ? kNPT * RP : 1];
     // Tp words: FP32 bits, or (BF) hi | lo << 16 split-BF16 halves
     __shared__ __align__(16) uint32_t T0[TPW];
     __shared__ __align__(16) uint32_t T1[TPW];
@@ -233,19 +247,19 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
     const int tx = b / ntiles.y;
     const int qx0 = tx * 4, qy0 = ty * 8, qz0 = tz * TZ;
 
-    // ---- this thread's slice: axis and offset of its 16 bytes in a table row
-    const int part = tid & 15;
-    int axis, qoff;
-    if (part < 2) {
-        axis = 0; qoff = qx0 + 2 * part;
-    } else if (part < 6) {
-        axis = 1; qoff = qy0 + 2 * (part - 2);
-    } else {
-        axis = 2; qoff = qz0 + 2 * min(part - 6, ZPARTS - 1);   // idle slices re-read a valid Z slice
-    }
+    // ---- this thread's slices: axis and offset of its 16 bytes in a table
+    // row.  Split: for the V^x / V^y buffer (spare slices re-read a valid V^y
+    // slice) and for the V^z buffer; not split: one slice of a whole row.
+    // Idle slices re-read a valid V^z slice.
+    const int part = tid & (RP - 1);
+    const int axis_xy = part < 2 ? 0 : 1;
+    const int qoff_xy = part < 2 ? qx0 + 2 * part : qy0 + 2 * min(part - 2, 3);
+    const int axis_z = SXY ? 2 : (part < 2 ? 0 : (part < 6 ? 1 : 2));
+    const int qoff_z = SXY ? qz0 + 2 * min(part, ZPARTS - 1)
+                           : (part < 6 ? qoff_xy : qz0 + 2 * min(part - 6, ZPARTS - 1));
 
     // row ids of the slices of chunk c (loaded one chunk ahead of the DMA)
-    int rid[NJ];
+    int rid_xy[NJ], rid_z[NJ];
     auto load_rows = [&](int c) {
         const int4 ch = sload_int4(chunks + c);   // (first unit, units, npp, first slot)
         const int nptl = ch.y * kChunk * ch.z;
@@ -253,23 +267,36 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
         // lane indices recomputed here rather than kept live across the loop
         int t0 = threadIdx.x;
         asm volatile("" : "+v"(t0));
-        const int p0 = t0 >> 4;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) rid[j] = tc[4 * min(p0 + TPP * j, nptl - 1) + axis];
-    };
-    // DMA of chunk c's raw slices into buffer rbase and its Tp block into tbase
-    auto issue_dma = [&](int c, uint32_t rbase, uint32_t tbase) {
+        const int p0 = SXY ? t0 >> 3 : t0 >> 4;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            // wave w of term group j covers terms TPP*j + 4w .. TPP*j + 4w + 3
-            // row ids are clamped to the table where they are used (after the
-            // barrier that waits for their loads), so no DMA can leave the
-            // table whatever the slot table holds
-            if (TPP * j + 4 * wave < kNPT) {
+            const int* tr = tc + 4 * min(p0 + TPP * j, nptl - 1);
+            if constexpr (SXY) rid_xy[j] = tr[axis_xy];
+            rid_z[j] = tr[axis_z];
+        }
+    };
+    // DMA of this thread's slices of a chunk into the raw buffer at rbase;
+    // wave w of term group j covers terms TPP*j + TPW8*w .. + TPW8-1.  Row ids
+    // are clamped to the table where they are used (after the barrier that
+    // waits for their loads), so no DMA can leave the table whatever the slot
+    // table holds
+    auto dma_slices = [&](const int (&rid)[NJ], int qoff, uint32_t rbase) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            if (TPP * j + TPW8 * wave < kNPT) {
                 const uint32_t r = min((uint32_t)rid[j], (uint32_t)(vrows - 1));
-                dma_b128(8u * (__umul24(r, vstride) + qoff), V, rbase + (TPP * j + 4 * wave) * kParts * 16);
+                dma_b128(8u * (__umul24(r, vstride) + qoff), V, rbase + (TPP * j + TPW8 * wave) * RP * 16);
             }
         }
+    };
+    // DMA of chunk c's V^x / V^y slices into XY (split buffers only)
+    auto issue_dma_xy = [&]() {
+        if constexpr (SXY) dma_slices(rid_xy, qoff_xy, lds_addr(XY));
+    };
+    // DMA of chunk c's V^z slices (or all its slices) into buffer zbase and
+    // its Tp block into tbase
+    auto issue_dma = [&](int c, uint32_t zbase, uint32_t tbase) {
+        dma_slices(rid_z, qoff_z, zbase);
         const int4 ch = sload_int4(chunks + c);
         const int tpf4 = ch.y * (kChunk * SW / 4);   // float4 of Tp in this chunk
         if (64 * wave < tpf4 && lane < tpf4 - 64 * wave)
@@ -305,7 +332,7 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
 
     int units_done = 0;   // units contracted so far (fold cadence of the FP32 path)
 
-    auto chunk_body = [&](int c, const float4* R, const uint32_t* T) {
+    auto chunk_body = [&](int c, const float4* Z, const uint32_t* T, auto after_w) {
         const int4 ch = sload_int4(chunks + c);
         const int nu = ch.y;
         const int npp = ch.z;
@@ -318,13 +345,15 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
         asm volatile("" : "+v"(i0));
         for (int i = i0; i < nu * kChunk * npp * 16; i += NT) {
             const int ptl = i >> 4, xq = (i >> 2) & 3, h = i & 3;
-            const float2 vx = reinterpret_cast<const float2*>(R + ptl * kParts)[xq];
-            const float4 y = R[ptl * kParts + 2 + h];
+            const float4* xy = SXY ? XY : Z;   // this chunk's V^x / V^y
+            const float2 vx = reinterpret_cast<const float2*>(xy + ptl * RP)[xq];
+            const float4 y = xy[ptl * RP + 2 + h];
             reinterpret_cast<float4*>(Wl + ptl * kWStride + xq * 8)[h] =
                 make_float4(vx.x * y.x - vx.y * y.y, vx.x * y.y + vx.y * y.x, vx.x * y.z - vx.y * y.w,
                             vx.x * y.w + vx.y * y.z);
         }
         barrier_lds();
+        after_w();   // XY is free: the next chunk's V^x / V^y DMA
         // G of one component pair (index p in the chunk) for this lane's 2
         // lines x QZL q_z values, G = sum_t W_t(line) Vz_t(qz).  The first term
         // initialises G; in the prefetching variant the slices of term t+1 are
@@ -335,12 +364,12 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
             // load still in flight (which would make it wait for that load)
             const int pt = __umul24(p, npp);
             const float2* wp = Wl + (__umul24(pt, kWStride) + wxq * 8 + 2 * lpair);
-            const float2* zp = reinterpret_cast<const float2*>(R) +
-                               (__umul24(pt, 2 * kParts) + 12 + wzh * (4 * QZL) + zgrp * QZL);
+            const float2* zp = reinterpret_cast<const float2*>(Z) +
+                               (__umul24(pt, 2 * RP) + 2 * ZOFF + wzh * (4 * QZL) + zgrp * QZL);
             auto load = [&](int t, float4& w, float4 (&zz)[QZL / 2]) {
                 w = *reinterpret_cast<const float4*>(wp + t * kWStride);
 #pragma unroll
-                for (int j = 0; j < QZL / 2; ++j) zz[j] = *reinterpret_cast<const float4*>(zp + t * (2 * kParts) + 2 * j);
+                for (int j = 0; j < QZL / 2; ++j) zz[j] = *reinterpret_cast<const float4*>(zp + t * (2 * RP) + 2 * j);
             };
             auto zval = [&](const float4 (&zz)[QZL / 2], int j) {
                 return (j & 1) ? make_float2(zz[j >> 1].z, zz[j >> 1].w) : make_float2(zz[j >> 1].x, zz[j >> 1].y);
@@ -446,24 +475,38 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
 
     if (c_hi > c_lo) {
         load_rows(c_lo);
-        issue_dma(c_lo, lds_addr(R0), lds_addr(T0));
+        issue_dma_xy();
+        issue_dma(c_lo, lds_addr(Z0), lds_addr(T0));
         if (c_lo + 1 < c_hi) load_rows(c_lo + 1);
     }
-    // two chunks per iteration so each buffer is a distinct LDS object
+    // two chunks per iteration so each buffer is a distinct LDS object.  The
+    // row ids held at the start of chunk c are chunk c+1's: its V^z / Tp DMA
+    // goes out at once, its V^x / V^y DMA once chunk c's W phase has read XY,
+    // and then the row ids of chunk c+2 are loaded
     for (int c = c_lo; c < c_hi; c += 2) {
-        barrier_dma();                                  // chunk c landed in R0/T0; Wl and R1 are free
+        barrier_dma();                                  // chunk c landed in Z0/T0 (and XY); Z1, T1 and Wl are free
         if (c + 1 < c_hi) {
-            issue_dma(c + 1, lds_addr(R1), lds_addr(T1));
-            if (c + 2 < c_hi) load_rows(c + 2);
+            issue_dma(c + 1, lds_addr(Z1), lds_addr(T1));
+            if (!SXY && c + 2 < c_hi) load_rows(c + 2);
         }
-        chunk_body(c, R0, T0);
+        chunk_body(c, Z0, T0, [&]() {
+            if (SXY && c + 1 < c_hi) {
+                issue_dma_xy();
+                if (c + 2 < c_hi) load_rows(c + 2);
+            }
+        });
         if (c + 1 >= c_hi) break;
-        barrier_dma();                                  // chunk c+1 landed in R1/T1; Wl and R0 are free
+        barrier_dma();                                  // chunk c+1 landed in Z1/T1 (and XY); Z0, T0 and Wl are free
         if (c + 2 < c_hi) {
-            issue_dma(c + 2, lds_addr(R0), lds_addr(T0));
-            if (c + 3 < c_hi) load_rows(c + 3);
+            issue_dma(c + 2, lds_addr(Z0), lds_addr(T0));
+            if (!SXY && c + 3 < c_hi) load_rows(c + 3);
         }
-        chunk_body(c + 1, R1, T1);
+        chunk_body(c + 1, Z1, T1, [&]() {
+            if (SXY && c + 2 < c_hi) {
+                issue_dma_xy();
+                if (c + 3 < c_hi) load_rows(c + 3);
+            }
+        });
     }
     if constexpr (!BF) {
         if (units_done & (kFoldUnits - 1)) fold();
@@ -475,17 +518,22 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
     // own LDS region as 16 rows (kk, lpair) of 4*QZL q_z, then the wave reads
     // the rows back with consecutive lanes on consecutive q_z and stores them,
     // so every row of the output (fixed state, q_x, q_y) is written as one
-    // contiguous run.  The staging reuses the raw slice buffers (no wave reads
-    // them after the barrier below).
+    // contiguous run.  The staging reuses the W buffer and a V^z buffer (no
+    // wave reads them after the barrier below, and no DMA is in flight).
     constexpr int RQ = 4 * QZL;          // q_z values of a row
     constexpr int RPI = 64 / RQ;         // rows per wave-wide read
     barrier_lds();
     const int qx = qx0 + wxq;
     const bool plane_ok = qx < nx_eval;
-    // per wave: 16 rows x RQ values; f (float2) or partial (double2) in R0, f2 (float) in R1
-    double2* sp2 = reinterpret_cast<double2*>(R0) + wave * 16 * RQ;
-    float2* sf = reinterpret_cast<float2*>(R0) + wave * 16 * RQ;
-    float* sf2 = reinterpret_cast<float*>(R1) + wave * 16 * RQ;
+    // per wave: 16 rows x RQ values; f (float2) or partial (double2) in Wl
+    // (split) or Z0, f2 (float) in Z0 (split) or Z1
+    static_assert(SXY ? (NW * 16 * RQ * sizeof(double2) <= sizeof(Wl) && NW * 16 * RQ * sizeof(float) <= sizeof(Z0))
+                      : (NW * 16 * RQ * sizeof(double2) <= sizeof(Z0) && NW * 16 * RQ * sizeof(float) <= sizeof(Z1)),
+                  "epilogue staging fits");
+    void* s_f = SXY ? (void*)Wl : (void*)Z0;
+    double2* sp2 = reinterpret_cast<double2*>(s_f) + wave * 16 * RQ;
+    float2* sf = reinterpret_cast<float2*>(s_f) + wave * 16 * RQ;
+    float* sf2 = reinterpret_cast<float*>(SXY ? Z0 : Z1) + wave * 16 * RQ;
     const int wrow = kk * 4 + lpair;     // the row this lane's values belong to
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb)
@@ -696,10 +744,15 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
 //   states (2 q_z per lane, 8 waves per tile), whose accumulators and FP64
 //   fold totals would not fit 2 waves per SIMD otherwise.
 // Every variant's tile covers 16 q_z values: 4 per lane on one wave per q_x
-// line, or 2 per lane on two waves per line.  Workgroups resident per CU: two
-// of 4 waves, or one of 8 (2 waves per SIMD either way).
+// line, or 2 per lane on two waves per line.  Workgroups resident per CU:
+// three of 4 waves for split-BF16 with <= 16 states (158 VGPRs, 50 KB of
+// LDS), one of 8 for FP32 with 17..32 states, two of 4 otherwise (their
+// registers allow 2 waves per SIMD).
 static int tile_qz(int, int) { return 16; }
-int grid_wg_per_cu(int state_blocks, int precision) { return state_blocks == 2 && precision == 0 ? 1 : 2; }
+int grid_wg_per_cu(int state_blocks, int precision) {
+    if (state_blocks == 2 && precision == 0) return 1;
+    return state_blocks == 1 && precision == 1 ? 3 : 2;
+}
 int grid_class(int state_blocks, int precision) { return (state_blocks - 1) + 2 * precision; }
 static int class_waves(int cls) { return cls == 1 ? 8 : 4; }
 
@@ -753,7 +806,7 @@ hipError_t launch_grid_desc(int cls, const GridDesc& d, long long blocks, hipStr
     switch (cls) {
         case 0: hipLaunchKernelGGL((grid_kernel<1, 4, 2, false, 4>), grid, dim3(256), 0, st, d); break;
         case 1: hipLaunchKernelGGL((grid_kernel<2, 2, 2, false, 8>), grid, dim3(512), 0, st, d); break;
-        case 2: hipLaunchKernelGGL((grid_kernel<1, 4, 2, true, 4>), grid, dim3(256), 0, st, d); break;
+        case 2: hipLaunchKernelGGL((grid_kernel<1, 4, 3, true, 4>), grid, dim3(256), 0, st, d); break;
         case 3: hipLaunchKernelGGL((grid_kernel<2, 4, 2, true, 4>), grid, dim3(256), 0, st, d); break;
         default: return hipErrorInvalidValue;
     }
@@ -770,7 +823,7 @@ hipError_t launch_grid_batch(int cls, const GridDesc* descs, const int2* items, 
     switch (cls) {
         case 0: hipLaunchKernelGGL((grid_batch_kernel<1, 4, 2, false, 4>), grid, block, 0, st, descs, items, n_items, counter); break;
         case 1: hipLaunchKernelGGL((grid_batch_kernel<2, 2, 2, false, 8>), grid, block, 0, st, descs, items, n_items, counter); break;
-        case 2: hipLaunchKernelGGL((grid_batch_kernel<1, 4, 2, true, 4>), grid, block, 0, st, descs, items, n_items, counter); break;
+        case 2: hipLaunchKernelGGL((grid_batch_kernel<1, 4, 3, true, 4>), grid, block, 0, st, descs, items, n_items, counter); break;
         case 3: hipLaunchKernelGGL((grid_batch_kernel<2, 4, 2, true, 4>), grid, block, 0, st, descs, items, n_items, counter); break;
         default: return hipErrorInvalidValue;
     }
