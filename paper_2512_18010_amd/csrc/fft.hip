@@ -38,13 +38,22 @@ typedef unsigned int fft_uintx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 fft_bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 fft_bf16x8 __attribute__((ext_vector_type(8)));
 
-// Split-BF16 of one value in one dword: hi = RNE(v) in the low half,
-// lo = RNE(v - hi) in the high half (v - hi is exact in FP32).
+// Split-BF16 of one value: hi = RNE(v), lo = RNE(v - hi), each in the low
+// half of a dword whose high half is zero.  v - hi is exact in FP32, so the
+// BF16 dot product hi . (-1, -0) + v gives it in one instruction (-0, not +0:
+// the compiler would encode (-1, +0) as the inline constant -1.0, which the
+// instruction reads as the BF16 pair (+0, -1)).
+__device__ inline void fft_split(float v, uint32_t& hi, uint32_t& lo) {
+    const fft_bf16x2 h = __builtin_convertvector(fft_floatx2{v, 0.f}, fft_bf16x2);
+    const float r = __builtin_amdgcn_fdot2_f32_bf16(h, fft_bf16x2{(__bf16)-1.0f, (__bf16)-0.0f}, v, false);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(fft_floatx2{r, 0.f}, fft_bf16x2));
+}
+// The same in one dword: hi in the low half, lo in the high half.
 __device__ inline uint32_t fft_split(float v) {
-    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(fft_floatx2{v, 0.f}, fft_bf16x2)) & 0xffffu;
-    const float r = v - __builtin_bit_cast(float, h << 16);
-    const uint32_t l = __builtin_bit_cast(uint32_t, __builtin_convertvector(fft_floatx2{r, 0.f}, fft_bf16x2)) & 0xffffu;
-    return h | (l << 16);
+    uint32_t hi, lo;
+    fft_split(v, hi, lo);
+    return hi | (lo << 16);
 }
 
 // Primitives whose exponent argument alpha r^2 exceeds this are skipped (the
@@ -245,12 +254,13 @@ __global__ __launch_bounds__(256) void fft_density_kernel(FftMol m, const void* 
         const int col = p & 15, cb = p >> 4;
         auto put = [&](int r, auto v) {
             if constexpr (BF) {
-                const uint32_t w = fft_split((float)v);
+                uint32_t hi, lo;
+                fft_split((float)v, hi, lo);
                 const int i = r & 3;
                 // dword of the hi half; the lo half is two dwords on
                 const int wd = ((((r >> 4) * 4 + ((r >> 2) & 3)) * CB + cb) * 16 + col) * 4 + (i >> 1);
-                ps16[2 * wd + (i & 1)] = (unsigned short)(w & 0xffffu);
-                ps16[2 * wd + 4 + (i & 1)] = (unsigned short)(w >> 16);
+                ps16[2 * wd + (i & 1)] = (unsigned short)hi;
+                ps16[2 * wd + 4 + (i & 1)] = (unsigned short)lo;
             } else {
                 ph[r * NP + col * CB + cb] = (float)v;
             }

@@ -47,10 +47,20 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2{a, b}, bf16x2));
 }
-// Split-BF16 of two values: hi = RNE(g), lo = RNE(g - hi); g - hi is exact in FP32.
+// Split-BF16 of two values: hi = RNE(g), lo = RNE(g - hi).  g - hi is exact
+// in FP32 (hi is a multiple of g's FP32 ulp and |g - hi| needs at most 16
+// significant bits), so any correctly rounded evaluation of it gives the same
+// value; a BF16 dot product hi . (-1, -0) + g forms it in one instruction,
+// without unpacking hi.  The weights carry -0 rather than +0 in the other
+// half: the compiler encodes (-1, +0) as the inline constant -1.0, which the
+// instruction reads as the FP32 pattern of -1.0, i.e. the BF16 pair (+0, -1);
+// (-1, -0) and (-0, -1) have no inline form and go as literals.
 __device__ __forceinline__ void split_bf16(float g0, float g1, uint32_t& hi, uint32_t& lo) {
-    hi = pack_bf16(g0, g1);
-    lo = pack_bf16(g0 - __uint_as_float(hi << 16), g1 - __uint_as_float(hi & 0xffff0000u));
+    const bf16x2 h = __builtin_convertvector(floatx2{g0, g1}, bf16x2);
+    const float l0 = __builtin_amdgcn_fdot2_f32_bf16(h, bf16x2{(__bf16)-1.0f, (__bf16)-0.0f}, g0, false);
+    const float l1 = __builtin_amdgcn_fdot2_f32_bf16(h, bf16x2{(__bf16)-0.0f, (__bf16)-1.0f}, g1, false);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = pack_bf16(l0, l1);
 }
 // Eight BF16 k-items of a 16x16x32 operand, two per dword (low half first).
 __device__ __forceinline__ bf16x8 bf16x8_of(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {
