@@ -114,7 +114,7 @@ __global__ void vtable_kernel(const VRowDev* __restrict__ rows, int nrows, int v
 // row ids it needs were loaded one chunk earlier.  With one state block (SB =
 // 1) V^x and V^y, which only the W phase reads, have a single buffer of
 // their own, refilled for chunk c+1 right after chunk c's W phase: 50 KB of
-// LDS per workgroup instead of 60, which lets the split-BF16 variant (158
+// LDS per workgroup instead of 60, which lets the split-BF16 variants (156-160
 // VGPRs) hold three workgroups per CU; the variants with two state blocks
 // keep all slices of a term in one double-buffered row (their registers
 // allow two workgroups per CU either way).  A term row holds RP float4
@@ -755,7 +755,7 @@ hipError_t launch_vtable(const VRowDev* rows, int nrows, int vstride, const int 
 //   fold totals would not fit 2 waves per SIMD otherwise.
 // Every variant's tile covers 16 q_z values: 4 per lane on one wave per q_x
 // line, or 2 per lane on two waves per line.  Workgroups resident per CU:
-// three of 4 waves for split-BF16 with <= 16 states (158 VGPRs, 50 KB of
+// three of 4 waves for split-BF16 with <= 16 states (156-160 VGPRs, 50 KB of
 // LDS), one of 8 for FP32 with 17..32 states, two of 4 otherwise (their
 // registers allow 2 waves per SIMD).
 static int tile_qz(int, int) { return 16; }
