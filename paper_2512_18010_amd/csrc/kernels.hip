@@ -437,6 +437,10 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
                 for (int sb = 0; sb < SB; ++sb) a_op[step][sb] = T[p * SW + sb * 16 + ln];
                 gen(p, gr[step], gi[step]);
                 if constexpr (!BF) {
+                    // raised wave priority while the matrix instructions
+                    // issue (four-wave variants; the eight-wave one measured
+                    // slower with it)
+                    if constexpr (NW == 4) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                     for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
@@ -445,6 +449,7 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
                             acc_r[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gr[step][s], acc_r[sb][s], 0, 0, 0);
                             acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gi[step][s], acc_i[sb][s], 0, 0, 0);
                         }
+                    if constexpr (NW == 4) __builtin_amdgcn_s_setprio(0);
                 }
             }
             ++units_done;
@@ -458,6 +463,10 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
                 // unit per MFMA, so no state is carried between units (pairing
                 // units for a 16-pair group made the compiler copy the
                 // accumulators on every unit).
+                // The split and the matrix instructions run at raised wave
+                // priority, so that a wave holding a unit's products is issued
+                // ahead of a wave in its generator loop on the same SIMD.
+                __builtin_amdgcn_s_setprio(1);
                 uint32_t hr[SLOTS], lr[SLOTS], hi[SLOTS], li[SLOTS];
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
@@ -477,6 +486,7 @@ __device__ __forceinline__ void grid_tile(const GridDesc& d, int blk) {
                         acc_i[sb][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bi, acc_i[sb][s], 0, 0, 0);
                     }
                 }
+                __builtin_amdgcn_s_setprio(0);
             } else {
                 if ((units_done & (kFoldUnits - 1)) == 0) fold();
             }
